@@ -1,0 +1,411 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics,
+not by the oracle itself: brute force on tiny inputs, an independent sort
+(numpy), the Figure 3 partition semantics, Lemma 4 / Theorem 1 (Section 3.1),
+Theorem 2 and the budget (Section 4.1), the linear-time claims (Section 5.2),
+the closed forms of Section 4.1, and a hand-listed float order."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import gen.workloads as W
+
+pytestmark = []
+
+
+def textbook_insertion_sort(xs):
+    """Plain insertion sort, written here independently of the oracle."""
+    a = list(xs)
+    for i in range(1, len(a)):
+        x = a[i]
+        j = i - 1
+        while j >= 0 and a[j] > x:
+            a[j + 1] = a[j]
+            j -= 1
+        a[j + 1] = x
+    return a
+
+
+def as_bytes(a):
+    return np.ascontiguousarray(a).view(np.uint8)
+
+
+# ---------------------------------------------------------------- P1 brute force
+
+@pytest.mark.parametrize("n", range(0, 9))
+def test_exhaustive_small_alphabet(oracle_lib, n):
+    """Every array over {0..3} of length n <= 8 (each as its own segment)."""
+    if n == 0:
+        k, _, _ = oracle_lib.segmented_sort(np.zeros(0, np.uint32), np.zeros(2, np.uint64))
+        assert k.size == 0
+        return
+    arrs = np.array(list(itertools.product(range(4), repeat=n)), dtype=np.uint32)
+    off = np.arange(arrs.shape[0] + 1, dtype=np.uint64) * n
+    k, _, _ = oracle_lib.segmented_sort(arrs.ravel(), off)
+    assert np.array_equal(k.reshape(arrs.shape), np.sort(arrs, axis=1))
+
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_all_permutations(oracle_lib, n):
+    perms = np.array(list(itertools.permutations(range(n))), dtype=np.int32)
+    off = np.arange(perms.shape[0] + 1, dtype=np.uint64) * n
+    k, _, _ = oracle_lib.segmented_sort(perms.ravel(), off)
+    assert np.array_equal(k.reshape(perms.shape), np.tile(np.arange(n, dtype=np.int32), (perms.shape[0], 1)))
+
+
+def test_random_vs_textbook_insertion_sort(oracle_lib):
+    rng = np.random.default_rng(7)
+    for trial in range(300):
+        n = int(rng.integers(0, 257))
+        alpha = int(rng.choice([2, 4, 16, 1 << 30]))
+        a = rng.integers(0, alpha, n).astype(np.int32)
+        fb = int(rng.choice([-1, -1, 0, 1, 2]))
+        block = bool(rng.integers(0, 2))
+        k, _, _, _ = oracle_lib.sort(a, block=block, force_budget=fb)
+        assert k.tolist() == textbook_insertion_sort(a.tolist()), (trial, n, alpha, fb, block)
+
+
+@pytest.mark.parametrize("alpha", [2, 3, 4])
+def test_small_alphabet_partition_sizes(oracle_lib, alpha):
+    """Sizes 24..400 over a tiny alphabet drive partition_left repeatedly."""
+    rng = np.random.default_rng(alpha)
+    sizes = rng.integers(24, 401, 400)
+    off = np.zeros(sizes.size + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    a = rng.integers(0, alpha, int(off[-1])).astype(np.uint32)
+    for block in (True, False):
+        k, _, c = oracle_lib.segmented_sort(a, off, block=block, count=True)
+        for s in range(sizes.size):
+            lo, hi = int(off[s]), int(off[s + 1])
+            assert np.array_equal(k[lo:hi], np.sort(a[lo:hi]))
+        assert c["partitions_left"] > 0
+
+
+def test_forced_heapsort(oracle_lib):
+    rng = np.random.default_rng(3)
+    for n in (24, 25, 100, 1000, 5000):
+        a = rng.integers(0, 1 << 20, n).astype(np.uint32)
+        k, _, c, _ = oracle_lib.sort(a, force_budget=0, count=True)
+        assert np.array_equal(k, np.sort(a))
+        assert c["heapsort_calls"] == 1 and c["heapsort_elements"] == n
+        assert c["partitions_right"] == 0
+
+
+def test_routines_against_independent_sort(oracle_lib):
+    rng = np.random.default_rng(11)
+    for n in (0, 1, 2, 3, 17, 64, 333):
+        a = rng.integers(-50, 50, n).astype(np.int32)
+        h, _, _ = oracle_lib.routine("heapsort", a)
+        assert np.array_equal(h, np.sort(a))
+        s, _, _ = oracle_lib.routine("insertion", a)
+        assert np.array_equal(s, np.sort(a))
+
+
+@pytest.mark.parametrize("moves", range(0, 13))
+def test_partial_insertion_abort_limit(oracle_lib, moves):
+    """[1, 2, ..., m, 0] needs exactly m element moves to sort; the partial
+    insertion sort gives up once more than 8 moves were needed (reading of
+    'a tiny number of corrections'), and always leaves a permutation."""
+    a = np.array(list(range(1, moves + 1)) + [0] + list(range(moves + 1, moves + 20)), dtype=np.uint32)
+    out, ok, _ = oracle_lib.routine("partial_insertion", a)
+    assert ok == (moves <= 8)
+    assert np.array_equal(np.sort(out), np.sort(a))
+    if ok:
+        assert np.array_equal(out, np.sort(a))
+
+
+# ---------------------------------------------------------------- P2 independent sort
+
+@pytest.mark.parametrize("pattern", W.C2_PATTERNS)
+def test_patterns_vs_numpy(oracle_lib, pattern):
+    a = W.pattern_i32(pattern, 1 << 18, seed=1, period=1 << 10, tail=1 << 8)
+    for block in (True, False):
+        k, _, _, _ = oracle_lib.sort(a, block=block)
+        assert np.array_equal(k, np.sort(a))
+
+
+@pytest.mark.parametrize("pattern", W.PAPER_PATTERNS)
+def test_paper_patterns_vs_numpy(oracle_lib, pattern):
+    a = W.paper_pattern_u64(pattern, 100_003, seed=2)
+    k, _, _, _ = oracle_lib.sort(a)
+    assert np.array_equal(k, np.sort(a))
+
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "u64"])
+def test_key_types_vs_numpy(oracle_lib, kt):
+    a = W.random_keys(kt, 300_001, seed=5)
+    k, _, _, _ = oracle_lib.sort(a)
+    assert np.array_equal(as_bytes(k), as_bytes(np.sort(a)))
+
+
+def test_f32_vs_numpy_and_signed_zero_order(oracle_lib):
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal(200_000).astype(np.float32)
+    a[rng.choice(a.size, 3000, replace=False)] = 0.0
+    z = rng.choice(a.size, 3000, replace=False)
+    a[z] = -0.0
+    a[rng.choice(a.size, 5, replace=False)] = np.inf
+    a[rng.choice(a.size, 5, replace=False)] = -np.inf
+    k, _, _, _ = oracle_lib.sort(a)
+    ref = np.sort(a)
+    assert np.array_equal(k, ref)  # numeric order (numpy treats -0.0 == +0.0)
+    zeros = k[k == 0]
+    sign = np.signbit(zeros)
+    # all -0.0 first, then all +0.0
+    assert not np.any(sign[1:] & ~sign[:-1])
+    assert sign.sum() == np.signbit(a[a == 0]).sum()
+
+
+def test_k_distinct_u64_and_mix(oracle_lib):
+    for k_ in (1, 2, 16, 1024):
+        a = W.k_distinct_u64(50_000, k_, seed=k_)
+        k, _, _, _ = oracle_lib.sort(a)
+        assert np.array_equal(k, np.sort(a))
+    a = W.one_value_mix_u64(50_000, seed=4)
+    k, _, _, _ = oracle_lib.sort(a)
+    assert np.array_equal(k, np.sort(a))
+
+
+# ---------------------------------------------------------------- P3 pairs / segmented
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+def test_pairs_permutation_invariants(oracle_lib, kt):
+    a = W.random_keys(kt, 100_000, seed=13)
+    if kt != "f32":
+        a = a % a.dtype.type(977) if kt != "i32" else (a % 977).astype(np.int32)
+    v = np.arange(a.size, dtype=np.uint32)
+    k, vo, _, _ = oracle_lib.sort(a, v)
+    assert np.array_equal(as_bytes(k), as_bytes(a[vo]))  # each key travels with its payload
+    assert np.array_equal(np.bincount(vo, minlength=a.size), np.ones(a.size, np.int64))
+    if kt == "f32":
+        assert np.array_equal(k, np.sort(a))
+    else:
+        assert np.array_equal(k, np.sort(a))
+
+
+def test_segmented_pairs(oracle_lib):
+    keys, off, vals = W.segmented_f32(300, max_log2=12, seed=3)
+    k, v, _ = oracle_lib.segmented_sort(keys, off, vals)
+    assert np.array_equal(as_bytes(k), as_bytes(keys[v]))
+    for s in range(off.size - 1):
+        lo, hi = int(off[s]), int(off[s + 1])
+        assert np.array_equal(k[lo:hi], np.sort(keys[lo:hi]))
+        assert set(v[lo:hi].tolist()) == set(range(lo, hi))
+
+
+# ---------------------------------------------------------------- P8 Fig. 3 semantics
+
+@pytest.mark.parametrize("block", [True, False])
+def test_partition_right_semantics(oracle_lib, block):
+    rng = np.random.default_rng(21)
+    for trial in range(400):
+        n = int(rng.integers(3, 3000))
+        a = rng.integers(0, int(rng.choice([3, 50, 1 << 31])), n).astype(np.uint32)
+        out, (r, no_swaps), _ = oracle_lib.routine("partition_right", a, block=block)
+        p = out[r]
+        assert np.array_equal(np.sort(out), np.sort(a))
+        assert np.all(out[:r] < p) and np.all(out[r + 1:] >= p)
+        assert r == int(np.count_nonzero(a < p))
+
+
+def test_partition_left_semantics(oracle_lib):
+    rng = np.random.default_rng(22)
+    for trial in range(400):
+        n = int(rng.integers(3, 3000))
+        a = rng.integers(0, int(rng.choice([2, 5, 1 << 31])), n).astype(np.uint32)
+        out, (r, _), _ = oracle_lib.routine("partition_left", a)
+        p = out[r]
+        assert np.array_equal(np.sort(out), np.sort(a))
+        assert np.all(out[:r] <= p) and np.all(out[r + 1:] > p)
+        assert r == int(np.count_nonzero(a <= p)) - 1
+
+
+def ninther_by_definition(a):
+    """Tukey's ninther over the candidate layout: triples (first, mid, last),
+    (first+1, mid-1, last-1), (first+2, mid+1, last-2), median of medians."""
+    n = a.size
+    m = n // 2
+    med = lambda x, y, z: sorted([x, y, z])[1]
+    t1 = med(a[0], a[m], a[n - 1])
+    t2 = med(a[1], a[m - 1], a[n - 2])
+    t3 = med(a[2], a[m + 1], a[n - 3])
+    return med(t1, t2, t3)
+
+
+def test_first_pivot_is_ninther(oracle_lib):
+    rng = np.random.default_rng(23)
+    for trial in range(200):
+        n = int(rng.integers(129, 5000))
+        a = rng.integers(0, 1 << 31, n).astype(np.uint32)
+        out, (r, _), _ = oracle_lib.routine("partition_right", a)
+        assert out[r] == ninther_by_definition(a)
+        _, _, c, _ = oracle_lib.sort(a, count=True)
+        assert c["first_pivot_image"] == ninther_by_definition(a)
+        assert c["first_left_size"] == int(np.count_nonzero(a < ninther_by_definition(a)))
+
+
+def test_ascending_is_swapless(oracle_lib):
+    for n in (200, 1000, 4097):
+        a = np.arange(n, dtype=np.uint32)
+        out, (r, no_swaps), _ = oracle_lib.routine("partition_right", a)
+        assert no_swaps and np.array_equal(out, a)
+    for n in (30, 100, 128):  # median-of-3 range
+        a = np.arange(n, dtype=np.uint32)
+        out, (r, no_swaps), _ = oracle_lib.routine("partition_right", a)
+        assert no_swaps and np.array_equal(out, a)
+
+
+# ---------------------------------------------------------------- P4 / P5 Section 3.1
+
+@pytest.mark.parametrize("k", [1, 2, 3, 16, 1024, None])
+def test_lemma4_each_value_pivot_at_most_twice(oracle_lib, k):
+    n = 1 << 16
+    if k is None:
+        a = np.random.default_rng(1).integers(0, 1 << 40, n, dtype=np.uint64)
+    else:
+        a = W.k_distinct_u64(n, k, seed=k)
+    _, _, c, (keys, modes) = oracle_lib.sort(a, count=True, pivot_log=1 << 20)
+    assert c["pivot_log_len"] == keys.size
+    first_use = {}
+    uses = {}
+    for kv, m in zip(keys.tolist(), modes.tolist()):
+        uses[kv] = uses.get(kv, 0) + 1
+        if uses[kv] == 1:
+            assert m == 0, "first use of a value must be partition_right (Corollary 1)"
+        else:
+            assert m == 1, "second use of a value must be partition_left (Lemma 4)"
+        assert uses[kv] <= 2
+    if k is not None and k <= 16:
+        assert c["comparisons"] <= 4 * n * (2 * k + 1) + 24 * n
+
+
+@pytest.mark.parametrize("k", [2, 16, 64])
+def test_theorem1_comparisons_linear_in_n(oracle_lib, k):
+    per_n = []
+    for lg in (14, 16, 18):
+        n = 1 << lg
+        a = W.k_distinct_u64(n, k, seed=lg)
+        _, _, c, _ = oracle_lib.sort(a, count=True)
+        per_n.append(c["comparisons"] / n)
+        assert c["comparisons"] <= 4 * n * (2 * k + 1) + 24 * n
+    lo, hi = min(per_n), max(per_n)
+    assert hi <= 1.25 * lo, per_n
+
+
+# ---------------------------------------------------------------- P6 Section 4.1
+
+@pytest.mark.parametrize("pattern", W.C2_PATTERNS)
+def test_theorem2_nlogn_and_budget(oracle_lib, pattern):
+    n = 1 << 17
+    a = W.pattern_i32(pattern, n, seed=3, period=1 << 10, tail=1 << 8)
+    _, _, c, _ = oracle_lib.sort(a, count=True)
+    assert c["comparisons"] <= 3 * n * math.log2(n)
+    assert c["max_bad_on_path"] <= int(math.log2(n))
+
+
+def test_merge_pattern_budget(oracle_lib):
+    n = 1 << 17
+    a = W.paper_pattern_u64("merge", n)
+    _, _, c, _ = oracle_lib.sort(a, count=True)
+    assert c["comparisons"] <= 3 * n * math.log2(n)
+
+
+def test_bad_partition_threshold_is_one_eighth(oracle_lib):
+    """n = 1024: a side with fewer than 1024 >> 3 = 128 elements is bad. The
+    ninther candidates are planted so the pivot has rank r."""
+    n = 1024
+    m = n // 2
+
+    def planted(r):
+        rest = [v for v in range(n) if v not in (r - 1, r, r + 1, r + 2, r + 3, r + 4, r - 4, r - 3, r - 2)]
+        rng = np.random.default_rng(r)
+        rest = list(rng.permutation(rest))
+        a = [None] * n
+        # triple 1 -> median r, triple 2 -> median r+3, triple 3 -> median r-3
+        for pos, v in ((0, r - 1), (m, r), (n - 1, r + 1),
+                       (1, r + 2), (m - 1, r + 3), (n - 2, r + 4),
+                       (2, r - 4), (m + 1, r - 3), (n - 3, r - 2)):
+            a[pos] = v
+        for i in range(n):
+            if a[i] is None:
+                a[i] = rest.pop()
+        return np.array(a, dtype=np.uint32)
+
+    for r, bad in ((127, True), (128, False), (896, True), (895, False)):
+        a = planted(r)
+        assert ninther_by_definition(a) == r
+        _, _, c, _ = oracle_lib.sort(a, count=True)
+        assert c["first_left_size"] == r
+        assert bool(c["first_bad"]) == bad, r
+
+
+# ---------------------------------------------------------------- P7 Section 5.2
+
+@pytest.mark.parametrize("lg", [10, 14, 18, 20])
+def test_linear_time_patterns(oracle_lib, lg):
+    n = 1 << lg
+    asc = np.arange(n, dtype=np.uint64)
+    _, _, c, _ = oracle_lib.sort(asc, count=True)
+    assert c["first_no_swaps"] == 1
+    assert c["comparisons"] <= 2.2 * n
+    _, _, c, _ = oracle_lib.sort(asc[::-1].copy(), count=True)
+    assert c["comparisons"] <= 3.2 * n
+    plus1 = np.concatenate([asc, np.array([n // 3], np.uint64)])
+    _, _, c, _ = oracle_lib.sort(plus1, count=True)
+    assert c["comparisons"] <= 8 * n
+
+
+# ---------------------------------------------------------------- P9 closed forms (Section 4.1)
+
+def _inv_entropy(p):
+    return 1.0 / (-p * math.log2(p) - (1 - p) * math.log2(1 - p))
+
+
+def test_slowdown_closed_forms():
+    # "split 80/20 ... only 40% slower"
+    assert abs(_inv_entropy(0.2) - 1.385) < 1e-3
+    assert round(_inv_entropy(0.2) - 1, 1) == 0.4
+    # p = 0.125 is "reasonably close to twice as slow"
+    assert abs(_inv_entropy(0.125) - 1.840) < 1e-3
+    # the p with 1/H(p) = 2 is about 0.110; 1/8 is the nearest power of two above it
+    lo, hi = 1e-6, 0.5
+    for _ in range(100):
+        mid = (lo + hi) / 2
+        if _inv_entropy(mid) > 2:
+            lo = mid
+        else:
+            hi = mid
+    assert abs(lo - 0.110) < 1e-3
+    assert 2 ** math.floor(math.log2(lo)) * 2 == 0.125 or 0.125 > lo
+
+
+# ---------------------------------------------------------------- P10 key order
+
+F32_ORDER = [0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x807FFFFF, 0x80000001, 0x80000000,
+             0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x3F800000, 0x7F7FFFFF, 0x7F800000]
+
+
+def test_float_bit_order(oracle_lib):
+    bits = np.array(F32_ORDER, dtype=np.uint32)
+    imgs = [oracle_lib.key_image("f32", b) for b in bits.view(np.float32)]
+    assert all(x < y for x, y in zip(imgs, imgs[1:]))
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        a = np.repeat(bits, 5)[rng.permutation(bits.size * 5)].view(np.float32)
+        k, _, _, _ = oracle_lib.sort(a)
+        assert np.array_equal(k.view(np.uint32), np.repeat(bits, 5))
+    big = np.tile(bits, 40)[rng.permutation(bits.size * 40)].view(np.float32)
+    k, _, _, _ = oracle_lib.sort(big)
+    assert np.array_equal(k.view(np.uint32), np.repeat(bits, 40))
+
+
+def test_integer_edge_order(oracle_lib):
+    i32 = np.array([-(2**31), -(2**31) + 1, -1, 0, 1, 2**31 - 1], dtype=np.int32)
+    u32 = np.array([0, 1, 2**31 - 1, 2**31, 2**32 - 1], dtype=np.uint32)
+    u64 = np.array([0, 1, 2**63 - 1, 2**63, 2**64 - 1], dtype=np.uint64)
+    rng = np.random.default_rng(1)
+    for arr in (i32, u32, u64):
+        a = np.tile(arr, 30)[rng.permutation(arr.size * 30)]
+        k, _, _, _ = oracle_lib.sort(a)
+        assert np.array_equal(k, np.repeat(arr, 30))
