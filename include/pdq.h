@@ -1,0 +1,150 @@
+/*
+ * pdq.h -- C ABI of the MI355X (gfx950) partition sort.
+ *
+ * The operation is the one of "Pattern-defeating Quicksort" (Peters,
+ * arXiv 2106.05123): an unstable, in-place, ascending sort of a contiguous
+ * range (Sections 1 and 3: a [begin, end) range, a comparison order, no
+ * stability). Its data-parallel hot path -- the partition step -- runs as
+ * out-of-place passes over all live segments at once:
+ *   - pivot: Tukey's ninther, with fresh candidates after a bad
+ *     partition (Sections 2 and 4.2);
+ *   - partition_right, or partition_left when the pivot equals the
+ *     predecessor, so k distinct keys need O(k) passes (Section 3,
+ *     Lemmas 1-4, Theorem 1);
+ *   - branchless block classification (Section 5.3) as wave ballots and
+ *     LDS prefix sums with a decoupled look-back scatter;
+ *   - bad-partition budget with heapsort fallback (Section 4.1);
+ *   - detection of already ordered segments (Section 5.2);
+ *   - an LDS-resident base case for segments of at most 4096 keys
+ *     (Section 5.1's small-case sort, as a sorting network).
+ *
+ * Key order ("canonical order"): uint32 / uint64 as unsigned integers,
+ * int32 as two's complement, float32 by the total order on its bit
+ * patterns: -inf < ... < -0.0 < +0.0 < ... < +inf. NaN inputs are outside
+ * the contract (they are placed by bit pattern, nothing more is promised).
+ * Sorted keys are unique bit for bit. Payloads (uint32) travel with their
+ * keys; the sort is unstable, so the order of payloads of equal keys is not
+ * specified (any permutation consistent with the keys is valid).
+ *
+ * Memory and ownership: every pointer argument named d_* is a device
+ * pointer owned by the caller. The library never allocates device memory:
+ * all scratch lives in the caller's workspace d_ws (size from
+ * pdq_workspace_bytes; 256-byte alignment recommended). d_ws must stay
+ * allocated until the work queued on `stream` has finished. No pointer is
+ * kept after a call returns. `stream` is a hipStream_t (NULL = the default
+ * stream). Calls run asynchronously on `stream` unless `stats` is non-NULL
+ * or PDQ_VALIDATE is set; the current implementation synchronises `stream`
+ * once per partition pass to read the number of live segments.
+ *
+ * Errors: every entry point returns PDQ_OK (0) or a negative status; no
+ * exception crosses the ABI. n <= 1 is a no-op returning PDQ_OK.
+ * Concurrent calls on different streams need different workspaces.
+ */
+#ifndef PDQ_H
+#define PDQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDQ_ABI_VERSION 1
+
+/* Largest segment that goes straight to the LDS base case. */
+#define PDQ_BASE_CASE_MAX 4096
+
+typedef enum pdq_key_type {
+  PDQ_U32 = 1,
+  PDQ_I32 = 2,
+  PDQ_F32 = 3,
+  PDQ_U64 = 4
+} pdq_key_type;
+
+/* The comparison order is supplied by the caller but fixed to ascending
+ * canonical order; any other value returns PDQ_ERR_UNSUPPORTED. */
+typedef enum pdq_order { PDQ_ASCENDING = 0 } pdq_order;
+
+enum pdq_status {
+  PDQ_OK = 0,
+  PDQ_ERR_INVALID = -1,     /* null pointer with n > 0, misaligned pointer, bad offsets (validate mode) */
+  PDQ_ERR_UNSUPPORTED = -2, /* key type, order, n >= 2^32, unknown flag */
+  PDQ_ERR_WORKSPACE = -3,   /* d_ws NULL or ws_bytes below pdq_workspace_bytes() */
+  PDQ_ERR_HIP = -4          /* a HIP launch or synchronisation failed (see pdq_last_hip_error) */
+};
+
+enum pdq_flags {
+  PDQ_VALIDATE = 1u << 0, /* check offsets on the device before sorting (synchronises) */
+  PDQ_PROFILE = 1u << 1   /* time every partition launch with HIP events (needs stats) */
+};
+
+typedef struct pdq_options {
+  uint32_t struct_size;  /* sizeof(pdq_options); 0 or a smaller value = older layout */
+  uint32_t flags;        /* pdq_flags */
+  int32_t force_budget;  /* < 0: floor(log2 size) per segment (Section 4.1); >= 0: that budget */
+  uint32_t tile;         /* keys per partition tile: 0 = auto, else 1024, 2048, 4096 or 8192 */
+  uint64_t seed;         /* reserved for the learned-splitter path */
+} pdq_options;
+
+/* Filled on request (forces a synchronisation at the end of the call). */
+typedef struct pdq_stats {
+  uint32_t struct_size;           /* set by the caller: sizeof(pdq_stats) */
+  uint32_t passes;                /* partition passes run */
+  uint64_t element_visits;        /* sum over passes of keys partitioned */
+  uint64_t partitions_right;
+  uint64_t partitions_left;
+  uint64_t bad_partitions;
+  uint64_t heapsort_segments;
+  uint64_t heapsort_elements;
+  uint64_t base_segments;         /* segments sorted by the LDS base case */
+  uint64_t base_elements;
+  uint64_t sorted_segments;       /* segments found already ascending or descending */
+  uint64_t sorted_elements;
+  uint64_t equal_elements;        /* keys retired by partition_left (equal to their pivot) */
+  uint64_t first_pivot_image;     /* first partition of a single-range sort: canonical pivot */
+  int64_t first_left_size;        /*   ... its left-side size (pivot excluded) */
+  int32_t first_mode;             /*   ... 0 partition_right, 1 partition_left, -1 none */
+  uint32_t partition_launches;    /* PDQ_PROFILE: partition kernel launches timed */
+  double partition_ms;            /* PDQ_PROFILE: summed duration of those launches */
+  uint64_t partition_bytes;       /* PDQ_PROFILE: algorithmic bytes moved by them (read + write) */
+  double first_pass_ms;           /* PDQ_PROFILE: duration of the first partition launch */
+  uint64_t first_pass_bytes;      /* PDQ_PROFILE: its algorithmic bytes */
+} pdq_stats;
+
+/* Bytes of device workspace needed for a call with these sizes. nseg is
+ * the number of segments (1 for pdq_sort / pdq_sort_pairs). */
+size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has_vals,
+                           const pdq_options* opt);
+
+/* Sort d_keys[0..n) ascending in place. */
+int pdq_sort(void* d_keys, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws,
+             size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* stats);
+
+/* Sort d_keys[0..n) ascending in place, moving d_vals[i] with d_keys[i]. */
+int pdq_sort_pairs(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type,
+                   pdq_order order, void* d_ws, size_t ws_bytes, void* stream,
+                   const pdq_options* opt, pdq_stats* stats);
+
+/* Sort each segment [d_offsets[s], d_offsets[s+1]) independently, for
+ * s < nseg. d_offsets is a device array of nseg+1 non-decreasing uint64
+ * with d_offsets[0] = 0 and d_offsets[nseg] = n (checked only with
+ * PDQ_VALIDATE). Empty segments are allowed. d_vals may be NULL. */
+int pdq_segmented_sort(void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets,
+                       size_t nseg, pdq_key_type key_type, pdq_order order, void* d_ws,
+                       size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* stats);
+
+/* Human-readable text of a status code (static storage). */
+const char* pdq_status_string(int status);
+
+/* The hipError_t value behind the last PDQ_ERR_HIP of this thread (0 if none). */
+int pdq_last_hip_error(void);
+
+/* PDQ_ABI_VERSION of the library. */
+int pdq_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDQ_H */

@@ -1,0 +1,423 @@
+// Per-pass control kernels of the partition sort: initial segment lists,
+// pivot choice, tile map, segment bookkeeping, and the finishing copies and
+// heapsort fallback.
+#include "pdq_internal.h"
+#include "wave_ops.h"
+
+namespace pdq {
+namespace {
+
+constexpr int kCtlThreads = 256;
+
+__device__ __forceinline__ uint32_t floor_log2_u64(uint64_t x) { return 63u - __clzll(x); }
+
+template <class K>
+__device__ __forceinline__ typename K::T load_key(const Ctx& c, uint32_t buf, uint64_t i) {
+  return static_cast<const typename K::T*>(c.keys[buf])[i];
+}
+
+// Append a range to an item list of capacity cap (every lane calls; `want`
+// selects). A full list skips the write and flags the call.
+__device__ __forceinline__ void push_item(const Ctx& c, Item* list, uint32_t* ctr, bool want, uint64_t b,
+                                          uint64_t e, uint32_t buf, uint32_t reverse) {
+  const uint32_t slot = wave_reserve(ctr, want);
+  if (want) {
+    if (slot < c.max_items) list[slot] = Item{b, e, buf, reverse};
+    else atomicOr(&c.ctr->errors, kErrCapacity);
+  }
+}
+
+// Append a live segment to list `parity` and reserve its tile tickets.
+__device__ __forceinline__ void push_seg(const Ctx& c, int parity, bool want, uint64_t b, uint64_t e,
+                                         uint32_t budget, uint32_t flags) {
+  const uint32_t nt = want ? tiles_of(b, e, c.tile) : 0u;
+  const uint64_t r = wave_reserve_packed(reinterpret_cast<unsigned long long*>(&c.ctr->list[parity]), want, nt);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->elems[parity]), want ? (e - b) : 0ull);
+  if (want && ((r >> 32) >= c.max_active || static_cast<uint64_t>(static_cast<uint32_t>(r)) + nt > c.max_tiles)) {
+    atomicOr(&c.ctr->errors, kErrCapacity);
+  } else if (want) {
+    Seg s;
+    s.begin = b;
+    s.end = e;
+    s.pivot = 0;
+    s.pidx = b;
+    s.left = 0;
+    s.tile_base = static_cast<uint32_t>(r);
+    s.ntiles = nt;
+    s.budget = budget;
+    s.flags = flags;
+    s.mode = kModeRight;
+    s.order_bits = 0;
+    c.segs[parity][r >> 32] = s;
+  }
+}
+
+__global__ void k_reset(Ctx c) {
+  if (threadIdx.x == 0) {
+    Counters z = {};
+    z.first_mode = -1;
+    *c.ctr = z;
+  }
+}
+
+// Initial lists: every input segment is leftmost, with budget floor(log2 size)
+// (Section 4.1) unless forced. Offsets are clamped into [0, n] so that bad
+// offsets can never address outside the arrays; they are flagged instead.
+__global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool live = i < c.nseg;
+  uint64_t b = 0, e = 0;
+  if (live) {
+    if (c.offsets) {
+      b = c.offsets[i];
+      e = c.offsets[i + 1];
+      bool bad = e < b || e > c.n || b > c.n || (i == 0 && b != 0) || (i + 1 == c.nseg && e != c.n);
+      if (bad) atomicOr(&c.ctr->bad_offsets, 1u);
+      if (b > c.n) b = c.n;
+      if (e > c.n) e = c.n;
+      if (e < b) e = b;
+    } else {
+      b = 0;
+      e = c.n;
+    }
+  }
+  const uint64_t size = e - b;
+  uint32_t budget = 0;
+  if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
+  const bool big = size > kBaseMax;
+  push_seg(c, 0, big && budget > 0, b, e, budget, kSegLeftmost);
+  const bool to_base = size >= 2 && !big;
+  const bool to_heap = big && budget == 0;
+  push_item(c, c.base, &c.ctr->nbase, to_base, b, e, 0u, 0u);
+  push_item(c, c.heap, &c.ctr->nheap, to_heap, b, e, 0u, 0u);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? size : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), to_heap ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), to_heap ? size : 0);
+}
+
+// Pivot choice for every live segment: Tukey's ninther over the triples
+// (first, mid, last), (first+1, mid-1, last-1), (first+2, mid+1, last-2);
+// after a bad partition the first/last candidates come from around the 25%
+// and 75% points instead (Sections 2 and 4.2). Then the predecessor rule of
+// Section 3 selects partition_left when the predecessor is not below the
+// pivot.
+template <class K>
+__global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32_t nseg, uint32_t src) {
+  using T = typename K::T;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.ctr->list[parity ^ 1] = 0;
+    c.ctr->elems[parity ^ 1] = 0;
+    c.ctr->nbase = 0;
+    c.ctr->nheap = 0;
+    c.ctr->ncopy = 0;
+  }
+  if (i >= nseg) return;
+  Seg* sp = &c.segs[parity][i];
+  const uint64_t b = sp->begin, e = sp->end;
+  const uint64_t size = e - b;
+  const bool fresh = (sp->flags & kSegFresh) != 0;
+  const uint64_t q = fresh ? size / 4 : 0;
+  const uint64_t m = size / 2;
+  const uint64_t off[9] = {q, m, size - 1 - q, q + 1, m - 1, size - 2 - q, q + 2, m + 1, size - 3 - q};
+  const T* keys = static_cast<const T*>(c.keys[src]);
+  T raw[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) raw[k] = keys[b + off[k]];
+  uint64_t best_ord = 0, best_pos = 0;
+  T best_raw = 0;
+  {
+    // medians of the three triples, then the median of those
+    uint64_t mo[3], mp[3];
+    T mr[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      uint64_t o0 = K::ord(raw[3 * t]), o1 = K::ord(raw[3 * t + 1]), o2 = K::ord(raw[3 * t + 2]);
+      int sel;
+      if (o0 < o1) sel = (o1 < o2) ? 1 : ((o0 < o2) ? 2 : 0);
+      else sel = (o0 < o2) ? 0 : ((o1 < o2) ? 2 : 1);
+      mo[t] = sel == 0 ? o0 : (sel == 1 ? o1 : o2);
+      mp[t] = off[3 * t + sel];
+      mr[t] = raw[3 * t + sel];
+    }
+    int sel;
+    if (mo[0] < mo[1]) sel = (mo[1] < mo[2]) ? 1 : ((mo[0] < mo[2]) ? 2 : 0);
+    else sel = (mo[0] < mo[2]) ? 0 : ((mo[1] < mo[2]) ? 2 : 1);
+    best_ord = mo[sel];
+    best_pos = mp[sel];
+    best_raw = mr[sel];
+  }
+  uint32_t mode = kModeRight;
+  if (!(sp->flags & kSegLeftmost)) {
+    // the predecessor is an ancestor's pivot and already sits at its final
+    // place in the user buffer (Lemma 1)
+    const T pred = static_cast<const T*>(c.keys[0])[b - 1];
+    if (!(static_cast<uint64_t>(K::ord(pred)) < best_ord)) mode = kModeLeft;
+  }
+  sp->pivot = static_cast<uint64_t>(best_raw);
+  sp->pidx = b + best_pos;
+  sp->mode = mode;
+}
+
+// Ticket -> segment map for the partition kernel, and a cleared status word
+// per ticket.
+__global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint32_t ntiles) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) c.ctr->ticket = 0;
+  if (t >= ntiles) return;
+  const uint32_t nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  const Seg* segs = c.segs[parity];
+  uint32_t lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].tile_base <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  c.tilemap[t] = lo;
+  c.status[t] = 0;
+}
+
+// After a partition pass: place each pivot at its final position in the user
+// buffer, retire segments that were already ordered (Section 5.2) and the
+// equal-to-pivot side of partition_left (Section 3), count bad partitions and
+// charge the budget (Section 4.1), and file every child as live segment, base
+// case or heapsort.
+template <class K>
+__global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uint32_t nseg, uint32_t src,
+                                                         uint32_t pass) {
+  using T = typename K::T;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < nseg;
+  const uint32_t dst = src ^ 1u;
+  Seg s = {};
+  if (live) s = c.segs[parity][i];
+  const uint64_t size = s.end - s.begin;
+  const bool no_desc = live && !(s.order_bits & static_cast<uint32_t>(kStDesc >> 32));
+  const bool no_asc = live && !(s.order_bits & static_cast<uint32_t>(kStAsc >> 32));
+  const bool asc_sorted = no_desc;           // non-decreasing in the source buffer
+  const bool desc_sorted = !no_desc && no_asc; // non-increasing in the source buffer
+  bool split = live && !asc_sorted && !desc_sorted;
+  if (split && s.left >= size) {
+    atomicOr(&c.ctr->errors, kErrSplit);
+    split = false;
+  }
+  const bool is_left = s.mode == kModeLeft;
+  const uint64_t L = s.left;
+  const uint64_t R = size - 1 - L;
+  const bool bad = split && !is_left && (L < (size >> 3) || R < (size >> 3));
+
+  if (live && c.single && pass == 0 && i == 0) {
+    c.ctr->first_pivot_image = static_cast<uint64_t>(K::ord(static_cast<T>(s.pivot)));
+    c.ctr->first_left = static_cast<int64_t>(L);
+    c.ctr->first_mode = static_cast<int32_t>(s.mode);
+  }
+  if (split) {
+    const uint64_t p = s.begin + L;
+    static_cast<T*>(c.keys[0])[p] = static_cast<T>(s.pivot);
+    if (c.has_vals) c.vals[0][p] = c.vals[src][s.pidx];
+  }
+  // already ordered: copy (reversed when descending) into the user buffer
+  const bool ordered = asc_sorted || desc_sorted;
+  push_item(c, c.copy, &c.ctr->ncopy, ordered && !(src == 0 && asc_sorted), s.begin, s.end, src,
+            desc_sorted ? 1u : 0u);
+  // partition_left: the left side equals the pivot and is final
+  push_item(c, c.copy, &c.ctr->ncopy, split && is_left && L > 0 && dst != 0, s.begin, s.begin + L, dst, 0u);
+
+  const uint32_t cbudget = s.budget - (bad ? 1u : 0u);
+  const uint32_t cflag_fresh = bad ? kSegFresh : 0u;
+  // two children: left (only for partition_right) and right
+  for (int side = 0; side < 2; ++side) {
+    const bool has = split && (side == 1 || !is_left);
+    const uint64_t cb = side == 0 ? s.begin : s.begin + L + 1;
+    const uint64_t ce = side == 0 ? s.begin + L : s.end;
+    const uint64_t cs = has ? ce - cb : 0;
+    const uint32_t cflags = cflag_fresh | (side == 0 ? (s.flags & kSegLeftmost) : 0u);
+    const bool to_base = has && cs >= 1 && cs <= kBaseMax && !(cs == 1 && dst == 0);
+    const bool to_heap = has && cs > kBaseMax && cbudget == 0;
+    const bool to_live = has && cs > kBaseMax && cbudget > 0;
+    push_item(c, c.base, &c.ctr->nbase, to_base, cb, ce, dst, 0u);
+    push_item(c, c.heap, &c.ctr->nheap, to_heap, cb, ce, dst, 0u);
+    push_seg(c, parity ^ 1, to_live, cb, ce, cbudget, cflags);
+    wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
+    wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? cs : 0);
+    wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), to_heap ? 1 : 0);
+    wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), to_heap ? cs : 0);
+  }
+
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->partitions_right), split && !is_left ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->partitions_left), split && is_left ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->bad_partitions), bad ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->sorted_segments), ordered ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->sorted_elements), ordered ? size : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->equal_elements), split && is_left ? L : 0);
+}
+
+// Copies into the user buffer: plain, reversed, or reversed in place.
+template <class K>
+__global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c) {
+  using T = typename K::T;
+  const Item it = c.copy[blockIdx.x];
+  const uint64_t len = it.end - it.begin;
+  T* out = static_cast<T*>(c.keys[0]);
+  const T* in = static_cast<const T*>(c.keys[it.buf]);
+  uint32_t* outv = c.vals[0];
+  const uint32_t* inv = c.vals[it.buf];
+  const uint64_t stride = static_cast<uint64_t>(gridDim.y) * blockDim.x;
+  const uint64_t start = static_cast<uint64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
+  if (it.reverse && it.buf == 0) {
+    for (uint64_t j = start; j < len / 2; j += stride) {
+      const uint64_t a = it.begin + j, z = it.end - 1 - j;
+      T ka = out[a], kz = out[z];
+      out[a] = kz;
+      out[z] = ka;
+      if (c.has_vals) {
+        uint32_t va = outv[a], vz = outv[z];
+        outv[a] = vz;
+        outv[z] = va;
+      }
+    }
+  } else if (it.reverse) {
+    for (uint64_t j = start; j < len; j += stride) {
+      out[it.begin + j] = in[it.end - 1 - j];
+      if (c.has_vals) outv[it.begin + j] = inv[it.end - 1 - j];
+    }
+  } else {
+    for (uint64_t j = start; j < len; j += stride) {
+      out[it.begin + j] = in[it.begin + j];
+      if (c.has_vals) outv[it.begin + j] = inv[it.begin + j];
+    }
+  }
+}
+
+// Heapsort fallback (Section 4.1: a segment that used up its bad-partition
+// budget). Williams' heapsort, one workgroup per segment: the workgroup
+// moves the segment into the user buffer, then one lane sorts it there.
+template <class K>
+__device__ void sift_down(typename K::T* a, uint32_t* v, uint64_t root, uint64_t n) {
+  for (;;) {
+    uint64_t child = 2 * root + 1;
+    if (child >= n) return;
+    if (child + 1 < n && K::ord(a[child]) < K::ord(a[child + 1])) ++child;
+    if (!(K::ord(a[root]) < K::ord(a[child]))) return;
+    typename K::T t = a[root];
+    a[root] = a[child];
+    a[child] = t;
+    if (v) {
+      uint32_t tv = v[root];
+      v[root] = v[child];
+      v[child] = tv;
+    }
+    root = child;
+  }
+}
+
+template <class K>
+__global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c) {
+  using T = typename K::T;
+  const Item it = c.heap[blockIdx.x];
+  const uint64_t len = it.end - it.begin;
+  T* a = static_cast<T*>(c.keys[0]) + it.begin;
+  uint32_t* v = c.has_vals ? c.vals[0] + it.begin : nullptr;
+  if (it.buf != 0) {
+    const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
+    const uint32_t* inv = c.has_vals ? c.vals[it.buf] + it.begin : nullptr;
+    for (uint64_t j = threadIdx.x; j < len; j += blockDim.x) {
+      a[j] = in[j];
+      if (v) v[j] = inv[j];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (threadIdx.x != 0 || len < 2) return;
+  for (uint64_t r = len / 2; r-- > 0;) sift_down<K>(a, v, r, len);
+  for (uint64_t end = len - 1; end > 0; --end) {
+    T t = a[0];
+    a[0] = a[end];
+    a[end] = t;
+    if (v) {
+      uint32_t tv = v[0];
+      v[0] = v[end];
+      v[end] = tv;
+    }
+    sift_down<K>(a, v, 0, end);
+  }
+}
+
+template <template <class> class F, class... Args>
+hipError_t dispatch_key(uint32_t kt, Args&&... args) {
+  switch (kt) {
+    case 1: return F<KeyU32>::run(args...);
+    case 2: return F<KeyI32>::run(args...);
+    case 3: return F<KeyF32>::run(args...);
+    case 4: return F<KeyU64>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline uint32_t blocks_for(uint64_t n, uint32_t per) { return static_cast<uint32_t>((n + per - 1) / per); }
+
+template <class K>
+struct PivotL {
+  static hipError_t run(const Ctx& c, int parity, uint32_t nseg, uint32_t src, hipStream_t s) {
+    hipLaunchKernelGGL(k_pivot<K>, dim3(blocks_for(nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, nseg, src);
+    return hipGetLastError();
+  }
+};
+template <class K>
+struct BookL {
+  static hipError_t run(const Ctx& c, int parity, uint32_t nseg, uint32_t src, uint32_t pass, hipStream_t s) {
+    hipLaunchKernelGGL(k_bookkeep<K>, dim3(blocks_for(nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, nseg,
+                       src, pass);
+    return hipGetLastError();
+  }
+};
+template <class K>
+struct CopyL {
+  static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy<K>, dim3(nitems, 64), dim3(kCtlThreads), 0, s, c);
+    return hipGetLastError();
+  }
+};
+template <class K>
+struct HeapL {
+  static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
+    hipLaunchKernelGGL(k_heap<K>, dim3(nitems), dim3(kCtlThreads), 0, s, c);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t launch_reset(const Ctx& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const Ctx& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(c.nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_pivot(const Ctx& c, int parity, uint32_t nseg, uint32_t src, hipStream_t s) {
+  return dispatch_key<PivotL>(c.key_type, c, parity, nseg, src, s);
+}
+
+hipError_t launch_tilemap(const Ctx& c, int parity, uint32_t ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_tilemap, dim3(blocks_for(ntiles, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_bookkeep(const Ctx& c, int parity, uint32_t nseg, uint32_t src, uint32_t pass, hipStream_t s) {
+  return dispatch_key<BookL>(c.key_type, c, parity, nseg, src, pass, s);
+}
+
+hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s) {
+  return dispatch_key<CopyL>(c.key_type, c, nitems, s);
+}
+
+hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s) {
+  return dispatch_key<HeapL>(c.key_type, c, nitems, s);
+}
+
+}  // namespace pdq

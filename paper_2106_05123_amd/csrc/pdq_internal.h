@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP kernels and the host driver of the
+// partition sort. Nothing here is part of the public C ABI (include/pdq.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdq {
+
+constexpr uint32_t kBaseMax = 4096;     // segments of at most this many keys go to the LDS base case
+constexpr uint32_t kWave = 64;          // CDNA wavefront width
+constexpr uint32_t kSegLeftmost = 1u;   // segment has no predecessor (Section 3)
+constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh candidates (Section 4.2)
+constexpr uint32_t kModeRight = 0u;
+constexpr uint32_t kModeLeft = 1u;
+
+// Tile status word of the decoupled look-back (64 bits):
+//   [63:62] state (0 empty, 1 aggregate, 2 inclusive prefix)
+//   [61]    some adjacent pair descends   (OR over the covered tiles)
+//   [60]    some adjacent pair ascends
+//   [59:0]  count of keys going left
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStIncl = 2ull << 62;
+constexpr uint64_t kStStateMask = 3ull << 62;
+constexpr uint64_t kStDesc = 1ull << 61;
+constexpr uint64_t kStAsc = 1ull << 60;
+constexpr uint64_t kStCountMask = (1ull << 60) - 1;
+
+// One live segment of a partition pass. Positions are absolute indices into
+// the key arrays; the segment's keys sit in the pass's source buffer.
+struct Seg {
+  uint64_t begin;
+  uint64_t end;
+  uint64_t pivot;      // raw key bits of the pivot (pivot kernel)
+  uint64_t pidx;       // absolute position of the pivot element in the source buffer
+  uint64_t left;       // keys that went left, pivot excluded (last tile of the segment)
+  uint32_t tile_base;  // first tile ticket of the segment in this pass
+  uint32_t ntiles;
+  uint32_t budget;     // bad partitions still allowed (Section 4.1)
+  uint32_t flags;      // kSegLeftmost | kSegFresh
+  uint32_t mode;       // kModeRight / kModeLeft (pivot kernel)
+  uint32_t order_bits; // kStDesc | kStAsc >> 32 of the whole segment (last tile)
+};
+
+// A range handed to a finishing kernel: base case, heapsort or a plain
+// (possibly reversing) copy into the user buffer.
+struct Item {
+  uint64_t begin;
+  uint64_t end;
+  uint32_t buf;     // 0 user buffer, 1 scratch buffer
+  uint32_t reverse; // copy items: write the range in reverse order
+};
+
+// Device-side counters. Host reads a snapshot after each pass.
+struct Counters {
+  uint64_t list[2];        // per list parity: (segments << 32) | tiles
+  uint64_t elems[2];       // per list parity: keys in the list
+  uint32_t nbase, nheap, ncopy, ticket;
+  // statistics (accumulated over the call)
+  uint64_t partitions_right, partitions_left, bad_partitions;
+  uint64_t heap_segments, heap_elements;
+  uint64_t base_segments, base_elements;
+  uint64_t sorted_segments, sorted_elements, equal_elements;
+  uint64_t first_pivot_image;
+  int64_t first_left;
+  int32_t first_mode;
+  uint32_t bad_offsets;    // validation: offsets not monotone / not covering [0, n)
+  uint32_t errors;         // kErr* bits: an internal inconsistency was caught and its writes skipped
+  uint32_t pad_;
+};
+
+constexpr uint32_t kErrCapacity = 1u;  // a list append found its list full (only reachable with bad offsets)
+constexpr uint32_t kErrLookback = 2u;  // a tile's prefix did not fit its segment
+constexpr uint32_t kErrSplit = 4u;     // a segment's left count did not fit the segment
+
+// Everything a kernel needs to know about one sort call.
+struct Ctx {
+  void* keys[2];        // [0] user keys, [1] scratch keys
+  uint32_t* vals[2];    // payloads (null when sorting keys only)
+  uint64_t n;
+  Seg* segs[2];         // live-segment lists, indexed by pass parity
+  uint32_t* tilemap;    // ticket -> segment index
+  uint64_t* status;     // ticket -> look-back status word
+  Item* base;
+  Item* heap;
+  Item* copy;
+  Counters* ctr;
+  const uint64_t* offsets;  // segmented input (null: one segment [0, n))
+  uint64_t nseg;
+  uint32_t tile;        // keys per partition tile
+  uint32_t max_active;  // capacity of each live-segment list
+  uint32_t max_tiles;   // capacity of tilemap / status
+  uint32_t max_items;   // capacity of each item list
+  int32_t force_budget;
+  uint32_t key_type;
+  uint32_t has_vals;
+  uint32_t single;      // 1: one segment [0, n) (records the first partition)
+};
+
+// ---- key traits: canonical unsigned image in registers only ---------------
+// ord() maps a key's bits to an unsigned integer with the same order; inv()
+// undoes it.
+struct KeyU32 {
+  using T = uint32_t;
+  static __device__ __forceinline__ uint32_t ord(uint32_t x) { return x; }
+  static __device__ __forceinline__ uint32_t inv(uint32_t x) { return x; }
+};
+struct KeyI32 {
+  using T = uint32_t;
+  static __device__ __forceinline__ uint32_t ord(uint32_t x) { return x ^ 0x80000000u; }
+  static __device__ __forceinline__ uint32_t inv(uint32_t x) { return x ^ 0x80000000u; }
+};
+struct KeyF32 {
+  using T = uint32_t;
+  // negative: flip all bits; non-negative: set the sign bit
+  static __device__ __forceinline__ uint32_t ord(uint32_t x) {
+    return x ^ (static_cast<uint32_t>(static_cast<int32_t>(x) >> 31) | 0x80000000u);
+  }
+  static __device__ __forceinline__ uint32_t inv(uint32_t y) {
+    return (y & 0x80000000u) ? (y ^ 0x80000000u) : ~y;
+  }
+};
+struct KeyU64 {
+  using T = uint64_t;
+  static __device__ __forceinline__ uint64_t ord(uint64_t x) { return x; }
+  static __device__ __forceinline__ uint64_t inv(uint64_t x) { return x; }
+};
+
+// ---- launch entry points (one translation unit each) ---------------------
+// Every launcher dispatches on ctx.key_type / ctx.has_vals.
+hipError_t launch_reset(const Ctx& c, hipStream_t s);
+hipError_t launch_init(const Ctx& c, hipStream_t s);
+hipError_t launch_pivot(const Ctx& c, int parity, uint32_t nseg, uint32_t src_buf, hipStream_t s);
+hipError_t launch_tilemap(const Ctx& c, int parity, uint32_t ntiles, hipStream_t s);
+hipError_t launch_partition(const Ctx& c, int parity, uint32_t ntiles, uint32_t src_buf, hipStream_t s);
+hipError_t launch_bookkeep(const Ctx& c, int parity, uint32_t nseg, uint32_t src_buf, uint32_t pass,
+                           hipStream_t s);
+hipError_t launch_base(const Ctx& c, uint32_t nitems, hipStream_t s);
+hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s);
+hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s);
+
+inline uint32_t key_bytes(uint32_t key_type) { return key_type == 4 ? 8u : 4u; }
+
+// Number of tile tickets a segment [b, e) takes: tiles are aligned to
+// multiples of `tile` in absolute index space.
+__host__ __device__ inline uint32_t tiles_of(uint64_t b, uint64_t e, uint32_t tile) {
+  return static_cast<uint32_t>((e - 1) / tile - b / tile + 1);
+}
+
+}  // namespace pdq

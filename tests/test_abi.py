@@ -1,0 +1,100 @@
+"""The C ABI library loads, exports every entry point of include/pdq.h, and
+rejects bad arguments before touching the GPU (no compute call here)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pdq.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pdq_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def pdq():
+    import paper_2106_05123_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        from paper_2106_05123_amd import build as b
+        b.build()
+    return p
+
+
+def test_exports_every_declared_function(pdq):
+    names = header_functions()
+    assert {"pdq_sort", "pdq_sort_pairs", "pdq_segmented_sort", "pdq_workspace_bytes"} <= set(names)
+    L = pdq.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", pdq.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (pdq_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_abi_version_matches_header(pdq):
+    m = re.search(r"#define PDQ_ABI_VERSION (\d+)", open(HEADER).read())
+    assert pdq.abi_version() == int(m.group(1))
+
+
+def test_status_strings(pdq):
+    for code, name in ((0, "PDQ_OK"), (-1, "PDQ_ERR_INVALID"), (-2, "PDQ_ERR_UNSUPPORTED"),
+                       (-3, "PDQ_ERR_WORKSPACE"), (-4, "PDQ_ERR_HIP")):
+        assert pdq.status_string(code).startswith(name)
+    assert "unknown" in pdq.status_string(12345)
+
+
+def test_workspace_bytes(pdq):
+    for kt, kb in (("u32", 4), ("i32", 4), ("f32", 4), ("u64", 8)):
+        prev = 0
+        for n in (0, 1, 4096, 4097, 1 << 20, 1 << 28):
+            w = pdq.workspace_bytes(n, 1, kt)
+            assert w >= n * kb and w >= prev
+            assert pdq.workspace_bytes(n, 1, kt, has_vals=True) >= w + 4 * n
+            prev = w
+    assert pdq.workspace_bytes(1 << 20, 1 << 16, "u32") >= pdq.workspace_bytes(1 << 20, 1, "u32")
+    assert pdq.lib().pdq_workspace_bytes(10, 1, 9, 0, None) == 0
+
+
+def _call_sort(pdq, keys, n, kt=1, order=0, ws=0x100000, ws_bytes=1 << 40, opt=None):
+    L = pdq.lib()
+    return L.pdq_sort(ctypes.c_void_p(keys), n, kt, order, ctypes.c_void_p(ws), ws_bytes, None,
+                      ctypes.byref(opt) if opt else None, None)
+
+
+def test_argument_errors_without_gpu(pdq):
+    L = pdq.lib()
+    Opt = pdq.Options
+    assert _call_sort(pdq, 0x1000, 10, order=1) == -2
+    assert _call_sort(pdq, 0x1000, 10, kt=0) == -2
+    assert _call_sort(pdq, 0x1000, 10, kt=5) == -2
+    assert _call_sort(pdq, 0, 10) == -1                      # null keys
+    assert _call_sort(pdq, 0x1002, 10) == -1                 # misaligned u32 keys
+    assert _call_sort(pdq, 0x1004, 10, kt=4) == -1           # misaligned u64 keys
+    assert _call_sort(pdq, 0x1000, 1 << 32) == -2            # n >= 2^32
+    assert _call_sort(pdq, 0x1000, 10, ws=0) == -3           # no workspace
+    assert _call_sort(pdq, 0x1000, 1 << 20, ws_bytes=100) == -3
+    assert _call_sort(pdq, 0, 0) == 0                        # n <= 1 is a no-op
+    assert _call_sort(pdq, 0, 1) == 0
+    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0x80, -1, 0, 0)) == -2  # unknown flag
+    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0, -1, 3000, 0)) == -2  # bad tile
+    # pairs without payload, segmented without offsets
+    assert L.pdq_sort_pairs(ctypes.c_void_p(0x1000), None, 10, 1, 0, ctypes.c_void_p(0x10000), 1 << 40, None,
+                            None, None) == -1
+    assert L.pdq_segmented_sort(ctypes.c_void_p(0x1000), None, 10, None, 3, 1, 0, ctypes.c_void_p(0x10000),
+                                1 << 40, None, None, None) == -1
+    assert L.pdq_segmented_sort(ctypes.c_void_p(0x1000), None, 10, ctypes.c_void_p(0x1004), 3, 1, 0,
+                                ctypes.c_void_p(0x10000), 1 << 40, None, None, None) == -1  # misaligned offsets
+
+
+def test_binding_has_no_fallback(pdq, monkeypatch):
+    """The Python layer never sorts by itself: without the library it raises."""
+    monkeypatch.setattr(pdq, "_lib", None)
+    monkeypatch.setattr(pdq, "LIB_PATH", "/nonexistent/libpdq.so")
+    with pytest.raises(RuntimeError):
+        pdq.lib()

@@ -1,0 +1,220 @@
+"""Parity of the HIP partition sort with the CPU oracle, through the C ABI.
+
+Keys must match the oracle bit for bit. Payloads must form a valid
+permutation that travels with the keys (the sort is unstable, so payload
+order among equal keys is not compared). At the full benchmark size the
+oracle would take too long per case, so there the checks are properties
+that hold at any size: sortedness, an order-independent multiset hash, and
+sampled order statistics counted by brute force."""
+import math
+
+import numpy as np
+import pytest
+
+import gen.workloads as W
+import oracle
+import paper_2106_05123_amd as pdq
+from tests._util import as_bytes, multiset_hash
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pdq.lib()  # fail loudly when the library is missing
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_sort(a, vals=None, **kw):
+    t = to_dev(a)
+    if vals is None:
+        st = pdq.sort_(t, stats=True, **kw)
+        torch.cuda.synchronize()
+        return t.cpu().numpy(), None, st
+    v = to_dev(vals)
+    st = pdq.sort_pairs_(t, v, stats=True, **kw)
+    torch.cuda.synchronize()
+    return t.cpu().numpy(), v.cpu().numpy(), st
+
+
+def check_pairs(keys_in, keys_out, vals_out):
+    assert np.array_equal(as_bytes(keys_out), as_bytes(keys_in[vals_out]))
+    cnt = np.bincount(vals_out.astype(np.int64), minlength=keys_in.size)
+    assert cnt.size == keys_in.size and np.all(cnt == 1)
+
+
+# ------------------------------------------------------------------ plain keys
+
+def test_uniform_u32_2p20_bit_exact_and_first_pass():
+    """Small config: 2^20 uint32 uniform keys, seed 0."""
+    a = W.uniform_u32(1 << 20, seed=0)
+    out, _, st = gpu_sort(a)
+    ref, _, c, _ = oracle.sort(a, count=True)
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+    # the first partition uses the same ninther on the same input, so its
+    # pivot and its left size (count of keys below it) are identical
+    assert st["first_pivot_image"] == c["first_pivot_image"]
+    assert st["first_left_size"] == c["first_left_size"]
+    assert st["first_mode"] == 0
+    assert st["heapsort_segments"] == 0
+
+
+@pytest.mark.parametrize("pattern", W.C2_PATTERNS)
+def test_patterns_i32(pattern):
+    a = W.pattern_i32(pattern, 1 << 22, seed=0, period=1 << 12, tail=1 << 10)
+    out, _, st = gpu_sort(a)
+    ref, _, c, _ = oracle.sort(a, count=True)
+    assert np.array_equal(out, ref)
+    if pattern in ("ascending", "descending"):
+        assert st["passes"] == 1 and st["sorted_elements"] == a.size
+
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 100, 4095, 4096, 4097, 4098, 8191, 8192, 8193, 12289, 65537, 1000003])
+def test_sizes_and_key_types(kt, n):
+    a = W.random_keys(kt, n, seed=n + 17)
+    out, _, _ = gpu_sort(a)
+    ref, _, _, _ = oracle.sort(a) if n else (a.copy(), None, None, None)
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+
+
+@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("pattern", ["random", "organ_pipe", "sawtooth"])
+def test_tile_sizes_same_keys(tile, pattern):
+    a = W.pattern_i32(pattern, (1 << 21) + 12345, seed=3, period=1 << 9)
+    out, _, _ = gpu_sort(a, tile=tile)
+    assert np.array_equal(out, oracle.sort(a)[0])
+
+
+def test_float_edge_bit_patterns():
+    bits = np.array([0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x807FFFFF, 0x80000001, 0x80000000,
+                     0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x3F800000, 0x7F7FFFFF, 0x7F800000],
+                    dtype=np.uint32)
+    rng = np.random.default_rng(5)
+    reps = 3000
+    a = np.tile(bits, reps)[rng.permutation(bits.size * reps)].view(np.float32)
+    out, _, _ = gpu_sort(a)
+    assert np.array_equal(out.view(np.uint32), np.repeat(bits, reps))
+
+
+def test_all_equal_and_two_values():
+    for a in (np.full(1 << 20, 7, np.uint32), W.k_distinct_u64(1 << 20, 2, seed=1)):
+        out, _, st = gpu_sort(a)
+        assert np.array_equal(out, np.sort(a))
+
+
+# ------------------------------------------------------------------ pairs / equal keys
+
+@pytest.mark.parametrize("k", [2, 16, 1024, 65536, "mix"])
+def test_k_distinct_u64_pairs(k):
+    n = 1 << 21
+    a = W.one_value_mix_u64(n, seed=2) if k == "mix" else W.k_distinct_u64(n, k, seed=k)
+    v = W.index_payload(n)
+    out, vo, st = gpu_sort(a, v)
+    ref, _, c, _ = oracle.sort(a, count=True)
+    assert np.array_equal(out, ref)
+    check_pairs(a, out, vo)
+    if k != "mix" and k <= 16:
+        # Theorem 1: each distinct value is a pivot at most twice
+        assert st["passes"] <= 2 * k + 2
+        assert st["element_visits"] <= n * (2 * k + 2)
+
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+def test_pairs_key_types(kt):
+    n = (1 << 20) + 77
+    a = W.random_keys(kt, n, seed=8)
+    if kt in ("u32", "u64"):
+        a = a % a.dtype.type(5000)
+    elif kt == "i32":
+        a = (a % 5000).astype(np.int32)
+    v = np.random.default_rng(1).permutation(n).astype(np.uint32)
+    out, vo, _ = gpu_sort(a, v)
+    assert np.array_equal(as_bytes(out), as_bytes(oracle.sort(a)[0]))
+    assert np.array_equal(as_bytes(out), as_bytes(a[np.argsort(v)][vo]))
+    assert np.array_equal(np.sort(vo), np.arange(n, dtype=np.uint32))
+
+
+# ------------------------------------------------------------------ segmented
+
+def test_segmented_f32_pairs():
+    keys, off, vals = W.segmented_f32(500, max_log2=16, seed=4)
+    t, o, v = to_dev(keys), to_dev(off), to_dev(vals)
+    st = pdq.segmented_sort_(t, o, v, stats=True, validate=True)
+    out, vo = t.cpu().numpy(), v.cpu().numpy()
+    ref, _, _ = oracle.segmented_sort(keys, off)
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+    check_pairs(keys, out, vo)
+    seg_of = np.searchsorted(off, np.arange(keys.size, dtype=np.uint64), side="right") - 1
+    assert np.array_equal(seg_of[vo], seg_of)  # payloads stay inside their segment
+
+
+def test_segmented_empty_and_tiny_segments():
+    sizes = np.array([0, 1, 0, 2, 3, 4096, 4097, 0, 1, 9000, 0], dtype=np.int64)
+    off = W.offsets_from_sizes(sizes)
+    a = W.uniform_u32(int(off[-1]), seed=9)
+    t = to_dev(a)
+    pdq.segmented_sort_(t, to_dev(off), validate=True)
+    assert np.array_equal(t.cpu().numpy(), oracle.segmented_sort(a, off)[0])
+
+
+def test_segmented_validate_rejects_bad_offsets():
+    a = W.uniform_u32(1000, seed=1)
+    bad = np.array([0, 600, 400, 1000], dtype=np.uint64)  # not monotone
+    with pytest.raises(pdq.PdqError) as ei:
+        pdq.segmented_sort_(to_dev(a), to_dev(bad), validate=True)
+    assert ei.value.status == -1
+    short = np.array([0, 500, 900], dtype=np.uint64)      # does not end at n
+    with pytest.raises(pdq.PdqError):
+        pdq.segmented_sort_(to_dev(a), to_dev(short), validate=True)
+
+
+# ------------------------------------------------------------------ fallbacks
+
+@pytest.mark.parametrize("n", [4097, 5000, 20000])
+def test_forced_heapsort(n):
+    a = W.uniform_u32(n, seed=n)
+    v = W.index_payload(n)
+    out, vo, st = gpu_sort(a, v, force_budget=0)
+    assert st["heapsort_segments"] == 1 and st["heapsort_elements"] == n
+    assert np.array_equal(out, oracle.sort(a)[0])
+    check_pairs(a, out, vo)
+
+
+def test_budget_one_reaches_heapsort_after_bad_partition():
+    a = W.pattern_i32("organ_pipe", 1 << 16)
+    out, _, st = gpu_sort(a, force_budget=1)
+    assert st["bad_partitions"] >= 1 and st["heapsort_segments"] >= 1
+    assert np.array_equal(out, oracle.sort(a)[0])
+
+
+# ------------------------------------------------------------------ full size, sampled
+
+def test_full_size_random_i32_sampled():
+    """2^28 int32 uniform keys in the benchmark's launch configuration:
+    sortedness, multiset hash, and order statistics at sampled ranks
+    (count of keys below / not above the output key, by brute force)."""
+    n = 1 << 28
+    a = W.pattern_i32("random", n, seed=0)
+    t = to_dev(a)
+    pdq.sort_(t)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    del t
+    torch.cuda.empty_cache()
+    assert np.all(out[1:] >= out[:-1])
+    assert multiset_hash(out) == multiset_hash(a)
+    rng = np.random.default_rng(0)
+    for r in list(rng.integers(0, n, 12)) + [0, n // 2, n - 1]:
+        v = out[r]
+        lt = int(np.count_nonzero(a < v))
+        le = int(np.count_nonzero(a <= v))
+        assert lt <= r < le
