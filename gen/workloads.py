@@ -49,9 +49,11 @@ def uniform_u64(n: int, seed: int = 0) -> np.ndarray:
 
 
 def pattern_i32(pattern: str, n: int, seed: int = 0, period: int = 1 << 16,
-                tail: int = 1 << 10) -> np.ndarray:
+                tail: int = 1 << 10, sorter=None) -> np.ndarray:
     """int32 keys in one of `C2_PATTERNS` (sign bit exercised: values are
-    centred on zero)."""
+    centred on zero). `sorter`, if given, replaces np.sort for the one
+    pattern that needs a sorted copy of its input (any correct sort gives
+    the same array)."""
     rng = np.random.default_rng(seed)
     half = n // 2
     if pattern == "random":
@@ -68,7 +70,7 @@ def pattern_i32(pattern: str, n: int, seed: int = 0, period: int = 1 << 16,
         return (np.arange(n, dtype=np.int64) % period).astype(np.int32)
     if pattern == "random_1pct_sorted":
         a = rng.integers(-(2**31), 2**31, n, dtype=np.int32)
-        s = np.sort(a, kind="stable")
+        s = np.sort(a) if sorter is None else sorter(a)
         pos = rng.choice(n, size=max(1, n // 100), replace=False) if n > 0 else np.zeros(0, np.int64)
         a[pos] = s[pos]
         return a

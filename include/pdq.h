@@ -6,8 +6,8 @@
  * range (Sections 1 and 3: a [begin, end) range, a comparison order, no
  * stability). Its data-parallel hot path -- the partition step -- runs as
  * out-of-place passes over all live segments at once:
- *   - pivot: Tukey's ninther, with fresh candidates after a bad
- *     partition (Sections 2 and 4.2);
+ *   - pivot: Tukey's ninther, with fresh (hashed, seeded) candidates
+ *     after a bad partition (Sections 2 and 4.2);
  *   - partition_right, or partition_left when the pivot equals the
  *     predecessor, so k distinct keys need O(k) passes (Section 3,
  *     Lemmas 1-4, Theorem 1);
@@ -83,8 +83,8 @@ typedef struct pdq_options {
   uint32_t struct_size;  /* sizeof(pdq_options); 0 or a smaller value = older layout */
   uint32_t flags;        /* pdq_flags */
   int32_t force_budget;  /* < 0: floor(log2 size) per segment (Section 4.1); >= 0: that budget */
-  uint32_t tile;         /* keys per partition tile: 0 = auto, else 1024, 2048, 4096 or 8192 */
-  uint64_t seed;         /* reserved for the learned-splitter path */
+  uint32_t tile;         /* keys per partition tile: 0 = auto (32768), else 1024 ... 65536, a power of two */
+  uint64_t seed;         /* seeds the hashed pivot candidates taken after a bad partition */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */

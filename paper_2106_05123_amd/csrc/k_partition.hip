@@ -13,10 +13,16 @@
 //   * a decoupled look-back over the tiles of the segment (tile tickets come
 //     from an atomic counter, so every tile waits only on tiles already
 //     running) gives the number of left keys before the tile;
-//   * keys are regrouped in LDS so that each class is one contiguous run,
-//     then written out coalesced: left keys from the segment start upward,
-//     right keys from the segment end downward (the right side is thus
-//     reversed, which no later step depends on);
+//   * keys are written straight from registers: within a (row, wave) the
+//     ranks of one class are consecutive, so every store instruction writes
+//     at most two contiguous runs -- left keys upward from the segment
+//     start, right keys downward from the segment end (the right side is
+//     thus reversed, which no later step depends on);
+//   * a tile that finds its prefix also publishes the inclusive prefixes of
+//     the predecessors it summed, so one finished look-back moves the
+//     frontier for a whole window;
+//   * the next tile's ticket, descriptor and keys are fetched while the
+//     current tile does its look-back and scatter;
 //   * the tile also records whether its adjacent pairs ever descend or
 //     ascend; the look-back ORs these bits so that the segment's last tile
 //     knows whether the whole segment was already ordered (Section 5.2).
@@ -26,22 +32,158 @@
 namespace pdq {
 namespace {
 
-template <class K, bool PAIRS, int NT, int IT>
+template <class T>
+struct TileDesc {
+  uint64_t b, e, pidx, chunk;
+  T piv;
+  uint32_t si, tis, nts;
+  bool left_mode;
+};
+
+template <class T, int TILE>
+__device__ __forceinline__ TileDesc<T> tile_desc(const Seg* segs, const uint32_t* tilemap, uint32_t t) {
+  TileDesc<T> d;
+  d.si = __builtin_amdgcn_readfirstlane(tilemap[t]);
+  const Seg* sg = segs + d.si;
+  d.b = sg->begin;
+  d.e = sg->end;
+  d.pidx = sg->pidx;
+  d.piv = static_cast<T>(sg->pivot);
+  d.left_mode = sg->mode == kModeLeft;
+  d.tis = t - sg->tile_base;
+  d.nts = sg->ntiles;
+  d.chunk = (d.b / TILE + d.tis) * static_cast<uint64_t>(TILE);
+  return d;
+}
+
+// Buffer descriptor over a whole array (no range limit; gfx9 layout).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, 0xFFFFFFFF, 0x00020000);
+}
+
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return static_cast<T>(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    v2i x = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return static_cast<T>(static_cast<uint32_t>(x.x)) | (static_cast<T>(static_cast<uint32_t>(x.y)) << 32);
+  }
+}
+
+// Loads one sub-tile: row i, lane tid holds slot i*NT + tid of the SUB
+// slots starting at absolute index base. A sub-tile wholly inside the array
+// is read unconditionally through a buffer descriptor (the row offset rides
+// in the scalar offset, so every row shares one vector offset); slots
+// outside the segment are ignored later. Only a sub-tile running past the
+// end of the array is read with per-slot predicates.
+template <class T, int NT, int IT>
+__device__ __forceinline__ void load_sub(uint64_t base, uint64_t n, const T* __restrict__ src, int tid, T (&k)[IT]) {
+  constexpr int SUB = NT * IT;
+  if (base + SUB <= n) {
+    const __amdgpu_buffer_rsrc_t rk = make_rsrc(src + base);
+    const uint32_t vo = static_cast<uint32_t>(tid) * sizeof(T);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) k[i] = buf_load<T>(rk, vo, static_cast<uint32_t>(i * NT * sizeof(T)));
+  } else {
+    const uint32_t lim = static_cast<uint32_t>(n - base);
+    const T* __restrict__ ts = src + base;
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const uint32_t off = static_cast<uint32_t>(i * NT + tid);
+      k[i] = off < lim ? ts[off] : T(0);
+    }
+  }
+}
+
+// Geometry of one tile (NSUB sub-tiles of SUB slots) inside its chunk:
+// slots [lo, hi) belong to the segment, pl is the pivot's slot (or none),
+// the successor of slot s is in the segment iff s + 1 < erel.
+struct TileGeom {
+  uint32_t lo, hi, pl, erel;
+};
+
+template <class T, int TILE>
+__device__ __forceinline__ TileGeom tile_geom(const TileDesc<T>& d) {
+  TileGeom g;
+  const uint64_t tlo = d.chunk > d.b ? d.chunk : d.b;
+  const uint64_t thi = d.chunk + TILE < d.e ? d.chunk + TILE : d.e;
+  g.lo = static_cast<uint32_t>(tlo - d.chunk);
+  g.hi = static_cast<uint32_t>(thi - d.chunk);
+  g.pl = (d.pidx >= d.chunk && d.pidx < d.chunk + TILE) ? static_cast<uint32_t>(d.pidx - d.chunk) : 0xFFFFFFFFu;
+  const uint64_t erel64 = d.e - d.chunk;
+  g.erel = erel64 < static_cast<uint64_t>(TILE + 1) ? static_cast<uint32_t>(erel64) : TILE + 1;
+  return g;
+}
+
+// Classification of one sub-tile (first slot s0 of the tile): bit i of
+// lmask = key of row i goes left (x < p for partition_right, x <= p for
+// partition_left), bit i of vmask = key of row i is a real, non-pivot key of
+// the segment. FULL: every slot is such a key and every in-group successor
+// lies inside the segment. Also reports whether adjacent pairs inside a
+// (row, wave) group descend / ascend.
+template <class K, int NT, int IT, bool FULL, bool PAIRCHECK>
+__device__ __forceinline__ void classify(const typename K::T (&k)[IT], const TileGeom& g, uint32_t s0,
+                                         bool left_mode, decltype(K::ord(typename K::T(0))) pv, int tid,
+                                         uint32_t& lmask, uint32_t& vmask, bool& has_d, bool& has_a) {
+  const int lane = tid & 63;
+  lmask = 0;
+  vmask = FULL ? ((IT == 32) ? 0xFFFFFFFFu : ((1u << IT) - 1u)) : 0u;
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const auto ko = K::ord(k[i]);
+    bool l;
+    const uint32_t off = s0 + static_cast<uint32_t>(i * NT + tid);
+    if constexpr (FULL) {
+      l = left_mode ? (ko <= pv) : (ko < pv);
+    } else {
+      const bool v = off >= g.lo && off < g.hi && off != g.pl;
+      l = v && (left_mode ? (ko <= pv) : (ko < pv));
+      vmask |= (v ? 1u : 0u) << i;
+    }
+    lmask |= (l ? 1u : 0u) << i;
+    if constexpr (PAIRCHECK) {
+      const typename K::T nx = __shfl_down(k[i], 1, 64);  // successor inside the group (lanes 0..62)
+      const auto z = K::ord(nx);
+      bool pair_ok = lane < 63;
+      if constexpr (!FULL) pair_ok = pair_ok && off >= g.lo && off < g.hi && off + 1 < g.erel;
+      has_d |= pair_ok && (z < ko);
+      has_a |= pair_ok && (z > ko);
+    }
+  }
+}
+
+// The partition kernel. A workgroup takes one tile of NSUB sub-tiles (SUB =
+// NT*IT keys each) and makes two streaming passes over it:
+//   count:   load each sub-tile, classify, record per (row, wave) group its
+//            left count and first / last key; no barrier inside the pass;
+//   publish: one barrier, then wave 0 scans the group counts, publishes the
+//            tile's aggregate and runs the decoupled look-back;
+//   scatter: load each sub-tile again (it was just read, so it comes from
+//            the caches), classify again and write every key straight from
+//            registers to its final place; no barrier inside the pass.
+// Keys therefore cross HBM once on the way in and once on the way out, while
+// the look-back, the only wait on other workgroups, is paid once per NSUB
+// sub-tiles.
+template <class K, bool PAIRS, int NT, int IT, int NSUB>
 __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t src_buf) {
   using T = typename K::T;
   constexpr int NW = NT / 64;
-  constexpr int TILE = NT * IT;
-  constexpr int NCNT = IT * NW;
-  constexpr int CPL = (NCNT + 63) / 64;  // count entries per lane of the scanning wave
+  constexpr int SUB = NT * IT;
+  constexpr int TILE = SUB * NSUB;
+  constexpr int NG = NSUB * IT * NW;  // (sub-tile, row, wave) groups; group q covers slots [64q, 64q + 64)
+  constexpr int GPL = (NG + 63) / 64;  // groups per lane of wave 0
+  static_assert(IT <= 32, "row masks are 32-bit");
 
-  __shared__ T s_key[TILE];
-  __shared__ uint32_t s_val[PAIRS ? TILE : 1];
-  __shared__ uint32_t s_cnt[NCNT];
-  __shared__ T s_first[NCNT];
-  __shared__ uint32_t s_ticket;
+  __shared__ uint32_t s_cnt[NG];  // per group left counts, then exclusive prefixes over the tile
+  __shared__ T s_first[NG];       // first / last key of each group: pairs across groups
+  __shared__ T s_last[NG];
+  __shared__ uint32_t s_next;     // the workgroup's next ticket
   __shared__ uint32_t s_bits;
   __shared__ uint64_t s_lpre;
   __shared__ uint32_t s_nl;
+  __shared__ T s_tail;            // first key after the tile (when the segment continues)
 
   const T* __restrict__ src = static_cast<const T*>(c.keys[src_buf]);
   T* __restrict__ dst = static_cast<T*>(c.keys[src_buf ^ 1]);
@@ -53,120 +195,104 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
   const int lane = tid & 63;
   const int wv = tid >> 6;
 
+  // Tickets come from one counter in the order workgroups ask, so a tile
+  // only ever waits on tiles that running workgroups already hold. A
+  // workgroup asks for its next ticket only when it is about to finish the
+  // current tile: a ticket held long before its tile starts would make
+  // every later tile of the segment wait for it.
+  if (tid == 0) {
+    s_next = atomicAdd(&c.ctr->ticket, 1u);
+    s_bits = 0;
+  }
+  lds_barrier();
+  uint32_t t = __builtin_amdgcn_readfirstlane(s_next);
+  if (t >= ntiles) return;
+  TileDesc<T> d = tile_desc<T, TILE>(segs, c.tilemap, t);
+  lds_barrier();  // every wave has read s_next
+
   for (;;) {
-    if (tid == 0) {
-      s_ticket = atomicAdd(&c.ctr->ticket, 1u);
-      s_bits = 0;
-    }
-    __syncthreads();
-    const uint32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
-    if (t >= ntiles) break;
+    const TileGeom g = tile_geom<T, TILE>(d);
+    const auto pv = K::ord(d.piv);
+    if (tid == NT - 1) s_tail = (g.erel > static_cast<uint32_t>(TILE)) ? src[d.chunk + TILE] : T(0);
 
-    const uint32_t si = __builtin_amdgcn_readfirstlane(c.tilemap[t]);
-    const uint64_t b = segs[si].begin;
-    const uint64_t e = segs[si].end;
-    const uint64_t pidx = segs[si].pidx;
-    const T piv = static_cast<T>(segs[si].pivot);
-    const bool left_mode = segs[si].mode == kModeLeft;
-    const uint32_t tis = t - segs[si].tile_base;
-    const uint32_t nts = segs[si].ntiles;
-    const uint64_t chunk = (b / TILE + tis) * static_cast<uint64_t>(TILE);
-    const uint64_t tlo = chunk > b ? chunk : b;
-    const uint64_t thi = chunk + TILE < e ? chunk + TILE : e;
-    const auto pv = K::ord(piv);
-    // tile-relative coordinates: slots [lo, hi) of the chunk belong to the
-    // segment; pl is the pivot's slot (or none); the successor of slot s
-    // exists in the segment iff s + 1 < erel
-    const T* __restrict__ tsrc = src + chunk;
-    const uint32_t lo = static_cast<uint32_t>(tlo - chunk);
-    const uint32_t hi = static_cast<uint32_t>(thi - chunk);
-    const uint32_t pl = (pidx >= chunk && pidx < chunk + TILE) ? static_cast<uint32_t>(pidx - chunk) : 0xFFFFFFFFu;
-    const uint32_t erel = static_cast<uint32_t>((e - chunk) < static_cast<uint64_t>(TILE + 1) ? (e - chunk) : TILE + 1);
+    // sub-tiles that hold keys of the segment: [j0, j1)
+    const int j0 = static_cast<int>(g.lo / SUB);
+    const int j1 = static_cast<int>((g.hi + SUB - 1) / SUB);
 
-    // ---- load (coalesced rows) and classify -------------------------------
-    T key[IT];
-    uint32_t val[PAIRS ? IT : 1];
-    uint32_t below[IT];  // left keys of lower lanes in the same (row, wave)
-    uint32_t lmask = 0;  // bit i: key of row i goes left
-    uint32_t vmask = 0;  // bit i: key of row i is a real, non-pivot key
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const uint32_t off = static_cast<uint32_t>(i * NT + tid);
-      const bool in = off >= lo && off < hi;
-      key[i] = in ? tsrc[off] : T(0);
-      if (PAIRS) val[i] = in ? srcv[chunk + off] : 0u;
-    }
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      const uint32_t off = static_cast<uint32_t>(i * NT + tid);
-      const bool v = off >= lo && off < hi && off != pl;
-      const auto ko = K::ord(key[i]);
-      const bool l = v && (left_mode ? (ko <= pv) : (ko < pv));
-      const uint64_t m = __ballot(l);
-      below[i] = lanes_below(m);
-      if (lane == 0) {
-        s_cnt[i * NW + wv] = static_cast<uint32_t>(__popcll(m));
-        s_first[i * NW + wv] = key[i];
-      }
-      lmask |= (l ? 1u : 0u) << i;
-      vmask |= (v ? 1u : 0u) << i;
-    }
-    __syncthreads();
-
-    // ---- adjacent pairs: does the tile's part of the segment ever descend/ascend?
+    // ---- count pass (the next sub-tile is loaded while this one is classified)
     {
+      for (int j = 0; j < NSUB; ++j)
+        if ((j < j0 || j >= j1) && lane < IT) s_cnt[(j * IT + lane) * NW + wv] = 0;
       bool has_d = false, has_a = false;
+      T k[IT], kn[IT];
+      load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+#pragma unroll 1
+      for (int j = j0; j < j1; ++j) {
+        const uint32_t s0 = static_cast<uint32_t>(j * SUB);
+        if (j + 1 < j1) load_sub<T, NT, IT>(d.chunk + s0 + SUB, c.n, src, tid, kn);
+        uint32_t* gc = s_cnt + j * IT * NW;
+        T* gf = s_first + j * IT * NW;
+        T* gl = s_last + j * IT * NW;
+        const bool full = s0 >= g.lo && s0 + SUB <= g.hi && s0 + SUB < g.erel && !(g.pl >= s0 && g.pl < s0 + SUB);
+        uint32_t lmask, vmask;
+        if (full)
+          classify<K, NT, IT, true, true>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, has_d, has_a);
+        else
+          classify<K, NT, IT, false, true>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, has_d, has_a);
 #pragma unroll
-      for (int i = 0; i < IT; ++i) {
-        T nx = __shfl_down(key[i], 1, 64);
-        const uint32_t off = static_cast<uint32_t>(i * NT + tid);
-        const bool pv_ok = off >= lo && off < hi && off + 1 < erel;
-        if (lane == 63) {
-          if (wv < NW - 1) nx = s_first[i * NW + wv + 1];
-          else if (i < IT - 1) nx = s_first[(i + 1) * NW];
-          else if (pv_ok) nx = tsrc[TILE];
+        for (int i = 0; i < IT; ++i) {
+          const uint64_t m = __ballot((lmask >> i) & 1u);
+          if (lane == 0) {
+            gc[i * NW + wv] = static_cast<uint32_t>(__popcll(m));
+            gf[i * NW + wv] = k[i];
+          }
+          if (lane == 63) gl[i * NW + wv] = k[i];
         }
-        const auto a = K::ord(key[i]);
-        const auto z = K::ord(nx);
-        has_d |= pv_ok && (z < a);
-        has_a |= pv_ok && (z > a);
-      }
-      const bool wd = __any(has_d);
-      const bool wa = __any(has_a);
-      if (lane == 0 && (wd || wa)) atomicOr(&s_bits, (wd ? static_cast<uint32_t>(kStDesc >> 32) : 0u) |
-                                                          (wa ? static_cast<uint32_t>(kStAsc >> 32) : 0u));
-    }
-
-    __syncthreads();  // s_bits complete
-
-    // ---- tile scan over (row, wave) counts, then decoupled look-back --------
-    if (wv == 0) {
-      uint32_t loc[CPL];
-      uint32_t sum = 0;
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const int idx = lane * CPL + k;
-        loc[k] = idx < NCNT ? s_cnt[idx] : 0u;
-        sum += loc[k];
+        for (int i = 0; i < IT; ++i) k[i] = kn[i];
+      }
+      const bool wd = __any(has_d), wa = __any(has_a);
+      if (lane == 0 && (wd || wa))
+        atomicOr(&s_bits, (wd ? static_cast<uint32_t>(kStDesc >> 32) : 0u) |
+                              (wa ? static_cast<uint32_t>(kStAsc >> 32) : 0u));
+    }
+    lds_barrier();  // B1: group counts, group edge keys, in-group pair bits
+
+    // ---- wave 0: edge pairs, scan, publish, decoupled look-back -------------
+    if (wv == 0) {
+      uint32_t loc[GPL];
+      uint32_t sum = 0;
+      bool ed = false, ea = false;
+      const T tn = s_tail;
+#pragma unroll
+      for (int kk = 0; kk < GPL; ++kk) {
+        const int q = lane * GPL + kk;
+        loc[kk] = q < NG ? s_cnt[q] : 0u;
+        sum += loc[kk];
+        const uint32_t slot = static_cast<uint32_t>(q) * 64u + 63u;  // last slot of group q
+        if (q < NG && slot >= g.lo && slot < g.hi && slot + 1 < g.erel) {
+          const auto a = K::ord(s_last[q]);
+          const auto z = K::ord(q + 1 < NG ? s_first[q + 1] : tn);
+          ed |= z < a;
+          ea |= z > a;
+        }
       }
       const uint64_t incl = wave_incl_scan_u64(sum);
       const uint32_t nl = static_cast<uint32_t>(__shfl(incl, 63, 64));
+      const bool wd = __any(ed), wa = __any(ea);
+      const uint64_t own_bits = (static_cast<uint64_t>(s_bits) << 32) | (wd ? kStDesc : 0ull) | (wa ? kStAsc : 0ull);
+      // publish this tile's aggregate (or its inclusive prefix) at once
+      if (lane == 0) store_status(&c.status[t], (d.tis == 0 ? kStIncl : kStAgg) | nl | own_bits);
       uint32_t run = static_cast<uint32_t>(incl) - sum;
 #pragma unroll
-      for (int k = 0; k < CPL; ++k) {
-        const int idx = lane * CPL + k;
-        if (idx < NCNT) s_cnt[idx] = run;
-        run += loc[k];
+      for (int kk = 0; kk < GPL; ++kk) {
+        if (lane * GPL + kk < NG) s_cnt[lane * GPL + kk] = run;
+        run += loc[kk];
       }
-      const uint64_t own_bits = static_cast<uint64_t>(s_bits) << 32;
-      const uint64_t own = static_cast<uint64_t>(nl) | own_bits;
       uint64_t ex = 0, exb = 0;
-      if (tis == 0) {
-        if (lane == 0) store_status(&c.status[t], kStIncl | own);
-      } else {
-        if (lane == 0) store_status(&c.status[t], kStAgg | own);
+      if (d.tis != 0) {
         uint32_t look = t - 1;
-        uint32_t rem = tis;  // tiles of this segment before this one
+        uint32_t rem = d.tis;  // tiles of this segment before this one
         for (;;) {
           uint64_t w = kStIncl;  // lanes past the segment's first tile read as an empty prefix
           if (static_cast<uint32_t>(lane) < rem) w = load_status(&c.status[look - lane]);
@@ -180,9 +306,27 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
             continue;
           }
           const bool take = lane <= fi;
-          ex += wave_sum_u64(take ? (w & kStCountMask) : 0ull);
-          exb |= wave_or_u64(take ? (w & (kStDesc | kStAsc)) : 0ull);
-          if (fi < 64) break;
+          const uint64_t cnt = take ? (w & kStCountMask) : 0ull;
+          const uint64_t bb = take ? (w & (kStDesc | kStAsc)) : 0ull;
+          if (fi < 64) {
+            // suffix sums over lanes k..fi are the inclusive prefixes of the
+            // tiles between the one found and this one: publish them too
+            uint64_t sc = cnt, sb = bb;
+            for (int dd = 1; dd < 64; dd <<= 1) {
+              const uint64_t tc = __shfl_down(sc, dd, 64);
+              const uint64_t tb = __shfl_down(sb, dd, 64);
+              if (lane + dd < 64) {
+                sc += tc;
+                sb |= tb;
+              }
+            }
+            if (lane < fi) store_status(&c.status[look - lane], kStIncl | sc | sb);
+            ex += __shfl(sc, 0, 64);
+            exb |= __shfl(sb, 0, 64);
+            break;
+          }
+          ex += wave_sum_u64(cnt);
+          exb |= wave_or_u64(bb);
           look -= 64;
           rem -= 64;
         }
@@ -191,55 +335,96 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
       if (lane == 0) {
         s_lpre = ex;
         s_nl = nl;
-        if (tis == nts - 1) {
-          segs[si].left = ex + nl;
-          segs[si].order_bits = static_cast<uint32_t>((exb | own_bits) >> 32);
+        s_bits = 0;  // ready for the next tile (all reads of it are done)
+        if (d.tis == d.nts - 1) {
+          segs[d.si].left = ex + nl;
+          segs[d.si].order_bits = static_cast<uint32_t>((exb | own_bits) >> 32);
         }
       }
     }
-    __syncthreads();
+    lds_barrier();  // B2: group prefixes, tile prefix and count
 
-    // ---- regroup in LDS: left run [0, nl), right run [nl, nvalid) -----------
-    const uint32_t nl = s_nl;
-    const uint64_t lpre = s_lpre;
-    const uint64_t pre_valid = (tlo - b) - (pidx < tlo ? 1u : 0u);
-    // lpre <= pre_valid bounds every write below inside [b, e); it always
-    // holds unless the look-back is broken, in which case the tile writes
-    // nothing and flags the call
-    const bool sane = lpre <= pre_valid;
-    if (!sane && tid == 0) atomicOr(&c.ctr->errors, kErrLookback);
-    const uint64_t gpre = sane ? pre_valid - lpre : 0;
-    const uint64_t lbase = b + lpre;      // where this tile's first left key goes
-    const uint64_t rbase = e - 1 - gpre;  // where this tile's first right key goes (then downward)
+    uint32_t nticket = 0;
+    if (tid == 0) nticket = atomicAdd(&c.ctr->ticket, 1u);  // returns while the tile is written out
+
+    // ---- scatter pass: reload, classify again, write from registers ---------
+    {
+      const uint32_t nl = __builtin_amdgcn_readfirstlane(s_nl);
+      const uint64_t lpre = (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre >> 32)))
+                             << 32) |
+                            __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre));
+      const uint64_t tlo = d.chunk + g.lo;
+      const uint64_t pre_valid = (tlo - d.b) - (d.pidx < tlo ? 1u : 0u);
+      const bool piv_in = g.pl >= g.lo && g.pl < g.hi;
+      const uint32_t nvalid = (g.hi - g.lo) - (piv_in ? 1u : 0u);
+      // lpre <= pre_valid and nl <= nvalid bound every write below inside
+      // [b, e); they always hold unless the look-back is broken, in which
+      // case the tile writes nothing and flags the call
+      const bool sane = lpre <= pre_valid && nl <= nvalid;
+      if (!sane && tid == 0) atomicOr(&c.ctr->errors, kErrLookback);
+      if (sane) {
+        const uint32_t nr = nvalid - nl;
+        const uint64_t gpre = pre_valid - lpre;
+        // left keys of this tile occupy [b + lpre, b + lpre + nl); right keys
+        // occupy [e - gpre - nr, e - gpre) in descending order of their rank
+        T* __restrict__ dl = dst + (d.b + lpre);
+        T* __restrict__ drl = dst + (d.e - gpre - nr);
+        uint32_t* __restrict__ dlv = PAIRS ? dstv + (d.b + lpre) : nullptr;
+        uint32_t* __restrict__ drlv = PAIRS ? dstv + (d.e - gpre - nr) : nullptr;
+        T k[IT], kn[IT];
+        uint32_t v[PAIRS ? IT : 1], vn[PAIRS ? IT : 1];
+        load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+        if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, srcv, tid, v);
+#pragma unroll 1
+        for (int j = j0; j < j1; ++j) {
+          const uint32_t s0 = static_cast<uint32_t>(j * SUB);
+          if (j + 1 < j1) {
+            load_sub<T, NT, IT>(d.chunk + s0 + SUB, c.n, src, tid, kn);
+            if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + s0 + SUB, c.n, srcv, tid, vn);
+          }
+          const bool full = s0 >= g.lo && s0 + SUB <= g.hi && !(g.pl >= s0 && g.pl < s0 + SUB);
+          // real keys of the tile before slot s0 + x are x + adj for x in a
+          // full sub-tile: adj = s0 - lo - (pivot before s0)
+          const uint32_t adj = s0 - g.lo - ((piv_in && g.pl < s0) ? 1u : 0u);
+          uint32_t lmask, vmask;
+          bool dd_, da_;
+          if (full)
+            classify<K, NT, IT, true, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
+          else
+            classify<K, NT, IT, false, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
+          const uint32_t* gc = s_cnt + j * IT * NW;
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-      if (sane && ((vmask >> i) & 1u)) {
-        const uint32_t rx = s_cnt[i * NW + wv] + below[i];  // left keys before this one in the tile
-        uint32_t slot;
-        if ((lmask >> i) & 1u) {
-          slot = rx;
-        } else {
-          const uint32_t off = static_cast<uint32_t>(i * NT + tid);
-          const uint32_t before = (off - lo) - ((pl >= lo && pl < off) ? 1u : 0u);
-          slot = nl + (before - rx);
+          for (int i = 0; i < IT; ++i) {
+            const bool l = (lmask >> i) & 1u;
+            const uint64_t m = __ballot(l);
+            const uint32_t rx = gc[i * NW + wv] + lanes_below(m);  // left keys before this one in the tile
+            if (full || ((vmask >> i) & 1u)) {
+              if (l) {
+                dl[rx] = k[i];
+                if constexpr (PAIRS) dlv[rx] = v[i];
+              } else {
+                const uint32_t x = static_cast<uint32_t>(i * NT + tid);
+                uint32_t before = x + adj;  // real keys of the tile before this one
+                if (!full) before = (s0 + x - g.lo) - ((piv_in && g.pl < s0 + x) ? 1u : 0u);
+                const uint32_t q = nr - 1u - (before - rx);
+                drl[q] = k[i];
+                if constexpr (PAIRS) drlv[q] = v[i];
+              }
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < IT; ++i) {
+            k[i] = kn[i];
+            if constexpr (PAIRS) v[i] = vn[i];
+          }
         }
-        s_key[slot] = key[i];
-        if (PAIRS) s_val[slot] = val[i];
       }
     }
-    __syncthreads();
-
-    // ---- coalesced write: left keys upward from b, right keys downward from e
-    const uint32_t nvalid = (hi - lo) - ((pl >= lo && pl < hi) ? 1u : 0u);
-#pragma unroll
-    for (int j = 0; j < IT; ++j) {
-      const uint32_t slot = static_cast<uint32_t>(j * NT + tid);
-      if (sane && slot < nvalid) {
-        const uint64_t p = slot < nl ? (lbase + slot) : (rbase - (slot - nl));
-        dst[p] = s_key[slot];
-        if (PAIRS) dstv[p] = s_val[slot];
-      }
-    }
+    if (tid == 0) s_next = nticket;
+    lds_barrier();  // B3: next ticket; LDS is rewritten by the next tile
+    t = __builtin_amdgcn_readfirstlane(s_next);
+    if (t >= ntiles) break;
+    d = tile_desc<T, TILE>(segs, c.tilemap, t);
   }
 }
 
@@ -257,12 +442,13 @@ int device_cus() {
   return cus;
 }
 
-template <class K, bool PAIRS, int NT, int IT>
+template <class K, bool PAIRS, int NT, int IT, int NSUB>
 hipError_t launch_one(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, hipStream_t s) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_partition<K, PAIRS, NT, IT>, NT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_partition<K, PAIRS, NT, IT, NSUB>, NT, 0) !=
+            hipSuccess ||
         nb <= 0)
       nb = 1;
     per_cu = nb;
@@ -270,7 +456,7 @@ hipError_t launch_one(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, h
   uint64_t grid = static_cast<uint64_t>(per_cu) * device_cus();
   if (grid > ntiles) grid = ntiles;
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_partition<K, PAIRS, NT, IT>), dim3(static_cast<uint32_t>(grid)), dim3(NT), 0, s, c, parity,
+  hipLaunchKernelGGL((k_partition<K, PAIRS, NT, IT, NSUB>), dim3(static_cast<uint32_t>(grid)), dim3(NT), 0, s, c, parity,
                      src);
   return hipGetLastError();
 }
@@ -278,9 +464,13 @@ hipError_t launch_one(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, h
 template <class K, bool PAIRS>
 hipError_t launch_tiles(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, hipStream_t s) {
   switch (c.tile) {
-    case 1024: return launch_one<K, PAIRS, 256, 4>(c, parity, ntiles, src, s);
-    case 2048: return launch_one<K, PAIRS, 256, 8>(c, parity, ntiles, src, s);
-    case 4096: return launch_one<K, PAIRS, 256, 16>(c, parity, ntiles, src, s);
+    case 1024: return launch_one<K, PAIRS, 256, 4, 1>(c, parity, ntiles, src, s);
+    case 2048: return launch_one<K, PAIRS, 256, 8, 1>(c, parity, ntiles, src, s);
+    case 4096: return launch_one<K, PAIRS, 256, 16, 1>(c, parity, ntiles, src, s);
+    case 8192: return launch_one<K, PAIRS, 256, 8, 4>(c, parity, ntiles, src, s);
+    case 16384: return launch_one<K, PAIRS, 256, 8, 8>(c, parity, ntiles, src, s);
+    case 32768: return launch_one<K, PAIRS, 256, 8, 16>(c, parity, ntiles, src, s);
+    case 65536: return launch_one<K, PAIRS, 256, 16, 16>(c, parity, ntiles, src, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -96,12 +96,25 @@ __global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), to_heap ? size : 0);
 }
 
-// Pivot choice for every live segment: Tukey's ninther over the triples
-// (first, mid, last), (first+1, mid-1, last-1), (first+2, mid+1, last-2);
-// after a bad partition the first/last candidates come from around the 25%
-// and 75% points instead (Sections 2 and 4.2). Then the predecessor rule of
-// Section 3 selects partition_left when the predecessor is not below the
-// pivot.
+// SplitMix64 finaliser (Steele, Lea and Flood, 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Pivot choice for every live segment: Tukey's ninther, the median of the
+// medians of three triples (Section 2). Normally the triples are (first,
+// mid, last), (first+1, mid-1, last-1), (first+2, mid+1, last-2). After a
+// bad partition the segment takes fresh candidates (Section 4.2) at nine
+// positions drawn from a counter-based hash of (seed, begin, end) -- the
+// randomised form of the fresh-candidate rule. The fixed 25%/75% positions
+// of the deterministic form are not used here: a stable out-of-place
+// partition keeps periodic input structure intact, so fixed offsets can
+// keep landing on equally bad candidates pass after pass. Then the
+// predecessor rule of Section 3 selects partition_left when the predecessor
+// is not below the pivot.
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32_t nseg, uint32_t src) {
   using T = typename K::T;
@@ -117,10 +130,13 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   Seg* sp = &c.segs[parity][i];
   const uint64_t b = sp->begin, e = sp->end;
   const uint64_t size = e - b;
-  const bool fresh = (sp->flags & kSegFresh) != 0;
-  const uint64_t q = fresh ? size / 4 : 0;
   const uint64_t m = size / 2;
-  const uint64_t off[9] = {q, m, size - 1 - q, q + 1, m - 1, size - 2 - q, q + 2, m + 1, size - 3 - q};
+  uint64_t off[9] = {0, m, size - 1, 1, m - 1, size - 2, 2, m + 1, size - 3};
+  if (sp->flags & kSegFresh) {
+    const uint64_t h0 = mix64(c.seed ^ mix64(b ^ mix64(e)));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) off[k] = mix64(h0 + static_cast<uint64_t>(k)) % size;
+  }
   const T* keys = static_cast<const T*>(c.keys[src]);
   T raw[9];
 #pragma unroll

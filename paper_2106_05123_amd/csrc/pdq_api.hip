@@ -28,7 +28,7 @@ thread_local int g_last_hip = 0;
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kMinTile = 1024;
-constexpr uint32_t kDefaultTile = 4096;
+constexpr uint32_t kDefaultTile = 32768;
 constexpr uint32_t kMaxPasses = 20000;  // far above any reachable pass count; a guard against bugs
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -73,6 +73,7 @@ struct Opts {
   uint32_t flags = 0;
   int32_t force_budget = -1;
   uint32_t tile = 0;
+  uint64_t seed = 0;
 };
 
 int read_opts(const pdq_options* o, Opts* out) {
@@ -83,8 +84,11 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, flags) + sizeof(uint32_t)) out->flags = o->flags;
   if (sz >= offsetof(pdq_options, force_budget) + sizeof(int32_t)) out->force_budget = o->force_budget;
   if (sz >= offsetof(pdq_options, tile) + sizeof(uint32_t)) out->tile = o->tile;
+  if (sz >= offsetof(pdq_options, seed) + sizeof(uint64_t)) out->seed = o->seed;
   if (out->flags & ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE)) return PDQ_ERR_UNSUPPORTED;
-  if (out->tile != 0 && out->tile != 1024 && out->tile != 2048 && out->tile != 4096) return PDQ_ERR_UNSUPPORTED;
+  if (out->tile != 0 && out->tile != 1024 && out->tile != 2048 && out->tile != 4096 && out->tile != 8192 &&
+      out->tile != 16384 && out->tile != 32768 && out->tile != 65536)
+    return PDQ_ERR_UNSUPPORTED;
   return PDQ_OK;
 }
 
@@ -176,6 +180,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.key_type = static_cast<uint32_t>(kt);
   c.has_vals = vals ? 1u : 0u;
   c.single = offsets ? 0u : 1u;
+  c.seed = o.seed;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool prof = (o.flags & PDQ_PROFILE) && st;

@@ -95,6 +95,8 @@ struct Ctx {
   uint32_t key_type;
   uint32_t has_vals;
   uint32_t single;      // 1: one segment [0, n) (records the first partition)
+  uint32_t pad0_;
+  uint64_t seed;        // seeds the candidate positions taken after a bad partition
 };
 
 // ---- key traits: canonical unsigned image in registers only ---------------

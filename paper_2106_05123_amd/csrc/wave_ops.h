@@ -63,6 +63,17 @@ __device__ __forceinline__ void wave_add(unsigned long long* ctr, uint64_t v) {
   if (lane_id() == 0 && s != 0) atomicAdd(ctr, static_cast<unsigned long long>(s));
 }
 
+// Workgroup barrier that orders LDS only. __syncthreads() also fences
+// global memory, which on this target waits for every outstanding global
+// load and store of the wave; the partition kernel keeps loads and stores in
+// flight across its barriers, and its barriers only hand LDS data between
+// waves.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Agent-scope relaxed loads/stores for the look-back status words: the
 // value travels inside the word, so no ordering of other memory is needed,
 // only visibility across the chip.

@@ -86,7 +86,7 @@ def test_sizes_and_key_types(kt, n):
     assert np.array_equal(as_bytes(out), as_bytes(ref))
 
 
-@pytest.mark.parametrize("tile", [1024, 2048, 4096])
+@pytest.mark.parametrize("tile", [1024, 2048, 4096, 8192, 16384, 32768, 65536])
 @pytest.mark.parametrize("pattern", ["random", "organ_pipe", "sawtooth"])
 def test_tile_sizes_same_keys(tile, pattern):
     a = W.pattern_i32(pattern, (1 << 21) + 12345, seed=3, period=1 << 9)
