@@ -185,7 +185,7 @@ def main():
         "dtype": "i32",
         "data": "synthetic",
         "config": {"workload": f"pdq_sort of 2^{args.log2n} int32 keys, uniform random (seed 0), keys only",
-                   "n": n, "key_type": "i32", "pattern": "random", "tile": args.tile or 4096,
+                   "n": n, "key_type": "i32", "pattern": "random", "tile": args.tile or 32768,
                    "passes": s0["passes"], "element_visits": s0["element_visits"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

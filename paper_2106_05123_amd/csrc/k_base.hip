@@ -1,135 +1,263 @@
 // LDS-resident base case: every segment of at most 4096 keys is sorted by
-// one workgroup in LDS and written to its final place in the user buffer.
+// one workgroup and written to its final place in the user buffer.
 //
 // The paper sorts small subsequences with insertion sort (Section 5.1) and
 // notes that sorting networks lost on its CPU through code size (Section 2);
-// on a GPU a workgroup-wide bitonic network is the natural small sort. Each
-// key is paired with its index inside the segment, so padding entries
-// (index >= size) sort after every real key, including real maximal keys,
-// and payloads are fetched by index afterwards.
+// on a GPU a bitonic network is the natural small sort. Here a segment of
+// P = E * NT slots (padded to a power of two) is held E slots per lane in
+// registers. Slot index i = (wave << (e + 6)) | (lane << e) | r, so a
+// compare-exchange across index bit b runs
+//   b < e        inside one lane's registers,
+//   e <= b < e+6 across lanes with a lane-xor shuffle,
+//   b >= e+6     across waves through LDS.
+// Keys are compared on their canonical images; with a payload each key is
+// paired with its index in the segment, so equal keys stay distinguishable
+// and padding (index >= size) sorts after every real key. Payloads are
+// gathered by index at the end.
 #include "pdq_internal.h"
+#include "wave_ops.h"
 
 namespace pdq {
 namespace {
 
-constexpr int kBaseThreads = 256;
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-__device__ __forceinline__ uint32_t next_pow2(uint32_t x) { return x <= 1 ? 1u : 1u << (32 - __clz(x - 1)); }
+// (64-bit image, 32-bit index) pair for 64-bit keys with a payload.
+struct KV {
+  uint64_t k;
+  uint32_t i;
+};
 
-// 32-bit keys: (canonical key << 32 | index) sorts as one 64-bit integer.
-template <class K, bool PAIRS>
-__global__ __launch_bounds__(kBaseThreads) void k_base32(Ctx c) {
-  __shared__ uint64_t s[kBaseMax];
-  __shared__ uint32_t sv[PAIRS ? kBaseMax : 1];
-  const Item it = c.base[blockIdx.x];
-  const uint32_t len = static_cast<uint32_t>(it.end - it.begin);
-  const uint32_t P = next_pow2(len);
-  const uint32_t* in = static_cast<const uint32_t*>(c.keys[it.buf]) + it.begin;
-  const uint32_t* inv = PAIRS ? c.vals[it.buf] + it.begin : nullptr;
-  for (uint32_t j = threadIdx.x; j < P; j += kBaseThreads) {
-    if (j < len) {
-      s[j] = (static_cast<uint64_t>(K::ord(in[j])) << 32) | j;
-      if (PAIRS) sv[j] = inv[j];
-    } else {
-      s[j] = ~0ull;
-    }
+// How one sort slot is built, compared, moved across lanes and stored.
+template <class K, bool PAIRS, bool WIDE = (sizeof(typename K::T) == 8)>
+struct Slot;
+
+// 32-bit keys, no payload: the canonical image itself.
+template <class K>
+struct Slot<K, false, false> {
+  using V = uint32_t;
+  static constexpr int kLdsBytes = 4;
+  __device__ static V make(uint32_t raw, uint32_t) { return K::ord(raw); }
+  __device__ static V pad() { return 0xFFFFFFFFu; }
+  __device__ static bool lt(V a, V b) { return a < b; }
+  __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static uint32_t key(V v) { return K::inv(v); }
+  __device__ static uint32_t idx(V) { return 0; }
+  __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
+  __device__ static V ld(const unsigned char* s, int, int i) { return reinterpret_cast<const V*>(s)[i]; }
+};
+
+// 32-bit keys with payload: image in the high half, index in the low half.
+template <class K>
+struct Slot<K, true, false> {
+  using V = uint64_t;
+  static constexpr int kLdsBytes = 8;
+  __device__ static V make(uint32_t raw, uint32_t i) { return (static_cast<uint64_t>(K::ord(raw)) << 32) | i; }
+  __device__ static V pad() { return ~0ull; }
+  __device__ static bool lt(V a, V b) { return a < b; }
+  __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static uint32_t key(V v) { return K::inv(static_cast<uint32_t>(v >> 32)); }
+  __device__ static uint32_t idx(V v) { return static_cast<uint32_t>(v); }
+  __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
+  __device__ static V ld(const unsigned char* s, int, int i) { return reinterpret_cast<const V*>(s)[i]; }
+};
+
+// 64-bit keys, no payload: the canonical image itself.
+template <class K>
+struct Slot<K, false, true> {
+  using V = uint64_t;
+  static constexpr int kLdsBytes = 8;
+  __device__ static V make(uint64_t raw, uint32_t) { return K::ord(raw); }
+  __device__ static V pad() { return ~0ull; }
+  __device__ static bool lt(V a, V b) { return a < b; }
+  __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static uint64_t key(V v) { return K::inv(v); }
+  __device__ static uint32_t idx(V) { return 0; }
+  __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
+  __device__ static V ld(const unsigned char* s, int, int i) { return reinterpret_cast<const V*>(s)[i]; }
+};
+
+// 64-bit keys with payload: (image, index), stored as two LDS planes.
+template <class K>
+struct Slot<K, true, true> {
+  using V = KV;
+  static constexpr int kLdsBytes = 12;
+  __device__ static V make(uint64_t raw, uint32_t i) { return KV{K::ord(raw), i}; }
+  __device__ static V pad() { return KV{~0ull, 0xFFFFFFFFu}; }
+  __device__ static bool lt(V a, V b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
+  __device__ static V xch(V a, int m) { return KV{__shfl_xor(a.k, m, 64), static_cast<uint32_t>(__shfl_xor(a.i, m, 64))}; }
+  __device__ static uint64_t key(V v) { return K::inv(v.k); }
+  __device__ static uint32_t idx(V v) { return v.i; }
+  // a plane of `plane` keys, then a plane of `plane` indices
+  __device__ static void st(unsigned char* s, int plane, int i, V v) {
+    reinterpret_cast<uint64_t*>(s)[i] = v.k;
+    reinterpret_cast<uint32_t*>(s + 8 * plane)[i] = v.i;
   }
-  __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < P / 2; t += kBaseThreads) {
-        const uint32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-        const uint32_t hi = lo | j;
-        const bool up = (lo & k) == 0;
-        const uint64_t a = s[lo], b = s[hi];
-        if ((a > b) == up) {
-          s[lo] = b;
-          s[hi] = a;
+  __device__ static V ld(const unsigned char* s, int plane, int i) {
+    return KV{reinterpret_cast<const uint64_t*>(s)[i], reinterpret_cast<const uint32_t*>(s + 8 * plane)[i]};
+  }
+};
+
+// LDS slot of index i: one padding slot every E slots keeps the per-lane
+// strided accesses of the register layout off a single bank.
+template <int E>
+__device__ __forceinline__ int lds_pos(int i) {
+  if constexpr (E == 1) return i;
+  else return i + (i >> ilog2(E));
+}
+
+template <int P, int E>
+constexpr int lds_plane() {
+  return E == 1 ? P : P + P / E;
+}
+
+template <class S, int E, int NT>
+__device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh, int tid) {
+  using V = typename S::V;
+  constexpr int e = ilog2(E);
+  constexpr int p = ilog2(E * NT);
+  constexpr int PL = lds_plane<E * NT, E>();
+  const int lane = tid & 63;
+  const int base = tid << e;  // index of x[0]: (wave << (e+6)) | (lane << e)
+#pragma unroll
+  for (int kb = 1; kb <= p; ++kb) {
+#pragma unroll
+    for (int b = kb - 1; b >= 0; --b) {
+      if (b < e) {
+        // partners inside this lane's registers
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if (r & (1 << b)) continue;
+          const int r2 = r | (1 << b);
+          const bool up = (((base | r) >> kb) & 1) == 0;
+          const V a = x[r], c = x[r2];
+          const bool sw = S::lt(c, a) == up;  // out of order for this block's direction
+          x[r] = sw ? c : a;
+          x[r2] = sw ? a : c;
         }
+      } else if (b < e + 6) {
+        // partners in lane ^ m, same register
+        const int m = 1 << (b - e);
+        const bool lower = (lane & m) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool up = (((base | r) >> kb) & 1) == 0;
+          const V y = S::xch(x[r], m);
+          const bool take_min = lower == up;
+          const bool y_less = S::lt(y, x[r]);
+          x[r] = (y_less == take_min) ? y : x[r];
+        }
+      } else {
+        // partners in another wave: exchange through LDS
+#pragma unroll
+        for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>(base | r), x[r]);
+        __syncthreads();
+        const bool lower = ((base >> b) & 1) == 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool up = (((base | r) >> kb) & 1) == 0;
+          const V y = S::ld(sh, PL, lds_pos<E>((base | r) ^ (1 << b)));
+          const bool take_min = lower == up;
+          const bool y_less = S::lt(y, x[r]);
+          x[r] = (y_less == take_min) ? y : x[r];
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
-  }
-  uint32_t* out = static_cast<uint32_t*>(c.keys[0]) + it.begin;
-  uint32_t* outv = PAIRS ? c.vals[0] + it.begin : nullptr;
-  for (uint32_t j = threadIdx.x; j < len; j += kBaseThreads) {
-    const uint64_t x = s[j];
-    out[j] = K::inv(static_cast<uint32_t>(x >> 32));
-    if (PAIRS) outv[j] = sv[static_cast<uint32_t>(x)];
   }
 }
 
-// 64-bit keys: keys and indices in two arrays, compared lexicographically.
-template <class K, bool PAIRS>
-__global__ __launch_bounds__(kBaseThreads) void k_base64(Ctx c) {
-  __shared__ uint64_t s[kBaseMax];
-  __shared__ uint16_t si[kBaseMax];
-  __shared__ uint32_t sv[PAIRS ? kBaseMax : 1];
-  const Item it = c.base[blockIdx.x];
-  const uint32_t len = static_cast<uint32_t>(it.end - it.begin);
-  const uint32_t P = next_pow2(len);
-  const uint64_t* in = static_cast<const uint64_t*>(c.keys[it.buf]) + it.begin;
-  const uint32_t* inv = PAIRS ? c.vals[it.buf] + it.begin : nullptr;
-  for (uint32_t j = threadIdx.x; j < P; j += kBaseThreads) {
-    if (j < len) {
-      s[j] = K::ord(in[j]);
-      si[j] = static_cast<uint16_t>(j);
-      if (PAIRS) sv[j] = inv[j];
-    } else {
-      s[j] = ~0ull;
-      si[j] = static_cast<uint16_t>(j);
-    }
+// One workgroup per base-case segment of at most E * NT keys.
+template <class K, bool PAIRS, int E, int NT>
+__global__ __launch_bounds__(NT) void k_base(Ctx c, int cls) {
+  using T = typename K::T;
+  using S = Slot<K, PAIRS>;
+  using V = typename S::V;
+  constexpr int P = E * NT;
+  constexpr int PL = lds_plane<P, E>();
+  __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
+  const Item it = c.base[cls][blockIdx.x];
+  const int len = static_cast<int>(it.end - it.begin);
+  const int tid = threadIdx.x;
+  const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
+
+  // coalesced load into LDS, then each lane picks up its E consecutive slots
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int j = r * NT + tid;
+    S::st(sh, PL, lds_pos<E>(j), j < len ? S::make(in[j], static_cast<uint32_t>(j)) : S::pad());
   }
   __syncthreads();
-  for (uint32_t k = 2; k <= P; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t t = threadIdx.x; t < P / 2; t += kBaseThreads) {
-        const uint32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-        const uint32_t hi = lo | j;
-        const bool up = (lo & k) == 0;
-        const uint64_t a = s[lo], b = s[hi];
-        const uint16_t ia = si[lo], ib = si[hi];
-        const bool gt = a > b || (a == b && ia > ib);
-        if (gt == up) {
-          s[lo] = b;
-          s[hi] = a;
-          si[lo] = ib;
-          si[hi] = ia;
-        }
-      }
-      __syncthreads();
+  V x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
+  __syncthreads();
+
+  bitonic<S, E, NT>(x, sh, tid);
+
+  // back through LDS so that the final writes are coalesced
+#pragma unroll
+  for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
+  __syncthreads();
+  V y[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) y[r] = S::ld(sh, PL, lds_pos<E>(r * NT + tid));
+  T* out = static_cast<T*>(c.keys[0]) + it.begin;
+  if constexpr (PAIRS) {
+    // gather every payload before anything is written: the segment may be
+    // sorted in place, in the buffer the payloads are read from
+    const uint32_t* vin = c.vals[it.buf] + it.begin;
+    uint32_t pv[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int j = r * NT + tid;
+      pv[r] = j < len ? vin[S::idx(y[r])] : 0u;
     }
-  }
-  uint64_t* out = static_cast<uint64_t*>(c.keys[0]) + it.begin;
-  uint32_t* outv = PAIRS ? c.vals[0] + it.begin : nullptr;
-  for (uint32_t j = threadIdx.x; j < len; j += kBaseThreads) {
-    out[j] = K::inv(s[j]);
-    if (PAIRS) outv[j] = sv[si[j]];
+    __syncthreads();
+    uint32_t* vout = c.vals[0] + it.begin;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int j = r * NT + tid;
+      if (j < len) {
+        out[j] = S::key(y[r]);
+        vout[j] = pv[r];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int j = r * NT + tid;
+      if (j < len) out[j] = S::key(y[r]);
+    }
   }
 }
 
 template <class K, bool PAIRS>
-hipError_t launch_k(const Ctx& c, uint32_t nitems, hipStream_t s) {
-  if constexpr (sizeof(typename K::T) == 4)
-    hipLaunchKernelGGL((k_base32<K, PAIRS>), dim3(nitems), dim3(kBaseThreads), 0, s, c);
-  else
-    hipLaunchKernelGGL((k_base64<K, PAIRS>), dim3(nitems), dim3(kBaseThreads), 0, s, c);
+hipError_t launch_cls(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
+  switch (cls) {
+    case 0: hipLaunchKernelGGL((k_base<K, PAIRS, 1, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
+    case 1: hipLaunchKernelGGL((k_base<K, PAIRS, 4, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
+    case 2: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
+    case 3: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 128>), dim3(nitems), dim3(128), 0, s, c, cls); break;
+    case 4: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 256>), dim3(nitems), dim3(256), 0, s, c, cls); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template <class K>
-hipError_t launch_kp(const Ctx& c, uint32_t nitems, hipStream_t s) {
-  return c.has_vals ? launch_k<K, true>(c, nitems, s) : launch_k<K, false>(c, nitems, s);
+hipError_t launch_kp(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
+  return c.has_vals ? launch_cls<K, true>(c, cls, nitems, s) : launch_cls<K, false>(c, cls, nitems, s);
 }
 
 }  // namespace
 
-hipError_t launch_base(const Ctx& c, uint32_t nitems, hipStream_t s) {
+hipError_t launch_base(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
   switch (c.key_type) {
-    case 1: return launch_kp<KeyU32>(c, nitems, s);
-    case 2: return launch_kp<KeyI32>(c, nitems, s);
-    case 3: return launch_kp<KeyF32>(c, nitems, s);
-    case 4: return launch_kp<KeyU64>(c, nitems, s);
+    case 1: return launch_kp<KeyU32>(c, cls, nitems, s);
+    case 2: return launch_kp<KeyI32>(c, cls, nitems, s);
+    case 3: return launch_kp<KeyF32>(c, cls, nitems, s);
+    case 4: return launch_kp<KeyU64>(c, cls, nitems, s);
     default: return hipErrorInvalidValue;
   }
 }

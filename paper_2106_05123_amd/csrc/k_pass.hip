@@ -27,6 +27,13 @@ __device__ __forceinline__ void push_item(const Ctx& c, Item* list, uint32_t* ct
   }
 }
 
+// Append a base-case segment to the list of its size class.
+__device__ __forceinline__ void push_base(const Ctx& c, bool want, uint64_t b, uint64_t e, uint32_t buf) {
+  const int cls = want ? base_class(e - b) : -1;
+#pragma unroll
+  for (int k = 0; k < kBaseClasses; ++k) push_item(c, c.base[k], &c.ctr->nbase[k], cls == k, b, e, buf, 0u);
+}
+
 // Append a live segment to list `parity` and reserve its tile tickets.
 __device__ __forceinline__ void push_seg(const Ctx& c, int parity, bool want, uint64_t b, uint64_t e,
                                          uint32_t budget, uint32_t flags) {
@@ -88,7 +95,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
   push_seg(c, 0, big && budget > 0, b, e, budget, kSegLeftmost);
   const bool to_base = size >= 2 && !big;
   const bool to_heap = big && budget == 0;
-  push_item(c, c.base, &c.ctr->nbase, to_base, b, e, 0u, 0u);
+  push_base(c, to_base, b, e, 0u);
   push_item(c, c.heap, &c.ctr->nheap, to_heap, b, e, 0u, 0u);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? size : 0);
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c.ctr->list[parity ^ 1] = 0;
     c.ctr->elems[parity ^ 1] = 0;
-    c.ctr->nbase = 0;
+    for (int k = 0; k < kBaseClasses; ++k) c.ctr->nbase[k] = 0;
     c.ctr->nheap = 0;
     c.ctr->ncopy = 0;
   }
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uin
     const bool to_base = has && cs >= 1 && cs <= kBaseMax && !(cs == 1 && dst == 0);
     const bool to_heap = has && cs > kBaseMax && cbudget == 0;
     const bool to_live = has && cs > kBaseMax && cbudget > 0;
-    push_item(c, c.base, &c.ctr->nbase, to_base, cb, ce, dst, 0u);
+    push_base(c, to_base, cb, ce, dst);
     push_item(c, c.heap, &c.ctr->nheap, to_heap, cb, ce, dst, 0u);
     push_seg(c, parity ^ 1, to_live, cb, ce, cbudget, cflags);
     wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);

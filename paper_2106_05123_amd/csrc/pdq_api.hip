@@ -35,7 +35,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0, status = 0;
-  size_t base = 0, heap = 0, copy = 0, ctr = 0, total = 0;
+  size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
 };
 
@@ -59,7 +59,7 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
   L.segs1 = take(sizeof(Seg) * L.max_active);
   L.tilemap = take(4ull * L.max_tiles);
   L.status = take(8ull * L.max_tiles);
-  L.base = take(sizeof(Item) * L.max_items);
+  for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
   L.heap = take(sizeof(Item) * L.max_items);
   L.copy = take(sizeof(Item) * L.max_items);
   L.ctr = take(sizeof(Counters));
@@ -116,14 +116,16 @@ int read_counters(const Ctx& c, Counters* snap, hipStream_t s) {
   }
   const uint32_t nact0 = static_cast<uint32_t>(snap->list[0] >> 32), nact1 = static_cast<uint32_t>(snap->list[1] >> 32);
   if (nact0 > c.max_active || nact1 > c.max_active || static_cast<uint32_t>(snap->list[0]) > c.max_tiles ||
-      static_cast<uint32_t>(snap->list[1]) > c.max_tiles || snap->nbase > c.max_items ||
-      snap->nheap > c.max_items || snap->ncopy > c.max_items)
+      static_cast<uint32_t>(snap->list[1]) > c.max_tiles || snap->nheap > c.max_items || snap->ncopy > c.max_items)
     return PDQ_ERR_INVALID;
+  for (int k = 0; k < kBaseClasses; ++k)
+    if (snap->nbase[k] > c.max_items) return PDQ_ERR_INVALID;
   return PDQ_OK;
 }
 
 int finish_items(const Ctx& c, const Counters& snap, hipStream_t s) {
-  if (snap.nbase) HIP_TRY(launch_base(c, snap.nbase, s));
+  for (int k = 0; k < kBaseClasses; ++k)
+    if (snap.nbase[k]) HIP_TRY(launch_base(c, k, snap.nbase[k], s));
   if (snap.nheap) HIP_TRY(launch_heap(c, snap.nheap, s));
   if (snap.ncopy) HIP_TRY(launch_copy(c, snap.ncopy, s));
   return PDQ_OK;
@@ -166,7 +168,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.segs[1] = reinterpret_cast<Seg*>(base + L.segs1);
   c.tilemap = reinterpret_cast<uint32_t*>(base + L.tilemap);
   c.status = reinterpret_cast<uint64_t*>(base + L.status);
-  c.base = reinterpret_cast<Item*>(base + L.base);
+  for (int k = 0; k < kBaseClasses; ++k) c.base[k] = reinterpret_cast<Item*>(base + L.base[k]);
   c.heap = reinterpret_cast<Item*>(base + L.heap);
   c.copy = reinterpret_cast<Item*>(base + L.copy);
   c.ctr = reinterpret_cast<Counters*>(base + L.ctr);

@@ -8,6 +8,7 @@
 namespace pdq {
 
 constexpr uint32_t kBaseMax = 4096;     // segments of at most this many keys go to the LDS base case
+constexpr int kBaseClasses = 5;         // base-case size classes: <= 64, 256, 1024, 2048, 4096 keys
 constexpr uint32_t kWave = 64;          // CDNA wavefront width
 constexpr uint32_t kSegLeftmost = 1u;   // segment has no predecessor (Section 3)
 constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh candidates (Section 4.2)
@@ -55,7 +56,8 @@ struct Item {
 struct Counters {
   uint64_t list[2];        // per list parity: (segments << 32) | tiles
   uint64_t elems[2];       // per list parity: keys in the list
-  uint32_t nbase, nheap, ncopy, ticket;
+  uint32_t nbase[kBaseClasses];
+  uint32_t nheap, ncopy, ticket, pad1_;
   // statistics (accumulated over the call)
   uint64_t partitions_right, partitions_left, bad_partitions;
   uint64_t heap_segments, heap_elements;
@@ -81,7 +83,7 @@ struct Ctx {
   Seg* segs[2];         // live-segment lists, indexed by pass parity
   uint32_t* tilemap;    // ticket -> segment index
   uint64_t* status;     // ticket -> look-back status word
-  Item* base;
+  Item* base[kBaseClasses];
   Item* heap;
   Item* copy;
   Counters* ctr;
@@ -137,11 +139,16 @@ hipError_t launch_tilemap(const Ctx& c, int parity, uint32_t ntiles, hipStream_t
 hipError_t launch_partition(const Ctx& c, int parity, uint32_t ntiles, uint32_t src_buf, hipStream_t s);
 hipError_t launch_bookkeep(const Ctx& c, int parity, uint32_t nseg, uint32_t src_buf, uint32_t pass,
                            hipStream_t s);
-hipError_t launch_base(const Ctx& c, uint32_t nitems, hipStream_t s);
+hipError_t launch_base(const Ctx& c, int cls, uint32_t nitems, hipStream_t s);
 hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s);
 hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s);
 
 inline uint32_t key_bytes(uint32_t key_type) { return key_type == 4 ? 8u : 4u; }
+
+// Size class of a base-case segment of n keys (1 <= n <= kBaseMax).
+__host__ __device__ inline int base_class(uint64_t n) {
+  return n <= 64 ? 0 : n <= 256 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 3 : 4;
+}
 
 // Number of tile tickets a segment [b, e) takes: tiles are aligned to
 // multiples of `tile` in absolute index space.
