@@ -55,6 +55,26 @@ def time_sorts(pdq, torch, pristine, work, ws, steps: int, profile: bool, tile: 
     return ms, stats
 
 
+def profiled_traffic():
+    """HBM bytes per partition launch measured with rocprofv3 counters (see
+    profiles/), or None when the kernel source changed since."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "partition_i32_2p28_traffic.md")
+    src = os.path.join(ROOT, "paper_2106_05123_amd", "csrc", "k_partition.hip")
+    try:
+        fields = {}
+        for ln in open(prof):
+            if ":" in ln and not ln.startswith(("|", "#", "`")):
+                k, v = ln.split(":", 1)
+                fields[k.strip()] = v.strip()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if fields.get("kernel_source_sha256_16") != h:
+            return None
+        return int(fields["avg_hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,7 +150,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": profiled_traffic(),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "k_partition",
         "avg_launch_ms": round(part_ms / max(launches, 1), 4),
         "avg_launch_bytes": int(part_bytes / max(launches, 1)),
