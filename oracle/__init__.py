@@ -87,6 +87,9 @@ def lib():
         L.oracle_routine.restype = ctypes.c_int
         L.oracle_key_image.argtypes = [ctypes.c_int, ctypes.c_void_p]
         L.oracle_key_image.restype = ctypes.c_uint64
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.oracle_mlp_infer_f32.argtypes = [fp, fp, ctypes.c_size_t, ctypes.c_int, fp]
+        L.oracle_mlp_infer_f32.restype = None
         _lib = L
     return _lib
 

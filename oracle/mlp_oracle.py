@@ -1,0 +1,331 @@
+"""Oracle of the learned first pass: a 1 -> 32 -> 32 -> 1 ReLU MLP fitted to
+the CDF of a key sample with Adam, and the splitters and bins it induces.
+
+TEST INFRASTRUCTURE ONLY: the product path never imports this module.
+
+The paper has no learned component. Its Section 2 names multiway
+partitioning as the route pdqsort did not take; this is the project's
+multiway first pass in that spirit: one histogram pass and one scatter into
+up to 511 bins replace the top eight levels of binary partitioning. Every
+definition is written out plainly in numpy (float64 unless a function says
+float32), so that it can be read against this summary:
+
+  sample     position j = SplitMix64(seed ^ j) mod n, j < m, with replacement;
+             keys are taken as their order-preserving unsigned images
+  feature    of a sorted sample image v: a piecewise-linear log2
+             L(v) = e + (v - 2^e) / 2^e for v >= 1 with e = floor(log2 v),
+             L(0) = -1, scaled by the sample's min and max onto [0, 1]; or a
+             linear scaling (v - lo) / (hi - lo). The scaling whose sample is
+             closer to uniform (smaller max |x_j - (j + 1/2) / m|) is used.
+             Computed in float64 with correctly rounded operations only, then
+             rounded once to float32.
+  target     mid-rank CDF of each sample key, (first + last + 1) / (2 m) over
+             its run of equal keys
+  model      y = x + W3 . relu(W2 relu(W1 x + b1) + b2) + b3   (residual form)
+             1153 parameters: W1[32] b1[32] W2[32][32] (row v, column u) b2[32]
+             W3[32] b3
+  init       from SplitMix64(seed ^ (0x5EED0000 + i)) with a_i uniform in
+             [-1, 1): |W1| in [1, 4] with a random sign, each first-layer knot
+             -b1/W1 at a sample quantile of x, W2 ~ a * sqrt(6/32),
+             W3 ~ a * sqrt(6/32) / 8, b2 = 0.1, b3 = 0
+  loss       mean over the minibatch of (y - t)^2
+  optimiser  Adam (beta1 0.9, beta2 0.999, eps 1e-8), learning rate cosine
+             from lr0 to lr1 over S steps, minibatch positions
+             SplitMix64(seed ^ (0xBA7C0000 + step * B + i)) mod m
+  splitters  running maximum of the clamped float32 prediction over the
+             sorted sample; for k = 1..255 the first sample key whose running
+             maximum reaches k / 256; duplicates removed
+  bins       b = number of splitters <= key; equality bin 2b - 1 when
+             key == s[b - 1], range bin 2b otherwise (2u + 1 bins)
+
+Where a float32 result decides an integer (the splitters), the float32
+inference is the C routine oracle_mlp_infer_f32 (pdq_oracle.cpp), which
+evaluates every dot product as a chain of fused multiply-adds in index order.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+H = 32
+NPARAM = H + H + H * H + H + H + 1  # 1153
+OFF_W1, OFF_B1, OFF_W2, OFF_B2, OFF_W3, OFF_B3 = 0, 32, 64, 64 + 1024, 64 + 1024 + 32, 64 + 1024 + 64
+NSPLIT = 255
+BETA1, BETA2, EPS = 0.9, 0.999, 1e-8
+LR0, LR1 = 1e-2, 1e-4
+SALT_INIT = 0x5EED0000
+SALT_BATCH = 0xBA7C0000
+
+M64 = (1 << 64) - 1
+
+
+# ----------------------------------------------------------------- random numbers
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output function applied to x (Steele, Lea, Flood 2014)."""
+    z = (x + 0x9E3779B97F4A7C15) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def splitmix64_np(x) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = np.asarray(x).astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def sample_positions(seed: int, m: int, n: int) -> np.ndarray:
+    j = np.arange(m, dtype=np.uint64)
+    return (splitmix64_np(np.uint64(seed) ^ j) % np.uint64(n)).astype(np.int64)
+
+
+def batch_positions(seed: int, step: int, batch: int, m: int) -> np.ndarray:
+    j = np.uint64(step) * np.uint64(batch) + np.arange(batch, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        h = splitmix64_np(np.uint64(seed) ^ (np.uint64(SALT_BATCH) + j))
+    return (h % np.uint64(m)).astype(np.int64)
+
+
+# ----------------------------------------------------------------- key images
+
+def key_images(keys: np.ndarray) -> np.ndarray:
+    """Order-preserving unsigned image of each key, as uint64."""
+    if keys.dtype == np.uint32 or keys.dtype == np.uint64:
+        return keys.astype(np.uint64)
+    if keys.dtype == np.int32:
+        return (keys.view(np.uint32) ^ np.uint32(0x80000000)).astype(np.uint64)
+    if keys.dtype == np.float32:
+        b = keys.view(np.uint32)
+        neg = (b >> np.uint32(31)) == 1
+        return np.where(neg, ~b, b | np.uint32(0x80000000)).astype(np.uint64)
+    raise TypeError(keys.dtype)
+
+
+# ----------------------------------------------------------------- features and targets
+
+def floor_log2_u64(v: np.ndarray) -> np.ndarray:
+    """Exact floor(log2 v) for v >= 1 (bit length - 1), by counting shifts."""
+    v = v.astype(np.uint64)
+    e = np.zeros(v.shape, dtype=np.int64)
+    for k in range(1, 64):
+        e += (v >> np.uint64(k)) > 0
+    return e
+
+
+def pseudo_log2(v: np.ndarray) -> np.ndarray:
+    """L(v) = e + (v - 2^e) / 2^e, L(0) = -1; float64 with one rounding in the
+    integer-to-float conversion and one in the final addition."""
+    v = v.astype(np.uint64)
+    out = np.full(v.shape, -1.0)
+    nz = v > 0
+    e = floor_log2_u64(v[nz])
+    d = (v[nz] - (np.uint64(1) << e.astype(np.uint64))).astype(np.float64)
+    out[nz] = np.ldexp(d, -e) + e.astype(np.float64)
+    return out
+
+
+def features(sorted_images: np.ndarray):
+    """Feature of each sorted sample image; returns (x float32, use_log)."""
+    v = sorted_images.astype(np.uint64)
+    m = v.size
+    lo, hi = v[0], v[-1]
+    if hi == lo:
+        return np.full(m, 0.5, dtype=np.float32), True
+    L = pseudo_log2(v)
+    xl = (L - L[0]) / (L[-1] - L[0])
+    xn = (v - lo).astype(np.float64) / np.float64(hi - lo)
+    ref = (np.arange(m, dtype=np.float64) + 0.5) / m
+    use_log = bool(np.max(np.abs(xl - ref)) <= np.max(np.abs(xn - ref)))
+    return (xl if use_log else xn).astype(np.float32), use_log
+
+
+def midrank_targets(sorted_keys: np.ndarray) -> np.ndarray:
+    """(first index + last index + 1) / (2 m) over each key's run of equals."""
+    m = sorted_keys.size
+    first = np.searchsorted(sorted_keys, sorted_keys, side="left")
+    last = np.searchsorted(sorted_keys, sorted_keys, side="right") - 1
+    return ((first + last + 1) / (2.0 * m)).astype(np.float32)
+
+
+# ----------------------------------------------------------------- model
+
+def unpack(p):
+    return (p[OFF_W1:OFF_B1], p[OFF_B1:OFF_W2], p[OFF_W2:OFF_B2].reshape(H, H), p[OFF_B2:OFF_W3],
+            p[OFF_W3:OFF_B3], p[OFF_B3])
+
+
+def init_params(seed: int, x_sorted: np.ndarray) -> np.ndarray:
+    """Initial float32 parameters. Every value is computed exactly in float64
+    and rounded once to float32."""
+    idx = np.arange(NPARAM, dtype=np.uint64)
+    h = splitmix64_np(np.uint64(seed) ^ (np.uint64(SALT_INIT) + idx))
+    a = (h >> np.uint64(40)).astype(np.float64) * 2.0 ** -23 - 1.0   # in [-1, 1), 24 bits
+    lim = np.float64(np.float32(math.sqrt(6.0 / H)))
+    p = np.zeros(NPARAM, dtype=np.float32)
+    w1 = np.where(a[OFF_W1:OFF_B1] >= 0, 1.0, -1.0) * (1.0 + 3.0 * np.abs(a[OFF_W1:OFF_B1]))
+    p[OFF_W1:OFF_B1] = w1.astype(np.float32)
+    m = x_sorted.size
+    q = x_sorted[((2 * np.arange(H) + 1) * m) // (2 * H)].astype(np.float64)
+    p[OFF_B1:OFF_W2] = (-(p[OFF_W1:OFF_B1].astype(np.float64) * q)).astype(np.float32)
+    p[OFF_W2:OFF_B2] = (a[OFF_W2:OFF_B2] * lim).astype(np.float32)
+    p[OFF_B2:OFF_W3] = np.float32(0.1)
+    p[OFF_W3:OFF_B3] = (a[OFF_W3:OFF_B3] * lim / 8.0).astype(np.float32)
+    p[OFF_B3] = 0.0
+    return p
+
+
+def forward(p: np.ndarray, x: np.ndarray, residual: bool = True):
+    """float64 forward pass; returns y and (z1, h1, z2, h2)."""
+    W1, b1, W2, b2, W3, b3 = unpack(p.astype(np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    z1 = np.outer(x, W1) + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ W2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    y = h2 @ W3 + b3
+    if residual:
+        y = y + x
+    return y, (z1, h1, z2, h2)
+
+
+def loss(p, x, t, residual: bool = True) -> float:
+    y, _ = forward(p, x, residual)
+    return float(np.mean((y - np.asarray(t, dtype=np.float64)) ** 2))
+
+
+def grad(p, x, t, residual: bool = True):
+    """Analytic gradient of the minibatch mean squared error (float64), by the
+    chain rule; the ReLU derivative is taken as 1 where its input is > 0."""
+    W1, b1, W2, b2, W3, b3 = unpack(p.astype(np.float64))
+    x = np.asarray(x, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    y, (z1, h1, z2, h2) = forward(p, x, residual)
+    B = x.size
+    dy = 2.0 * (y - t) / B
+    g = np.zeros(NPARAM, dtype=np.float64)
+    g[OFF_W3:OFF_B3] = h2.T @ dy
+    g[OFF_B3] = dy.sum()
+    dz2 = np.outer(dy, W3) * (z2 > 0)
+    g[OFF_W2:OFF_B2] = (dz2.T @ h1).ravel()
+    g[OFF_B2:OFF_W3] = dz2.sum(axis=0)
+    dz1 = (dz2 @ W2) * (z1 > 0)
+    g[OFF_W1:OFF_B1] = dz1.T @ x
+    g[OFF_B1:OFF_W2] = dz1.sum(axis=0)
+    return g, float(np.mean((y - t) ** 2))
+
+
+def numeric_grad(p, x, t, residual: bool = True, h: float = 1e-6) -> np.ndarray:
+    """Central finite differences of `loss` in float64."""
+    p64 = p.astype(np.float64)
+    g = np.zeros(NPARAM)
+    for i in range(NPARAM):
+        a = p64.copy()
+        b = p64.copy()
+        a[i] += h
+        b[i] -= h
+        g[i] = (loss(a, x, t, residual) - loss(b, x, t, residual)) / (2 * h)
+    return g
+
+
+def lr_at(step: int, steps: int, lr0: float = LR0, lr1: float = LR1) -> float:
+    """Cosine schedule: lr0 at step 1, lr1 at step `steps`."""
+    if steps <= 1:
+        return lr0
+    return lr1 + 0.5 * (lr0 - lr1) * (1.0 + math.cos(math.pi * (step - 1) / (steps - 1)))
+
+
+def adam_train(p0: np.ndarray, x: np.ndarray, t: np.ndarray, seed: int, steps: int, batch: int,
+               residual: bool = True):
+    """Adam from p0 over `steps` minibatches; returns (float32 params, losses)."""
+    p = p0.astype(np.float64)
+    mom = np.zeros(NPARAM)
+    vel = np.zeros(NPARAM)
+    losses = []
+    for s in range(1, steps + 1):
+        pos = batch_positions(seed, s, batch, x.size)
+        g, L = grad(p, x[pos], t[pos], residual)
+        losses.append(L)
+        mom = BETA1 * mom + (1 - BETA1) * g
+        vel = BETA2 * vel + (1 - BETA2) * g * g
+        mh = mom / (1 - BETA1 ** s)
+        vh = vel / (1 - BETA2 ** s)
+        p = p - lr_at(s, steps) * mh / (np.sqrt(vh) + EPS)
+    return p.astype(np.float32), np.array(losses)
+
+
+# ----------------------------------------------------------------- float32 inference (C)
+
+def infer_f32(p: np.ndarray, x: np.ndarray, residual: bool = True) -> np.ndarray:
+    """Clamped float32 prediction, fused multiply-adds in index order (C)."""
+    import oracle
+
+    lib = oracle.lib()
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty(x.size, dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.oracle_mlp_infer_f32(p.ctypes.data_as(fp), x.ctypes.data_as(fp), ctypes.c_size_t(x.size),
+                             ctypes.c_int(1 if residual else 0), y.ctypes.data_as(fp))
+    return y
+
+
+# ----------------------------------------------------------------- splitters and bins
+
+def splitters(sorted_images: np.ndarray, pred: np.ndarray, nsplit: int = NSPLIT) -> np.ndarray:
+    """Splitter k = first sample key whose running maximum of the clamped
+    float32 prediction reaches k / (nsplit + 1); duplicates removed."""
+    r = np.maximum.accumulate(np.clip(pred.astype(np.float32), np.float32(0), np.float32(1)))
+    out = []
+    for k in range(1, nsplit + 1):
+        thr = np.float32(k) / np.float32(nsplit + 1)
+        j = int(np.searchsorted(r, thr, side="left"))
+        if j < r.size:
+            out.append(sorted_images[j])
+    out = np.array(out, dtype=np.uint64)
+    if out.size:
+        out = out[np.concatenate([[True], out[1:] != out[:-1]])]
+    return out
+
+
+def bins_of(images: np.ndarray, split: np.ndarray) -> np.ndarray:
+    """Bin of every key image: range bin 2b, equality bin 2b - 1."""
+    images = images.astype(np.uint64)
+    split = split.astype(np.uint64)
+    b = np.searchsorted(split, images, side="right")
+    eq = np.zeros(images.size, dtype=bool)
+    nz = b > 0
+    eq[nz] = images[nz] == split[b[nz] - 1]
+    return np.where(eq, 2 * b - 1, 2 * b).astype(np.int64)
+
+
+def histogram(images: np.ndarray, split: np.ndarray) -> np.ndarray:
+    return np.bincount(bins_of(images, split), minlength=2 * split.size + 1).astype(np.uint64)
+
+
+def judge(hist: np.ndarray, n: int, limit: float = 2.0) -> bool:
+    """True when every range bin holds at most limit * n / 256 keys (equality
+    bins are final and are not judged)."""
+    return bool(np.all(hist[0::2].astype(np.float64) <= limit * n / 256.0))
+
+
+# ----------------------------------------------------------------- whole fit
+
+def fit(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, steps: int = 256, batch: int = 1024,
+        residual: bool = True):
+    """Sample, sort, features, targets, Adam, float32 inference, splitters.
+    Returns a dict of every intermediate."""
+    img = key_images(keys)
+    pos = sample_positions(seed, m, img.size)
+    samp = np.sort(img[pos])
+    x, use_log = features(samp)
+    t = midrank_targets(samp)
+    p0 = init_params(seed, x)
+    p, losses = adam_train(p0, x, t, seed, steps, batch, residual)
+    y = infer_f32(p, x, residual)
+    sp = splitters(samp, y)
+    return dict(sample=samp, x=x, use_log=use_log, t=t, p0=p0, params=p, losses=losses, pred=y, splitters=sp)

@@ -27,6 +27,7 @@
 // NaN is outside the contract). The comparison is done on a canonical
 // unsigned image of the key; stored bits are never altered.
 
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <cstddef>
@@ -616,6 +617,38 @@ uint64_t oracle_key_image(int key_type, const void* key) {
     case 3: return canon(*static_cast<const float*>(key));
     case 4: return canon(*static_cast<const uint64_t*>(key));
     default: return 0;
+  }
+}
+
+// Float32 prediction of the learned-splitter model (the numpy model in
+// mlp_oracle.py defines it; this is its float32 evaluation, used wherever a
+// float32 value decides an integer). Parameters: W1[32] b1[32] W2[32][32]
+// (row v, column u) b2[32] W3[32] b3. Every dot product is a chain of fused
+// multiply-adds in increasing index order, started from the bias; ReLU keeps
+// values > 0; the residual input x is added last; the result is clamped to
+// [0, 1].
+void oracle_mlp_infer_f32(const float* p, const float* x, size_t n, int residual, float* y) {
+  const float* W1 = p;
+  const float* b1 = p + 32;
+  const float* W2 = p + 64;
+  const float* b2 = p + 64 + 1024;
+  const float* W3 = p + 64 + 1024 + 32;
+  const float b3 = p[64 + 1024 + 64];
+  for (size_t i = 0; i < n; ++i) {
+    float h1[32], h2[32];
+    for (int u = 0; u < 32; ++u) {
+      const float z = std::fmaf(W1[u], x[i], b1[u]);
+      h1[u] = z > 0.0f ? z : 0.0f;
+    }
+    for (int v = 0; v < 32; ++v) {
+      float acc = b2[v];
+      for (int u = 0; u < 32; ++u) acc = std::fmaf(W2[v * 32 + u], h1[u], acc);
+      h2[v] = acc > 0.0f ? acc : 0.0f;
+    }
+    float out = b3;
+    for (int v = 0; v < 32; ++v) out = std::fmaf(W3[v], h2[v], out);
+    if (residual) out = out + x[i];
+    y[i] = out < 0.0f ? 0.0f : (out > 1.0f ? 1.0f : out);
   }
 }
 
