@@ -1,16 +1,24 @@
 """Benchmark of the MI355X partition sort (one JSON line on stdout).
 
-Workload: pdq_sort of 2^28 int32 keys (keys only), uniform random, seed 0 --
-the plain GPU partition-sort configuration. A step is one full sort (every
-pass of the hot path) of a fresh copy of the input already resident in HBM;
-the device-to-device reset copy before each step is outside the HIP events
-that time the sort. Also reported:
+Workload: pdq_sort of 2^28 uint32 keys drawn uniformly from [0, 2^32), seed
+0, keys only, in two forms on the same input: the plain partition sort, and
+the sort with the learned multiway first pass (PDQ_LEARNED: sample, fused MLP
+training, splitters, histogram, scatter into up to 511 bins, then partition
+passes inside the bins). `value` is the learned form; the plain form is
+reported beside it. A step is one full sort of a fresh copy of the input
+already resident in HBM; the device-to-device reset copy before each step is
+outside the HIP events that time the sort, and both forms' outputs are
+checked (sorted, same sum) before timing.
+
+Also reported:
   * roofline: the partition kernel's algorithmic bytes (read + write of every
-    key it partitions, 8 B/key for 32-bit keys) divided by its launch
-    durations, measured by the library with HIP events on the launch stream
-    over the timed steps, against the 8 TB/s HBM peak; the first pass (one
-    2^28-key segment) separately;
-  * patterns: keys/s for each of the seven input patterns;
+    key it partitions: 8 B/key for 32-bit keys) over its launch durations,
+    timed by the library with HIP events on the launch stream during the
+    timed steps of the learned form, against the 8 TB/s HBM peak; the
+    histogram and scatter kernels of the learned pass, and the plain form's
+    partition kernel and first pass, beside it;
+  * patterns: keys/s of both forms on 2^28 int32 keys in the seven input
+    patterns;
   * cpu_baseline: the oracle (single-threaded CPU pdqsort) on a bounded
     sample of the same input, timed on this host.
 
@@ -19,6 +27,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -37,7 +46,7 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_sorts(pdq, torch, pristine, work, ws, steps: int, profile: bool, tile: int = 0):
+def time_sorts(pdq, torch, pristine, work, ws, steps: int, profile: bool, **kw):
     """Returns (list of sort ms, list of stats dicts)."""
     ms, stats = [], []
     stream = torch.cuda.current_stream()
@@ -46,13 +55,21 @@ def time_sorts(pdq, torch, pristine, work, ws, steps: int, profile: bool, tile: 
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        st = pdq.sort_(work, workspace=ws, profile=profile, tile=tile)
+        st = pdq.sort_(work, workspace=ws, profile=profile, **kw)
         b.record(stream)
         b.synchronize()
         ms.append(a.elapsed_time(b))
         if st is not None:
             stats.append(st)
     return ms, stats
+
+
+def check_sorted(torch, work, pristine, what):
+    w = work.to(torch.int64)  # torch has no device comparison for uint32
+    ok = bool((w[1:] >= w[:-1]).all().item()) and int(w.sum()) == int(pristine.to(torch.int64).sum())
+    del w
+    if not ok:
+        raise SystemExit(f"bench: {what} output is not a sorted permutation of the input")
 
 
 def profiled_traffic():
@@ -73,6 +90,41 @@ def profiled_traffic():
         return int(fields["avg_hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def summarize(ms, stats, n):
+    s0 = stats[0]
+    part_ms = sum(s["partition_ms"] for s in stats)
+    part_bytes = sum(s["partition_bytes"] for s in stats)
+    launches = sum(s["partition_launches"] for s in stats)
+    out = {
+        "keys/s": round(n / (float(np.mean(ms)) * 1e-3), 0),
+        "ms": round(float(np.mean(ms)), 4),
+        "ms_min": round(float(np.min(ms)), 4),
+        "passes": s0["passes"],
+        "element_visits": s0["element_visits"],
+        "partition_ms": round(part_ms / len(stats), 4),
+        "partition_GBps": round(part_bytes / (part_ms * 1e-3) / 1e9, 1) if part_ms > 0 else None,
+        "partition_launches_per_sort": launches // len(stats),
+        "partition_bytes_per_sort": part_bytes // len(stats),
+    }
+    if s0.get("learned", 0):
+        out["learned_state"] = s0["learned"]
+    if s0.get("learned", 0) == 1:
+        fit = float(np.mean([s["learned_fit_ms"] for s in stats]))
+        hist = float(np.mean([s["learned_hist_ms"] for s in stats]))
+        scat = float(np.mean([s["learned_scatter_ms"] for s in stats]))
+        out.update({
+            "fit_ms": round(fit, 4),
+            "hist_ms": round(hist, 4),
+            "hist_GBps": round(s0["learned_hist_bytes"] / (hist * 1e-3) / 1e9, 1),
+            "scatter_ms": round(scat, 4),
+            "scatter_GBps": round(s0["learned_scatter_bytes"] / (scat * 1e-3) / 1e9, 1),
+            "splitters": s0["learned_splitters"],
+            "max_range_bin_over_fair": round(s0["learned_max_range_bin"] / (n / 256), 3),
+            "final_loss": s0["learned_final_loss"],
+        })
+    return out, part_ms, part_bytes, launches
 
 
 def main():
@@ -99,40 +151,41 @@ def main():
 
     dev = torch.device("cuda:0")
     n = 1 << args.log2n
-    log(f"generating {n} int32 keys")
-    host = W.pattern_i32("random", n, seed=0)
+    log(f"generating {n} uint32 keys")
+    host = W.uniform_u32(n, seed=0)
     pristine = torch.from_numpy(host).to(dev)
     work = torch.empty_like(pristine)
-    ws = torch.empty(pdq.workspace_bytes(n, 1, "i32"), dtype=torch.uint8, device=dev)
+    lopt = pdq.Options(ctypes.sizeof(pdq.Options), pdq.FLAG_LEARNED, -1, args.tile, 0, 0.0, 0, 0, 0)
+    ws = torch.empty(pdq.workspace_bytes(n, 1, "u32", options=lopt), dtype=torch.uint8, device=dev)
 
-    # check once that the timed configuration sorts correctly (sortedness + sum)
-    work.copy_(pristine)
-    pdq.sort_(work, workspace=ws, tile=args.tile)
-    torch.cuda.synchronize()
-    ok = bool((work[1:] >= work[:-1]).all().item()) and int(work.sum(dtype=torch.int64)) == int(
-        pristine.sum(dtype=torch.int64))
-    if not ok:
-        raise SystemExit("bench: GPU output is not a sorted permutation of the input")
+    forms = {"plain": dict(tile=args.tile), "learned": dict(tile=args.tile, learned=True)}
+    results = {}
+    for name, kw in forms.items():
+        work.copy_(pristine)
+        pdq.sort_(work, workspace=ws, **kw)
+        torch.cuda.synchronize()
+        check_sorted(torch, work, pristine, name)
+        log(f"{name}: warmup {args.warmup}")
+        time_sorts(pdq, torch, pristine, work, ws, args.warmup, profile=False, **kw)
+        torch.cuda.synchronize()
+        log(f"{name}: timing {args.steps} steps")
+        t0 = time.perf_counter()
+        ms, stats = time_sorts(pdq, torch, pristine, work, ws, args.steps, profile=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        results[name] = (ms, stats, wall)
 
-    log(f"warmup {args.warmup}")
-    time_sorts(pdq, torch, pristine, work, ws, args.warmup, profile=False, tile=args.tile)
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    ms, stats = time_sorts(pdq, torch, pristine, work, ws, args.steps, profile=True, tile=args.tile)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    ms, stats, wall = results["learned"]
+    learned, part_ms, part_bytes, launches = summarize(ms, stats, n)
+    plain, p_part_ms, p_part_bytes, p_launches = summarize(*results["plain"][:2], n)
+    p_stats = results["plain"][1]
     ms_step = float(np.mean(ms))
     value = n / (ms_step * 1e-3)
-
-    part_ms = sum(s["partition_ms"] for s in stats)
-    part_bytes = sum(s["partition_bytes"] for s in stats)
-    launches = sum(s["partition_launches"] for s in stats)
     achieved = part_bytes / (part_ms * 1e-3) / 1e9 if part_ms > 0 else 0.0
-    fp_ms = float(np.mean([s["first_pass_ms"] for s in stats]))
-    fp_bytes = stats[0]["first_pass_bytes"]
+    fp_ms = float(np.mean([s["first_pass_ms"] for s in p_stats]))
+    fp_bytes = p_stats[0]["first_pass_bytes"]
     fp_gbs = fp_bytes / (fp_ms * 1e-3) / 1e9
-    s0 = stats[0]
+
     # achievable ceiling on this machine: a device-to-device copy of the same bytes
     cms = []
     for _ in range(5):
@@ -156,26 +209,34 @@ def main():
         "avg_launch_ms": round(part_ms / max(launches, 1), 4),
         "avg_launch_bytes": int(part_bytes / max(launches, 1)),
         "launches": launches,
-        "first_pass": {"ms": round(fp_ms, 4), "bytes": int(fp_bytes), "GB/s": round(fp_gbs, 1),
-                       "frac": round(fp_gbs / HBM_PEAK_GBS, 4)},
         "partition_share_of_sort": round(part_ms / sum(ms), 3),
+        "learned_hist": {"GB/s": learned.get("hist_GBps"),
+                         "frac": round(learned["hist_GBps"] / HBM_PEAK_GBS, 4) if "hist_GBps" in learned else None},
+        "learned_scatter": {"GB/s": learned.get("scatter_GBps"),
+                            "frac": round(learned["scatter_GBps"] / HBM_PEAK_GBS, 4)
+                            if "scatter_GBps" in learned else None},
+        "plain_partition": {"GB/s": plain["partition_GBps"],
+                            "frac": round(plain["partition_GBps"] / HBM_PEAK_GBS, 4),
+                            "avg_launch_ms": round(p_part_ms / max(p_launches, 1), 4)},
+        "plain_first_pass": {"ms": round(fp_ms, 4), "bytes": int(fp_bytes), "GB/s": round(fp_gbs, 1),
+                             "frac": round(fp_gbs / HBM_PEAK_GBS, 4)},
         "copy_ceiling_GBps": round(copy_gbs, 1),
     }
 
     patterns = {}
     if not args.no_patterns:
         for p in W.C2_PATTERNS:
-            if p == "random":
-                patterns[p] = {"keys/s": round(value, 0), "ms": round(ms_step, 3), "passes": s0["passes"]}
-                continue
             log(f"pattern {p}")
             hp = W.pattern_i32(p, n, seed=0)
             pp = torch.from_numpy(hp).to(dev)
-            pms, pst = time_sorts(pdq, torch, pp, work, ws, args.pattern_steps, profile=True, tile=args.tile)
-            patterns[p] = {"keys/s": round(n / (np.mean(pms) * 1e-3), 0), "ms": round(float(np.mean(pms)), 3),
-                           "passes": pst[0]["passes"], "sorted_elements": pst[0]["sorted_elements"],
-                           "heapsort_elements": pst[0]["heapsort_elements"]}
-            del pp
+            wi = torch.empty_like(pp)  # int32 work buffer: the pattern keys are signed
+            row = {}
+            for name, kw in forms.items():
+                pms, pst = time_sorts(pdq, torch, pp, wi, ws, args.pattern_steps, profile=True, **kw)
+                row[name] = {"keys/s": round(n / (np.mean(pms) * 1e-3), 0), "ms": round(float(np.mean(pms)), 3),
+                             "passes": pst[0]["passes"], "learned_state": pst[0]["learned"]}
+            patterns[p] = row
+            del pp, wi
 
     cpu = None
     if not args.no_cpu:
@@ -187,7 +248,7 @@ def main():
         oracle.sort(sample)
         dt = time.perf_counter() - t1
         cpu = {"value": round(m / dt, 0), "unit": "keys/s", "cores": 1, "kind": "oracle",
-               "sample": f"first 2^{int(np.log2(m))} keys of the same int32 input, one single-threaded "
+               "sample": f"first 2^{int(np.log2(m))} keys of the same uint32 input, one single-threaded "
                          f"oracle sort ({dt:.2f} s)",
                "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
 
@@ -203,14 +264,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i32",
+        "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"pdq_sort of 2^{args.log2n} int32 keys, uniform random (seed 0), keys only",
-                   "n": n, "key_type": "i32", "pattern": "random", "tile": args.tile or 32768,
-                   "passes": s0["passes"], "element_visits": s0["element_visits"]},
+        "config": {"workload": f"pdq_sort with the learned first pass of 2^{args.log2n} uint32 keys, "
+                               f"uniform random (seed 0), keys only",
+                   "n": n, "key_type": "u32", "tile": args.tile or 32768},
+        "forms": {"learned": learned, "plain": plain,
+                  "learned_over_plain": round(plain["ms"] / learned["ms"], 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "patterns": patterns,
+        "patterns_i32": patterns,
     }
     print(json.dumps(line), flush=True)
 

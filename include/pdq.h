@@ -17,6 +17,13 @@
  *   - detection of already ordered segments (Section 5.2);
  *   - an LDS-resident base case for segments of at most 4096 keys
  *     (Section 5.1's small-case sort, as a sorting network).
+ * With PDQ_LEARNED a multiway first pass runs before the partition passes
+ * (the multiway partitioning Section 2 mentions as the road not taken): a
+ * small MLP fitted to the CDF of a key sample proposes up to 255
+ * splitters, one histogram pass judges the bins they induce, and one
+ * scatter splits the input into up to 511 bins; a bin holding too many keys
+ * sends the whole call back to the plain ninther path. The building blocks
+ * of that pass have entry points of their own in pdq_learned.h.
  *
  * Key order ("canonical order"): uint32 / uint64 as unsigned integers,
  * int32 as two's complement, float32 by the total order on its bit
@@ -50,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PDQ_ABI_VERSION 1
+#define PDQ_ABI_VERSION 2
 
 /* Largest segment that goes straight to the LDS base case. */
 #define PDQ_BASE_CASE_MAX 4096
@@ -76,7 +83,10 @@ enum pdq_status {
 
 enum pdq_flags {
   PDQ_VALIDATE = 1u << 0, /* check offsets on the device before sorting (synchronises) */
-  PDQ_PROFILE = 1u << 1   /* time every partition launch with HIP events (needs stats) */
+  PDQ_PROFILE = 1u << 1,  /* time every partition launch with HIP events (needs stats) */
+  PDQ_LEARNED = 1u << 2   /* learned multiway first pass (pdq_sort / pdq_sort_pairs with
+                             n > 65536; other calls ignore it); pass the same options to
+                             pdq_workspace_bytes */
 };
 
 typedef struct pdq_options {
@@ -84,7 +94,13 @@ typedef struct pdq_options {
   uint32_t flags;        /* pdq_flags */
   int32_t force_budget;  /* < 0: floor(log2 size) per segment (Section 4.1); >= 0: that budget */
   uint32_t tile;         /* keys per partition tile: 0 = auto (32768), else 1024 ... 65536, a power of two */
-  uint64_t seed;         /* seeds the hashed pivot candidates taken after a bad partition */
+  uint64_t seed;         /* seeds the hashed pivot candidates taken after a bad partition, and
+                            the sample, initial weights and minibatches of PDQ_LEARNED */
+  float learned_imbalance_limit; /* PDQ_LEARNED: fall back to the plain path when a range bin holds
+                                    more than limit * n / 256 keys; 0 = 2.0; < 0 = always fall back */
+  uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps, 0 = 256 (at most 65536) */
+  uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
+  uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */
@@ -110,10 +126,22 @@ typedef struct pdq_stats {
   uint64_t partition_bytes;       /* PDQ_PROFILE: algorithmic bytes moved by them (read + write) */
   double first_pass_ms;           /* PDQ_PROFILE: duration of the first partition launch */
   uint64_t first_pass_bytes;      /* PDQ_PROFILE: its algorithmic bytes */
+  uint32_t learned;               /* 0 not run, 1 learned first pass used, 2 judged and fell back */
+  uint32_t learned_splitters;     /* splitters after duplicates were removed */
+  uint64_t learned_max_range_bin; /* keys in the largest range bin */
+  uint64_t learned_equal_elements;/* keys retired in equality bins */
+  float learned_final_loss;       /* mean squared error of the last training step */
+  uint32_t learned_use_log;       /* 1: piecewise-linear log2 feature, 0: linear feature */
+  double learned_fit_ms;          /* PDQ_PROFILE: sample, sample sort, features, training, splitters */
+  double learned_hist_ms;         /* PDQ_PROFILE: histogram and scans */
+  double learned_scatter_ms;      /* PDQ_PROFILE: scatter into the bins */
+  uint64_t learned_hist_bytes;    /* PDQ_PROFILE: algorithmic bytes of the histogram pass */
+  uint64_t learned_scatter_bytes; /* PDQ_PROFILE: algorithmic bytes of the scatter */
 } pdq_stats;
 
-/* Bytes of device workspace needed for a call with these sizes. nseg is
- * the number of segments (1 for pdq_sort / pdq_sort_pairs). */
+/* Bytes of device workspace needed for a call with these sizes and options
+ * (PDQ_LEARNED and its learn_* fields enlarge it). nseg is the number of
+ * segments (1 for pdq_sort / pdq_sort_pairs). */
 size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has_vals,
                            const pdq_options* opt);
 

@@ -32,9 +32,11 @@ float32), so that it can be read against this summary:
   optimiser  Adam (beta1 0.9, beta2 0.999, eps 1e-8), learning rate cosine
              from lr0 to lr1 over S steps, minibatch positions
              SplitMix64(seed ^ (0xBA7C0000 + step * B + i)) mod m
-  splitters  running maximum of the clamped float32 prediction over the
-             sorted sample; for k = 1..255 the first sample key whose running
-             maximum reaches k / 256; duplicates removed
+  splitters  for k = 1..255: the sample key at index k m / 256 if it fills at
+             least m / 256 sample slots (a heavy key, which a smooth model
+             cannot isolate; it gets an equality bin), else the first sample
+             key whose running maximum of the clamped float32 prediction
+             reaches k / 256; sorted, duplicates removed
   bins       b = number of splitters <= key; equality bin 2b - 1 when
              key == s[b - 1], range bin 2b otherwise (2u + 1 bins)
 
@@ -277,19 +279,26 @@ def infer_f32(p: np.ndarray, x: np.ndarray, residual: bool = True) -> np.ndarray
 # ----------------------------------------------------------------- splitters and bins
 
 def splitters(sorted_images: np.ndarray, pred: np.ndarray, nsplit: int = NSPLIT) -> np.ndarray:
-    """Splitter k = first sample key whose running maximum of the clamped
-    float32 prediction reaches k / (nsplit + 1); duplicates removed."""
+    """Candidate k (k = 1..nsplit): the sample key at index q = floor(k m /
+    (nsplit + 1)) when that key fills at least m / (nsplit + 1) sample slots
+    (a heavy key: it gets an equality bin), else the first sample key whose
+    running maximum of the clamped float32 prediction reaches
+    k / (nsplit + 1), if any. Splitters: the sorted distinct candidates."""
+    m = sorted_images.size
     r = np.maximum.accumulate(np.clip(pred.astype(np.float32), np.float32(0), np.float32(1)))
+    first = np.searchsorted(sorted_images, sorted_images, side="left")
+    end = np.searchsorted(sorted_images, sorted_images, side="right")
     out = []
     for k in range(1, nsplit + 1):
+        q = (k * m) // (nsplit + 1)
+        if (end[q] - first[q]) * (nsplit + 1) >= m:
+            out.append(sorted_images[q])
+            continue
         thr = np.float32(k) / np.float32(nsplit + 1)
         j = int(np.searchsorted(r, thr, side="left"))
-        if j < r.size:
+        if j < m:
             out.append(sorted_images[j])
-    out = np.array(out, dtype=np.uint64)
-    if out.size:
-        out = out[np.concatenate([[True], out[1:] != out[:-1]])]
-    return out
+    return np.unique(np.array(out, dtype=np.uint64))
 
 
 def bins_of(images: np.ndarray, split: np.ndarray) -> np.ndarray:

@@ -11,6 +11,11 @@ built, every call raises.
     pdq.sort_(x)                      # in place, ascending
     pdq.sort_pairs_(keys, vals)       # vals: uint32 payload moved with keys (unstable)
     pdq.segmented_sort_(keys, offsets, vals=None)
+    pdq.sort_(x, learned=True)        # learned multiway first pass (include/pdq_learned.h)
+
+The learned pass's building blocks (MLP inference, gradient, fused trainer,
+features, splitter extraction, bin histogram, the whole fit) are bound
+one by one below with the names of their C entry points.
 """
 from __future__ import annotations
 
@@ -20,6 +25,8 @@ import os
 __all__ = [
     "PdqError", "Options", "Stats", "lib", "workspace_bytes", "sort_", "sort_pairs_",
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
+    "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
+    "learned_features", "learned_extract", "bucket_histogram", "learned_fit",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +35,10 @@ LIB_PATH = os.path.join(_HERE, "libpdq.so")
 PDQ_OK = 0
 FLAG_VALIDATE = 1
 FLAG_PROFILE = 2
+FLAG_LEARNED = 4
+MLP_PARAMS = 1153
+MAX_SPLITTERS = 255
+LEARN_SAMPLE = 65536
 KEY_TYPES = {"u32": 1, "i32": 2, "f32": 3, "u64": 4}
 
 
@@ -38,6 +49,10 @@ class Options(ctypes.Structure):
         ("force_budget", ctypes.c_int32),
         ("tile", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("learned_imbalance_limit", ctypes.c_float),
+        ("learn_steps", ctypes.c_uint32),
+        ("learn_batch", ctypes.c_uint32),
+        ("learn_grid", ctypes.c_uint32),
     ]
 
 
@@ -64,10 +79,26 @@ class Stats(ctypes.Structure):
         ("partition_bytes", ctypes.c_uint64),
         ("first_pass_ms", ctypes.c_double),
         ("first_pass_bytes", ctypes.c_uint64),
+        ("learned", ctypes.c_uint32),
+        ("learned_splitters", ctypes.c_uint32),
+        ("learned_max_range_bin", ctypes.c_uint64),
+        ("learned_equal_elements", ctypes.c_uint64),
+        ("learned_final_loss", ctypes.c_float),
+        ("learned_use_log", ctypes.c_uint32),
+        ("learned_fit_ms", ctypes.c_double),
+        ("learned_hist_ms", ctypes.c_double),
+        ("learned_scatter_ms", ctypes.c_double),
+        ("learned_hist_bytes", ctypes.c_uint64),
+        ("learned_scatter_bytes", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+
+
+class FitBuffers(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("d_sample", "d_x", "d_t", "d_pred", "d_params", "d_losses", "d_splitters", "d_count", "d_info")]
 
 
 class PdqError(RuntimeError):
@@ -105,6 +136,23 @@ def lib():
         L.pdq_last_hip_error.restype = ctypes.c_int
         L.pdq_abi_version.argtypes = []
         L.pdq_abi_version.restype = ctypes.c_int
+        i, u32, u64 = ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64
+        L.pdq_mlp_infer.argtypes = [vp, vp, sz, i, vp, vp]
+        L.pdq_mlp_gradient.argtypes = [vp, vp, vp, u32, i, vp, vp, vp]
+        L.pdq_mlp_train_workspace_bytes.argtypes = [u32]
+        L.pdq_mlp_train_workspace_bytes.restype = sz
+        L.pdq_mlp_train.argtypes = [vp, vp, sz, u64, u32, u32, u32, i, vp, vp, vp, vp, sz, vp]
+        L.pdq_learned_features.argtypes = [vp, sz, vp, vp, vp, vp]
+        L.pdq_learned_extract.argtypes = [vp, vp, sz, vp, vp, vp, vp]
+        L.pdq_bucket_workspace_bytes.argtypes = [sz]
+        L.pdq_bucket_workspace_bytes.restype = sz
+        L.pdq_bucket_histogram.argtypes = [vp, sz, i, vp, vp, vp, vp, sz, vp]
+        L.pdq_learned_fit_workspace_bytes.argtypes = [ctypes.POINTER(Options)]
+        L.pdq_learned_fit_workspace_bytes.restype = sz
+        L.pdq_learned_fit.argtypes = [vp, sz, i, vp, sz, vp, ctypes.POINTER(Options), ctypes.POINTER(FitBuffers)]
+        for f in ("pdq_mlp_infer", "pdq_mlp_gradient", "pdq_mlp_train", "pdq_learned_features",
+                  "pdq_learned_extract", "pdq_bucket_histogram", "pdq_learned_fit"):
+            getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -130,8 +178,10 @@ def _key_type(t) -> int:
     return m[t.dtype]
 
 
-def _options(force_budget: int, tile: int, flags: int) -> Options:
-    return Options(ctypes.sizeof(Options), flags, force_budget, tile, 0)
+def _options(force_budget: int, tile: int, flags: int, seed: int = 0, imbalance_limit: float = 0.0,
+             learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0) -> Options:
+    return Options(ctypes.sizeof(Options), flags, force_budget, tile, seed, imbalance_limit, learn_steps,
+                   learn_batch, learn_grid)
 
 
 def workspace_bytes(n: int, nseg: int = 1, key_type: int | str = "u32", has_vals: bool = False,
@@ -141,7 +191,7 @@ def workspace_bytes(n: int, nseg: int = 1, key_type: int | str = "u32", has_vals
                                          ctypes.byref(options) if options else None))
 
 
-def _prepare(keys, vals, nseg, force_budget, tile, flags, workspace):
+def _prepare(keys, vals, nseg, force_budget, tile, flags, workspace, learn=None):
     import torch
     if not keys.is_cuda:
         raise ValueError("keys must be a device tensor")
@@ -153,7 +203,7 @@ def _prepare(keys, vals, nseg, force_budget, tile, flags, workspace):
         if vals.numel() != keys.numel():
             raise ValueError("vals must have as many elements as keys")
     kt = _key_type(keys)
-    opt = _options(force_budget, tile, flags)
+    opt = _options(force_budget, tile, flags, **(learn or {}))
     need = workspace_bytes(keys.numel(), nseg, kt, vals is not None, opt)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
@@ -165,11 +215,20 @@ def _finish(st, want):
     return st.as_dict() if want else None
 
 
+def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid):
+    flags = FLAG_LEARNED if learned else 0
+    return flags, dict(seed=seed, imbalance_limit=imbalance_limit, learn_steps=learn_steps,
+                       learn_batch=learn_batch, learn_grid=learn_grid)
+
+
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
-          workspace=None):
-    """Sort a 1-D device tensor in place (ascending canonical order)."""
-    kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile, FLAG_PROFILE if profile else 0,
-                                         workspace)
+          workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
+          learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0):
+    """Sort a 1-D device tensor in place (ascending canonical order).
+    learned=True runs the learned multiway first pass (see pdq_learned.h)."""
+    lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
+    kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
+                                         (FLAG_PROFILE if profile else 0) | lf, workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
                         need, stream, ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
@@ -178,10 +237,12 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
 
 
 def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
-                stats: bool = False, workspace=None):
+                stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
+                imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0):
     """Sort keys in place and move the uint32 payload `vals` with them."""
-    kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile, FLAG_PROFILE if profile else 0,
-                                         workspace)
+    lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
+    kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
+                                         (FLAG_PROFILE if profile else 0) | lf, workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),
                               kt, 0, ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
@@ -208,3 +269,112 @@ def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: i
                                   ctypes.byref(st) if st is not None else None)
     _check(rc)
     return _finish(st, st is not None)
+
+
+# ---------------------------------------------------------------- learned pass, step by step
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_infer(params, x, residual: bool = True):
+    """float32 clamped prediction of the splitter model for features x."""
+    import torch
+    y = torch.empty_like(x)
+    _check(lib().pdq_mlp_infer(_ptr(params), _ptr(x), x.numel(), 1 if residual else 0, _ptr(y), _stream(x)))
+    return y
+
+
+def mlp_gradient(params, x, t, residual: bool = True):
+    """Gradient of the mean squared error over (x, t); returns (grad, loss)."""
+    import torch
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().pdq_mlp_gradient(_ptr(params), _ptr(x), _ptr(t), x.numel(), 1 if residual else 0, _ptr(g),
+                                  _ptr(loss), _stream(x)))
+    return g, loss
+
+
+def mlp_train(x, t, *, seed: int = 0, steps: int = 256, batch: int = 1024, grid: int = 16, residual: bool = True,
+              init=None):
+    """Fused Adam training on sorted features x and targets t; returns (params, losses)."""
+    import torch
+    p = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+    losses = torch.empty(steps, dtype=torch.float32, device=x.device)
+    need = int(lib().pdq_mlp_train_workspace_bytes(grid))
+    ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check(lib().pdq_mlp_train(_ptr(x), _ptr(t), x.numel(), seed, steps, batch, grid, 1 if residual else 0,
+                               _ptr(init), _ptr(p), _ptr(losses), _ptr(ws), need, _stream(x)))
+    return p, losses
+
+
+def learned_features(sorted_images):
+    """Features, targets and info words of a sorted uint64 sample of key images."""
+    import torch
+    m = sorted_images.numel()
+    x = torch.empty(m, dtype=torch.float32, device=sorted_images.device)
+    t = torch.empty_like(x)
+    info = torch.zeros(4, dtype=torch.uint64, device=sorted_images.device)
+    _check(lib().pdq_learned_features(_ptr(sorted_images), m, _ptr(x), _ptr(t), _ptr(info), _stream(x)))
+    return x, t, info
+
+
+def learned_extract(sorted_images, pred):
+    """Splitters (uint64 images) from clamped predictions of a sorted sample."""
+    import torch
+    dev = pred.device
+    r = torch.empty_like(pred)
+    sp = torch.zeros(MAX_SPLITTERS, dtype=torch.uint64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.uint32, device=dev)
+    _check(lib().pdq_learned_extract(_ptr(sorted_images), _ptr(pred), pred.numel(), _ptr(r), _ptr(sp), _ptr(cnt),
+                                     _stream(pred)))
+    u = int(cnt.cpu().item())
+    return sp[:u].clone(), r
+
+
+def bucket_histogram(keys, splitters):
+    """Keys per bin (2u + 1 bins) for sorted, distinct uint64 splitter images."""
+    import torch
+    dev = keys.device
+    u = splitters.numel()
+    sp = torch.zeros(MAX_SPLITTERS, dtype=torch.uint64, device=dev)
+    sp[:u] = splitters
+    cnt = torch.tensor([u], dtype=torch.uint32, device=dev)
+    hist = torch.zeros(512, dtype=torch.uint64, device=dev)
+    need = int(lib().pdq_bucket_workspace_bytes(keys.numel()))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().pdq_bucket_histogram(_ptr(keys), keys.numel(), _key_type(keys), _ptr(sp), _ptr(cnt), _ptr(hist),
+                                      _ptr(ws), need, _stream(keys)))
+    return hist[:2 * u + 1]
+
+
+def learned_fit(keys, *, seed: int = 0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0):
+    """The whole fit of the learned pass; returns a dict of device tensors."""
+    import torch
+    dev = keys.device
+    opt = _options(-1, 0, 0, seed=seed, learn_steps=learn_steps, learn_batch=learn_batch, learn_grid=learn_grid)
+    steps = learn_steps or 256
+    m = LEARN_SAMPLE
+    out = dict(sample=torch.empty(m, dtype=torch.uint64, device=dev),
+               x=torch.empty(m, dtype=torch.float32, device=dev),
+               t=torch.empty(m, dtype=torch.float32, device=dev),
+               pred=torch.empty(m, dtype=torch.float32, device=dev),
+               params=torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev),
+               losses=torch.empty(steps, dtype=torch.float32, device=dev),
+               splitters=torch.zeros(MAX_SPLITTERS, dtype=torch.uint64, device=dev),
+               count=torch.zeros(1, dtype=torch.uint32, device=dev),
+               info=torch.zeros(4, dtype=torch.uint64, device=dev))
+    fb = FitBuffers(*[_ptr(out[k]) for k in ("sample", "x", "t", "pred", "params", "losses", "splitters",
+                                             "count", "info")])
+    need = int(lib().pdq_learned_fit_workspace_bytes(ctypes.byref(opt)))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().pdq_learned_fit(_ptr(keys), keys.numel(), _key_type(keys), _ptr(ws), need, _stream(keys),
+                                 ctypes.byref(opt), ctypes.byref(fb)))
+    u = int(out["count"].cpu().item())
+    out["splitters"] = out["splitters"][:u]
+    return out

@@ -1,0 +1,288 @@
+// Histogram and scatter of the learned multiway first pass.
+//
+// A key with image v falls into bin 2b (range bin) or 2b - 1 (equality bin),
+// where b is the number of splitters <= v and the equality bin is taken when
+// v equals splitter b - 1. Range bins hold the keys strictly between two
+// consecutive splitters, so every key of bin i precedes every key of bin
+// i + 1; equality bins hold copies of one key and are final.
+//
+//   hist      per tile of 8192 keys: branchless binary search over the
+//             splitters in LDS, LDS bin counters, one row of 512 counts; and
+//             whether any adjacent pair ascends or descends (an ordered
+//             input is left to the plain path, which retires it in one pass)
+//   scan      chunk sums of 64 rows, one workgroup scanning the chunk sums
+//             (bin totals, bin starts), then each chunk rescans its rows into
+//             absolute per-tile offsets
+//   scatter   per tile: classify again, rank within the bin by an LDS atomic,
+//             stage the tile in LDS in bin order, write every bin's run
+//             contiguously to its offset
+#include "learn_internal.h"
+#include "pdq_internal.h"
+#include "wave_ops.h"
+
+namespace pdq {
+namespace {
+
+constexpr uint32_t kNT = kBucketThreads;
+constexpr uint32_t kPer = kBucketTile / kBucketThreads;  // keys per thread
+static_assert(kPer * kNT == kBucketTile, "tile must be a multiple of the workgroup");
+
+// The u sorted splitters in LDS, padded to 256 with the largest image, in the
+// key's own width (32-bit keys have 32-bit images). Entry i sits at
+// i + i / 2^kSkew: the probes of one search level are a power of two apart,
+// and the skew spreads them over distinct banks.
+template <class S>
+struct SplitTable {
+  static constexpr uint32_t kSkew = sizeof(S) == 8 ? 4 : 5;
+  S v[256 + (256 >> kSkew)];
+  __device__ __forceinline__ static uint32_t at(uint32_t i) { return i + (i >> kSkew); }
+  __device__ __forceinline__ S get(uint32_t i) const { return v[at(i)]; }
+};
+
+template <class S>
+__device__ __forceinline__ void load_splitters(SplitTable<S>& t, const BucketBufs& b, uint32_t& u) {
+  u = *b.count;
+  for (uint32_t i = threadIdx.x; i < 256; i += kNT) t.v[SplitTable<S>::at(i)] = i < u ? static_cast<S>(b.splitters[i]) : S(~S(0));
+}
+
+// Bin of a key image: branchless binary search for the number b of
+// splitters <= img (padding is clamped away), then the equality test.
+template <class S>
+__device__ __forceinline__ uint32_t bin_of(const SplitTable<S>& t, uint32_t u, S img) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t step = 128; step >= 1; step >>= 1)
+    if (t.get(pos + step - 1) <= img) pos += step;
+  const uint32_t bsel = pos < u ? pos : u;
+  const bool eq = bsel > 0 && t.get(bsel - 1) == img;
+  return eq ? 2 * bsel - 1 : 2 * bsel;
+}
+
+// Exclusive scan of s[0..512) in place by the 512 threads; returns the total.
+__device__ uint32_t block_exclusive_scan_512(uint32_t* s, uint32_t* s_wsum) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t v = s[tid];
+  uint32_t incl = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane >= static_cast<uint32_t>(d)) incl += t;
+  }
+  if (lane == 63) s_wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (uint32_t k = 0; k < kNT / 64; ++k) {
+    if (k < w) before += s_wsum[k];
+    total += s_wsum[k];
+  }
+  __syncthreads();
+  s[tid] = before + incl - v;
+  __syncthreads();
+  return total;
+}
+
+template <class K>
+__global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ keys, uint64_t n, BucketBufs b) {
+  using S = typename K::T;
+  __shared__ SplitTable<S> s_sp;
+  __shared__ uint32_t s_cnt[kBinStride];
+  __shared__ uint32_t s_order;
+  uint32_t u;
+  load_splitters(s_sp, b, u);
+  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) s_cnt[i] = 0;
+  if (threadIdx.x == 0) s_order = 0;
+  __syncthreads();
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBucketTile;
+  typename K::T v[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint64_t i = base + k * kNT + threadIdx.x;
+    v[k] = i < n ? keys[i] : typename K::T(0);
+  }
+  // order of adjacent pairs (i, i+1): the neighbour is the next lane's key,
+  // or for the last lane a load of its own
+  bool desc = false, asc = false;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint64_t i = base + k * kNT + threadIdx.x;
+    const S o = K::ord(v[k]);
+    if (i < n) atomicAdd(&s_cnt[bin_of(s_sp, u, o)], 1u);
+    typename K::T nx = __shfl_down(v[k], 1, 64);
+    if (lane_id() == 63 && i + 1 < n) nx = keys[i + 1];
+    if (i + 1 < n) {
+      const S on = K::ord(nx);
+      desc |= on < o;
+      asc |= on > o;
+    }
+  }
+  const uint32_t bits = (__ballot(desc) ? 1u : 0u) | (__ballot(asc) ? 2u : 0u);
+  if (bits && lane_id() == 0) atomicOr(&s_order, bits);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_order) atomicOr(b.order, s_order);
+  uint32_t* row = b.rows + static_cast<uint64_t>(blockIdx.x) * kBinStride;
+  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) row[i] = s_cnt[i];
+}
+
+// Sum of each bin over the rows of one chunk.
+__global__ __launch_bounds__(kBinStride) void k_chunk_sum(BucketBufs b) {
+  const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
+  const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
+  uint32_t sum = 0;
+  for (uint64_t r = r0; r < r1; ++r) sum += b.rows[r * kBinStride + threadIdx.x];
+  b.chunk[static_cast<uint64_t>(blockIdx.x) * kBinStride + threadIdx.x] = sum;
+}
+
+// One workgroup: chunk sums -> per-chunk exclusive offsets within each bin,
+// bin totals, and the start of every bin (exclusive scan over bins).
+__global__ __launch_bounds__(kBinStride) void k_chunk_scan(BucketBufs b) {
+  __shared__ uint32_t s_tot[kBinStride];
+  __shared__ uint32_t s_wsum[kBinStride / 64];
+  const uint32_t tid = threadIdx.x;
+  uint64_t run = 0;
+  for (uint64_t c = 0; c < b.nchunks; ++c) {
+    uint32_t* p = b.chunk + c * kBinStride + tid;
+    const uint32_t v = *p;
+    *p = static_cast<uint32_t>(run);
+    run += v;
+  }
+  b.totals[tid] = run;
+  s_tot[tid] = static_cast<uint32_t>(run);
+  __syncthreads();
+  const uint32_t total = block_exclusive_scan_512(s_tot, s_wsum);
+  b.begin[tid] = s_tot[tid];
+  if (tid == 0) b.begin[kBinStride] = total;
+}
+
+// Rows of one chunk -> absolute start of each (tile, bin) run.
+__global__ __launch_bounds__(kBinStride) void k_tile_rescan(BucketBufs b) {
+  const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
+  const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
+  uint32_t run = static_cast<uint32_t>(b.begin[threadIdx.x]) + b.chunk[static_cast<uint64_t>(blockIdx.x) * kBinStride + threadIdx.x];
+  for (uint64_t r = r0; r < r1; ++r) {
+    uint32_t* p = b.rows + r * kBinStride + threadIdx.x;
+    const uint32_t v = *p;
+    *p = run;
+    run += v;
+  }
+}
+
+template <class K, bool PAIRS>
+__global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict__ kin,
+                                                 const uint32_t* __restrict__ vin, typename K::T* __restrict__ kout,
+                                                 uint32_t* __restrict__ vout, uint64_t n, BucketBufs b) {
+  using T = typename K::T;
+  __shared__ SplitTable<T> s_sp;
+  __shared__ uint32_t s_loc[kBinStride];   // ranks, then local run starts
+  __shared__ uint32_t s_goff[kBinStride];  // global run starts of this tile
+  __shared__ uint32_t s_wsum[kNT / 64];
+  __shared__ T s_key[kBucketTile];
+  __shared__ uint16_t s_bin[kBucketTile];
+  __shared__ uint32_t s_val[PAIRS ? kBucketTile : 1];
+  uint32_t u;
+  load_splitters(s_sp, b, u);
+  const uint32_t* row = b.rows + static_cast<uint64_t>(blockIdx.x) * kBinStride;
+  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) {
+    s_loc[i] = 0;
+    s_goff[i] = row[i];
+  }
+  __syncthreads();
+  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBucketTile;
+  const uint32_t cnt = static_cast<uint32_t>(n - base < kBucketTile ? n - base : kBucketTile);
+  T v[kPer];
+  uint32_t pv[PAIRS ? kPer : 1];
+  uint32_t bin[kPer], rank[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = k * kNT + threadIdx.x;
+    v[k] = i < cnt ? kin[base + i] : T(0);
+    if constexpr (PAIRS) pv[k] = i < cnt ? vin[base + i] : 0u;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = k * kNT + threadIdx.x;
+    bin[k] = bin_of(s_sp, u, K::ord(v[k]));
+    rank[k] = i < cnt ? atomicAdd(&s_loc[bin[k]], 1u) : 0u;
+  }
+  __syncthreads();
+  block_exclusive_scan_512(s_loc, s_wsum);
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t i = k * kNT + threadIdx.x;
+    if (i < cnt) {
+      const uint32_t at = s_loc[bin[k]] + rank[k];
+      s_key[at] = v[k];
+      s_bin[at] = static_cast<uint16_t>(bin[k]);
+      if constexpr (PAIRS) s_val[at] = pv[k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cnt; i += kNT) {
+    const uint32_t bi = s_bin[i];
+    const uint64_t pos = static_cast<uint64_t>(s_goff[bi]) + (i - s_loc[bi]);
+    if (pos >= n) {  // histogram and scatter disagree: never write outside the output
+      atomicOr(b.errors, kErrScatter);
+      continue;
+    }
+    kout[pos] = s_key[i];
+    if constexpr (PAIRS) vout[pos] = s_val[i];
+  }
+}
+
+template <class K>
+struct HistL {
+  static hipError_t run(const void* keys, uint64_t n, const BucketBufs& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist<K>, dim3(static_cast<uint32_t>(b.ntiles)), dim3(kNT), 0, s,
+                       static_cast<const typename K::T*>(keys), n, b);
+    return hipGetLastError();
+  }
+};
+
+template <class K>
+struct ScatterL {
+  static hipError_t run(bool pairs, const void* kin, const uint32_t* vin, void* kout, uint32_t* vout, uint64_t n,
+                        const BucketBufs& b, hipStream_t s) {
+    using T = typename K::T;
+    if (pairs)
+      hipLaunchKernelGGL((k_scatter<K, true>), dim3(static_cast<uint32_t>(b.ntiles)), dim3(kNT), 0, s,
+                         static_cast<const T*>(kin), vin, static_cast<T*>(kout), vout, n, b);
+    else
+      hipLaunchKernelGGL((k_scatter<K, false>), dim3(static_cast<uint32_t>(b.ntiles)), dim3(kNT), 0, s,
+                         static_cast<const T*>(kin), vin, static_cast<T*>(kout), vout, n, b);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+__global__ void k_zero_word(uint32_t* p) { *p = 0; }
+
+hipError_t launch_bucket_hist(uint32_t kt, const void* keys, uint64_t n, const BucketBufs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, b.order);
+  switch (kt) {
+    case 1: return HistL<KeyU32>::run(keys, n, b, s);
+    case 2: return HistL<KeyI32>::run(keys, n, b, s);
+    case 3: return HistL<KeyF32>::run(keys, n, b, s);
+    case 4: return HistL<KeyU64>::run(keys, n, b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bucket_scan(const BucketBufs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_sum, dim3(static_cast<uint32_t>(b.nchunks)), dim3(kBinStride), 0, s, b);
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kBinStride), 0, s, b);
+  hipLaunchKernelGGL(k_tile_rescan, dim3(static_cast<uint32_t>(b.nchunks)), dim3(kBinStride), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket_scatter(uint32_t kt, bool pairs, const void* keys_in, const uint32_t* vals_in,
+                                 void* keys_out, uint32_t* vals_out, uint64_t n, const BucketBufs& b,
+                                 hipStream_t s) {
+  switch (kt) {
+    case 1: return ScatterL<KeyU32>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    case 2: return ScatterL<KeyI32>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    case 3: return ScatterL<KeyF32>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    case 4: return ScatterL<KeyU64>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pdq

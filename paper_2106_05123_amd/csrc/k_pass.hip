@@ -1,6 +1,7 @@
 // Per-pass control kernels of the partition sort: initial segment lists,
 // pivot choice, tile map, segment bookkeeping, and the finishing copies and
 // heapsort fallback.
+#include "learn_internal.h"
 #include "pdq_internal.h"
 #include "wave_ops.h"
 
@@ -103,12 +104,36 @@ __global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), to_heap ? size : 0);
 }
 
-// SplitMix64 finaliser (Steele, Lea and Flood, 2014).
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z += 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
+// After the learned multiway scatter the bins are contiguous ranges of the
+// scratch buffer, in key order. Range bins (even index) become leftmost
+// segments: their keys are strictly greater than every key before them, so
+// the predecessor rule would always pick partition_right anyway. Equality
+// bins (odd index) hold copies of one key and are copied out unchanged.
+__global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64_t* begin) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < static_cast<uint32_t>(kBinStride);
+  uint64_t b = 0, e = 0;
+  if (in) {
+    b = begin[i];
+    e = begin[i + 1];
+  }
+  const uint64_t size = e - b;
+  const bool eq = in && (i & 1u) && size > 0;
+  const bool range = in && !(i & 1u) && size > 0;
+  uint32_t budget = 0;
+  if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
+  const bool big = size > kBaseMax;
+  push_item(c, c.copy, &c.ctr->ncopy, eq, b, e, 1u, 0u);
+  push_seg(c, 0, range && big && budget > 0, b, e, budget, kSegLeftmost);
+  const bool to_base = range && !big;
+  const bool to_heap = range && big && budget == 0;
+  push_base(c, to_base, b, e, 1u);
+  push_item(c, c.heap, &c.ctr->nheap, to_heap, b, e, 1u, 0u);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? size : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), to_heap ? 1 : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), to_heap ? size : 0);
+  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->equal_elements), eq ? size : 0);
 }
 
 // Pivot choice for every live segment: Tukey's ninther, the median of the
@@ -419,6 +444,11 @@ hipError_t launch_reset(const Ctx& c, hipStream_t s) {
 
 hipError_t launch_init(const Ctx& c, hipStream_t s) {
   hipLaunchKernelGGL(k_init, dim3(blocks_for(c.nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket_init(const Ctx& c, const uint64_t* begin, hipStream_t s) {
+  hipLaunchKernelGGL(k_bucket_init, dim3(blocks_for(kBinStride, kCtlThreads)), dim3(kCtlThreads), 0, s, c, begin);
   return hipGetLastError();
 }
 

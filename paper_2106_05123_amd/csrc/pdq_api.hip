@@ -12,12 +12,21 @@
 // Keys ping-pong between the user buffer and a scratch buffer of the same
 // size inside the caller's workspace; everything that is final ends up in
 // the user buffer.
+//
+// With PDQ_LEARNED a single-range call first fits the splitter model on a
+// key sample, counts the keys per bin, and -- if no range bin is too full --
+// scatters the keys into their bins in the scratch buffer; the partition
+// passes then start from the scratch buffer with one segment per range bin.
 #include <stdint.h>
 #include <string.h>
 
 #include <vector>
 
+#include <math.h>
+
+#include "learn_internal.h"
 #include "pdq.h"
+#include "pdq_learned.h"
 #include "pdq_internal.h"
 
 namespace {
@@ -31,13 +40,84 @@ constexpr uint32_t kMinTile = 1024;
 constexpr uint32_t kDefaultTile = 32768;
 constexpr uint32_t kMaxPasses = 20000;  // far above any reachable pass count; a guard against bugs
 
+constexpr uint64_t kLearnSample = PDQ_LEARN_SAMPLE;
+constexpr uint32_t kMaxTrainGrid = 64;
+constexpr uint32_t kMaxLearnSteps = 65536;
+
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0, status = 0;
   size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
+  // learned first pass (zero sizes when not requested)
+  size_t fit_out = 0, fit_scratch = 0, bucket = 0;
 };
+
+// Offsets inside an area, built by the same bump allocator as the layout.
+struct Bump {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = (off + bytes + kAlign - 1) / kAlign * kAlign;
+    return o;
+  }
+};
+
+Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals);
+
+// Outputs of the fit (sample, features, targets, prediction, parameters,
+// losses, splitters, count, info).
+struct FitOutLayout {
+  size_t sample, x, t, y, params, losses, splitters, count, info, total;
+};
+FitOutLayout fit_out_layout(uint32_t steps) {
+  FitOutLayout f;
+  Bump b;
+  f.sample = b.take(kLearnSample * 8);
+  f.x = b.take(kLearnSample * 4);
+  f.t = b.take(kLearnSample * 4);
+  f.y = b.take(kLearnSample * 4);
+  f.params = b.take(kParamStride * 4);
+  f.losses = b.take(static_cast<size_t>(steps) * 4);
+  f.splitters = b.take(256 * 8);
+  f.count = b.take(4);
+  f.info = b.take(4 * 8);
+  f.total = b.off;
+  return f;
+}
+
+// Scratch of the fit: running maximum, gradient partials, barrier words, and
+// the unsorted sample.
+struct FitScratchLayout {
+  size_t runmax, partials, sync, raw, total;
+};
+FitScratchLayout fit_scratch_layout(uint32_t grid) {
+  FitScratchLayout f;
+  Bump b;
+  f.runmax = b.take(kLearnSample * 4);
+  f.partials = b.take(2ull * grid * kParamStride * 4);
+  f.sync = b.take(4 * 4);
+  f.raw = b.take(kLearnSample * 8);
+  f.total = b.off;
+  return f;
+}
+
+// Per-tile rows, chunk rows, bin totals and bin starts of the histogram.
+struct BucketLayout {
+  size_t rows, chunk, totals, begin, order, total;
+};
+BucketLayout bucket_layout(size_t n) {
+  BucketLayout L;
+  Bump b;
+  L.rows = b.take(bucket_tiles(n) * kBinStride * 4);
+  L.chunk = b.take(bucket_chunks(n) * kBinStride * 4);
+  L.totals = b.take(kBinStride * 8);
+  L.begin = b.take((kBinStride + 1) * 8);
+  L.order = b.take(4);
+  L.total = b.off;
+  return L;
+}
 
 Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
   Layout L;
@@ -67,6 +147,20 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
   return L;
 }
 
+Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool learned, uint32_t steps, uint32_t grid) {
+  Layout L = make_layout(n, nseg, kt, vals);
+  if (!learned) return L;
+  size_t off = L.total - kAlign;
+  L.fit_out = off;
+  off += fit_out_layout(steps).total;
+  L.fit_scratch = off;
+  off += fit_scratch_layout(grid).total;
+  L.bucket = off;
+  off += bucket_layout(n).total;
+  L.total = off + kAlign;
+  return L;
+}
+
 bool valid_key_type(int kt) { return kt >= PDQ_U32 && kt <= PDQ_U64; }
 
 struct Opts {
@@ -74,7 +168,12 @@ struct Opts {
   int32_t force_budget = -1;
   uint32_t tile = 0;
   uint64_t seed = 0;
+  float limit = 2.0f;
+  uint32_t steps = 256;
+  uint32_t batch = 1024;
+  uint32_t grid = 16;
 };
+
 
 int read_opts(const pdq_options* o, Opts* out) {
   if (!o) return PDQ_OK;
@@ -85,7 +184,14 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, force_budget) + sizeof(int32_t)) out->force_budget = o->force_budget;
   if (sz >= offsetof(pdq_options, tile) + sizeof(uint32_t)) out->tile = o->tile;
   if (sz >= offsetof(pdq_options, seed) + sizeof(uint64_t)) out->seed = o->seed;
-  if (out->flags & ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE)) return PDQ_ERR_UNSUPPORTED;
+  if (sz >= offsetof(pdq_options, learned_imbalance_limit) + sizeof(float) && o->learned_imbalance_limit != 0.0f)
+    out->limit = o->learned_imbalance_limit;
+  if (sz >= offsetof(pdq_options, learn_steps) + sizeof(uint32_t) && o->learn_steps) out->steps = o->learn_steps;
+  if (sz >= offsetof(pdq_options, learn_batch) + sizeof(uint32_t) && o->learn_batch) out->batch = o->learn_batch;
+  if (sz >= offsetof(pdq_options, learn_grid) + sizeof(uint32_t) && o->learn_grid) out->grid = o->learn_grid;
+  if (out->flags & ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED)) return PDQ_ERR_UNSUPPORTED;
+  if (out->steps > kMaxLearnSteps || out->grid > kMaxTrainGrid || out->batch > 65536 || out->batch % out->grid)
+    return PDQ_ERR_UNSUPPORTED;
   if (out->tile != 0 && out->tile != 1024 && out->tile != 2048 && out->tile != 4096 && out->tile != 8192 &&
       out->tile != 16384 && out->tile != 32768 && out->tile != 65536)
     return PDQ_ERR_UNSUPPORTED;
@@ -132,6 +238,172 @@ int finish_items(const Ctx& c, const Counters& snap, hipStream_t s) {
 }
 
 int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
+             void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st);
+
+char* align_ptr(void* p) {
+  return reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(p) + kAlign - 1) / kAlign * kAlign);
+}
+
+FitBufs fit_bufs(char* out, char* scratch, uint32_t steps, uint32_t grid) {
+  const FitOutLayout fo = fit_out_layout(steps);
+  const FitScratchLayout fs = fit_scratch_layout(grid);
+  FitBufs f;
+  f.sample = reinterpret_cast<uint64_t*>(out + fo.sample);
+  f.x = reinterpret_cast<float*>(out + fo.x);
+  f.t = reinterpret_cast<float*>(out + fo.t);
+  f.y = reinterpret_cast<float*>(out + fo.y);
+  f.params = reinterpret_cast<float*>(out + fo.params);
+  f.losses = reinterpret_cast<float*>(out + fo.losses);
+  f.splitters = reinterpret_cast<uint64_t*>(out + fo.splitters);
+  f.count = reinterpret_cast<uint32_t*>(out + fo.count);
+  f.info = reinterpret_cast<uint64_t*>(out + fo.info);
+  f.runmax = reinterpret_cast<float*>(scratch + fs.runmax);
+  f.partials = reinterpret_cast<float*>(scratch + fs.partials);
+  f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
+  f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  return f;
+}
+
+// Sample, sample sort, features, training, inference, splitters, all queued
+// on the stream without a synchronisation.
+int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s) {
+  const uint64_t m = kLearnSample;
+  HIP_TRY(launch_sample(kt, keys, n, m, o.seed, f.raw, s));
+  HIP_TRY(launch_sample_sort(f.raw, m, f.sample, s));
+  HIP_TRY(launch_features(f.sample, m, f.x, f.t, f.info, s));
+  TrainArgs a;
+  a.x = f.x;
+  a.t = f.t;
+  a.m = m;
+  a.seed = o.seed;
+  a.steps = o.steps;
+  a.batch = o.batch;
+  a.grid = o.grid;
+  a.residual = 1;
+  a.init = nullptr;
+  a.params = f.params;
+  a.losses = f.losses;
+  a.partials = f.partials;
+  a.sync = f.sync;
+  HIP_TRY(launch_train(a, s));
+  HIP_TRY(launch_infer(f.params, f.x, m, 1u, f.y, s));
+  HIP_TRY(launch_extract(f.sample, f.y, m, f.runmax, f.splitters, f.count, s));
+  return PDQ_OK;
+}
+
+BucketBufs bucket_bufs(char* area, uint64_t n, const uint64_t* splitters, const uint32_t* count) {
+  const BucketLayout L = bucket_layout(n);
+  BucketBufs b;
+  b.splitters = splitters;
+  b.count = count;
+  b.rows = reinterpret_cast<uint32_t*>(area + L.rows);
+  b.chunk = reinterpret_cast<uint32_t*>(area + L.chunk);
+  b.totals = reinterpret_cast<uint64_t*>(area + L.totals);
+  b.begin = reinterpret_cast<uint64_t*>(area + L.begin);
+  b.ntiles = bucket_tiles(n);
+  b.nchunks = bucket_chunks(n);
+  b.errors = nullptr;
+  b.order = reinterpret_cast<uint32_t*>(area + L.order);
+  return b;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool make() { return hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
+  double ms() const {
+    float v = 0;
+    if (a && b) (void)hipEventElapsedTime(&v, a, b);
+    return v;
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// What the learned first pass found, for the statistics.
+struct LearnedResult {
+  uint32_t state = 0;  // 0 not run, 1 used, 2 fell back
+  uint32_t splitters = 0, use_log = 0, ordered = 0;
+  uint64_t max_range = 0, equal = 0;
+  float loss = 0.0f;
+  double fit_ms = 0, hist_ms = 0, scatter_ms = 0;
+  uint64_t hist_bytes = 0, scatter_bytes = 0;
+};
+
+// Fit, histogram, judge and (if the judge agrees) scatter into bins.
+// Returns with res.state 1 when the bins were set up as the first lists,
+// 2 when the caller must start the plain path.
+int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, LearnedResult& res, hipStream_t s) {
+  const uint32_t kt = c.key_type;
+  const uint64_t n = c.n;
+  const uint32_t kb = key_bytes(kt);
+  const FitBufs f = fit_bufs(base + L.fit_out, base + L.fit_scratch, o.steps, o.grid);
+  BucketBufs b = bucket_bufs(base + L.bucket, n, f.splitters, f.count);
+  b.errors = &c.ctr->errors;
+  EventPair e_fit, e_hist, e_scat;
+  if (prof && !(e_fit.make() && e_hist.make() && e_scat.make())) return PDQ_ERR_HIP;
+  if (prof) HIP_TRY(hipEventRecord(e_fit.a, s));
+  int rc = run_fit(c.keys[0], n, kt, o, f, s);
+  if (rc != PDQ_OK) return rc;
+  if (prof) {
+    HIP_TRY(hipEventRecord(e_fit.b, s));
+    HIP_TRY(hipEventRecord(e_hist.a, s));
+  }
+  HIP_TRY(launch_bucket_hist(kt, c.keys[0], n, b, s));
+  HIP_TRY(launch_bucket_scan(b, s));
+  if (prof) HIP_TRY(hipEventRecord(e_hist.b, s));
+  // judge on the host: bin totals, splitter count, trainer flag, last loss
+  uint64_t totals[kBinStride];
+  uint32_t count = 0, sync[2] = {0, 0}, order_bits = 0;
+  uint64_t info[4] = {0, 0, 0, 0};
+  float loss = 0.0f;
+  HIP_TRY(hipMemcpyAsync(totals, b.totals, sizeof(totals), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&count, f.count, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(sync, f.sync, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&loss, f.losses + (o.steps - 1), 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&order_bits, b.order, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  res.splitters = count;
+  res.use_log = static_cast<uint32_t>(info[2]);
+  res.loss = loss;
+  uint64_t max_range = 0, equal = 0;
+  for (uint32_t i = 0; i <= 2 * count && i < static_cast<uint32_t>(kBinStride); ++i) {
+    if (i & 1u) equal += totals[i];
+    else if (totals[i] > max_range) max_range = totals[i];
+  }
+  res.max_range = max_range;
+  res.equal = equal;
+  // an input that is already non-decreasing or non-increasing is retired by
+  // the plain path's first pass; the learned bins would lose that order
+  const bool ordered = (order_bits & 1u) == 0 || (order_bits & 2u) == 0;
+  res.ordered = ordered ? 1u : 0u;
+  const bool ok = !ordered && sync[1] == 0 && isfinite(loss) && o.limit >= 0.0f &&
+                  static_cast<double>(max_range) <= static_cast<double>(o.limit) * static_cast<double>(n) / 256.0;
+  if (prof) {
+    res.fit_ms = e_fit.ms();
+    res.hist_ms = e_hist.ms();
+    res.hist_bytes = n * kb;
+  }
+  if (!ok) {
+    res.state = 2;
+    return PDQ_OK;
+  }
+  if (prof) HIP_TRY(hipEventRecord(e_scat.a, s));
+  HIP_TRY(launch_bucket_scatter(kt, c.has_vals != 0, c.keys[0], c.vals[0], c.keys[1], c.vals[1], n, b, s));
+  if (prof) HIP_TRY(hipEventRecord(e_scat.b, s));
+  HIP_TRY(launch_bucket_init(c, b.begin, s));
+  if (prof) {
+    HIP_TRY(hipEventSynchronize(e_scat.b));
+    res.scatter_ms = e_scat.ms();
+    res.scatter_bytes = n * 2ull * (kb + (c.has_vals ? 4u : 0u));
+  }
+  res.state = 1;
+  return PDQ_OK;
+}
+
+int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
              void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
   g_last_hip = 0;
   if (!valid_key_type(kt) || order != PDQ_ASCENDING) return PDQ_ERR_UNSUPPORTED;
@@ -154,7 +426,9 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   if (vals && (reinterpret_cast<uintptr_t>(vals) % 4)) return PDQ_ERR_INVALID;
   if (offsets && (reinterpret_cast<uintptr_t>(offsets) % 8)) return PDQ_ERR_INVALID;
   if (nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
-  const Layout L = make_layout(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals != nullptr);
+  const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
+  const Layout L = make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals != nullptr, learned,
+                                    o.steps, o.grid);
   if (!ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
 
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + kAlign - 1) / kAlign * kAlign);
@@ -196,7 +470,15 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
-  HIP_TRY(launch_init(c, s));
+  LearnedResult lres;
+  uint32_t src = 0;
+  if (learned) {
+    c.single = 0;  // the first partition pass sees the bins, not the whole range
+    rc = run_learned(c, o, L, base, prof, lres, s);
+    if (rc != PDQ_OK) return rc;
+    if (lres.state == 1) src = 1;
+  }
+  if (src == 0) HIP_TRY(launch_init(c, s));
   rc = read_counters(c, &snap, s);
   if (rc != PDQ_OK) return rc;
   if ((o.flags & PDQ_VALIDATE) && snap.bad_offsets) return PDQ_ERR_INVALID;
@@ -206,7 +488,6 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   const uint64_t bytes_per_key = 2ull * kb + (vals ? 8ull : 0ull);
   int parity = 0;
-  uint32_t src = 0;
   uint32_t pass = 0;
   uint64_t visits = 0;
   for (;;) {
@@ -268,6 +549,17 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     st->first_pivot_image = snap.first_pivot_image;
     st->first_left_size = snap.first_left;
     st->first_mode = snap.first_mode;
+    st->learned = lres.state;
+    st->learned_splitters = lres.splitters;
+    st->learned_max_range_bin = lres.max_range;
+    st->learned_equal_elements = lres.state == 1 ? lres.equal : 0;
+    st->learned_final_loss = lres.loss;
+    st->learned_use_log = lres.use_log;
+    st->learned_fit_ms = lres.fit_ms;
+    st->learned_hist_ms = lres.hist_ms;
+    st->learned_scatter_ms = lres.scatter_ms;
+    st->learned_hist_bytes = lres.hist_bytes;
+    st->learned_scatter_bytes = lres.scatter_bytes;
     if (prof) {
       double total = 0;
       uint64_t bytes = 0;
@@ -290,26 +582,43 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   return PDQ_OK;
 }
 
+// Runs a sort with statistics gathered in a current-layout struct and copied
+// out up to the caller's struct_size (older, smaller layouts stay valid).
+int sort_entry(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
+               void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
+  if (!st) return run_sort(keys, vals, n, offsets, nseg, kt, order, ws, ws_bytes, stream, opt, nullptr);
+  pdq_stats local;
+  memset(&local, 0, sizeof(local));
+  const uint32_t user_size = st->struct_size;
+  const size_t copy = user_size == 0 || user_size > sizeof(pdq_stats) ? sizeof(pdq_stats) : user_size;
+  const int rc = run_sort(keys, vals, n, offsets, nseg, kt, order, ws, ws_bytes, stream, opt, &local);
+  local.struct_size = user_size;
+  memcpy(st, &local, copy);
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has_vals, const pdq_options* opt) {
-  (void)opt;
   if (!valid_key_type(key_type)) return 0;
+  Opts o;
+  if (read_opts(opt, &o) != PDQ_OK) return 0;
   if (nseg == 0) nseg = 1;
-  return make_layout(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0).total;
+  const bool learned = (o.flags & PDQ_LEARNED) && nseg == 1 && n > kLearnSample;
+  return make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps, o.grid).total;
 }
 
 int pdq_sort(void* d_keys, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws, size_t ws_bytes,
              void* stream, const pdq_options* opt, pdq_stats* stats) {
-  return run_sort(d_keys, nullptr, n, nullptr, 1, key_type, order, d_ws, ws_bytes, stream, opt, stats);
+  return sort_entry(d_keys, nullptr, n, nullptr, 1, key_type, order, d_ws, ws_bytes, stream, opt, stats);
 }
 
 int pdq_sort_pairs(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws,
                    size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* stats) {
   if (n > 1 && !d_vals) return PDQ_ERR_INVALID;
-  return run_sort(d_keys, d_vals, n, nullptr, 1, key_type, order, d_ws, ws_bytes, stream, opt, stats);
+  return sort_entry(d_keys, d_vals, n, nullptr, 1, key_type, order, d_ws, ws_bytes, stream, opt, stats);
 }
 
 int pdq_segmented_sort(void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets, size_t nseg,
@@ -317,7 +626,7 @@ int pdq_segmented_sort(void* d_keys, uint32_t* d_vals, size_t n, const uint64_t*
                        const pdq_options* opt, pdq_stats* stats) {
   if (!d_offsets && nseg > 0) return PDQ_ERR_INVALID;
   if (!d_offsets) return n == 0 ? PDQ_OK : PDQ_ERR_INVALID;
-  return run_sort(d_keys, d_vals, n, d_offsets, nseg, key_type, order, d_ws, ws_bytes, stream, opt, stats);
+  return sort_entry(d_keys, d_vals, n, d_offsets, nseg, key_type, order, d_ws, ws_bytes, stream, opt, stats);
 }
 
 const char* pdq_status_string(int status) {
@@ -334,5 +643,136 @@ const char* pdq_status_string(int status) {
 int pdq_last_hip_error(void) { return g_last_hip; }
 
 int pdq_abi_version(void) { return PDQ_ABI_VERSION; }
+
+// ---- learned first pass, step by step (pdq_learned.h) ----------------------
+
+int pdq_mlp_infer(const float* d_params, const float* d_x, size_t m, int residual, float* d_y, void* stream) {
+  g_last_hip = 0;
+  if (m == 0) return PDQ_OK;
+  if (!d_params || !d_x || !d_y) return PDQ_ERR_INVALID;
+  HIP_TRY(launch_infer(d_params, d_x, m, residual ? 1u : 0u, d_y, static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+int pdq_mlp_gradient(const float* d_params, const float* d_x, const float* d_t, uint32_t batch, int residual,
+                     float* d_grad, float* d_loss, void* stream) {
+  g_last_hip = 0;
+  if (batch == 0 || batch > 65536) return PDQ_ERR_UNSUPPORTED;
+  if (!d_params || !d_x || !d_t || !d_grad || !d_loss) return PDQ_ERR_INVALID;
+  HIP_TRY(launch_gradient(d_params, d_x, d_t, batch, residual ? 1u : 0u, d_grad, d_loss,
+                          static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+size_t pdq_mlp_train_workspace_bytes(uint32_t grid) {
+  Bump b;
+  b.take(2ull * grid * kParamStride * 4);
+  b.take(4 * 4);
+  return b.off + kAlign;
+}
+
+int pdq_mlp_train(const float* d_x, const float* d_t, size_t m, uint64_t seed, uint32_t steps, uint32_t batch,
+                  uint32_t grid, int residual, const float* d_init, float* d_params, float* d_losses, void* d_ws,
+                  size_t ws_bytes, void* stream) {
+  g_last_hip = 0;
+  if (grid == 0 || grid > kMaxTrainGrid || batch == 0 || batch > 65536 || batch % grid || steps == 0 ||
+      steps > kMaxLearnSteps || m == 0 || m >= (1ull << 32))
+    return PDQ_ERR_UNSUPPORTED;
+  if (!d_x || !d_t || !d_params || !d_losses) return PDQ_ERR_INVALID;
+  if (!d_ws || ws_bytes < pdq_mlp_train_workspace_bytes(grid)) return PDQ_ERR_WORKSPACE;
+  char* base = align_ptr(d_ws);
+  Bump b;
+  const size_t partials = b.take(2ull * grid * kParamStride * 4);
+  const size_t sync = b.take(4 * 4);
+  TrainArgs a;
+  a.x = d_x;
+  a.t = d_t;
+  a.m = m;
+  a.seed = seed;
+  a.steps = steps;
+  a.batch = batch;
+  a.grid = grid;
+  a.residual = residual ? 1u : 0u;
+  a.init = d_init;
+  a.params = d_params;
+  a.losses = d_losses;
+  a.partials = reinterpret_cast<float*>(base + partials);
+  a.sync = reinterpret_cast<uint32_t*>(base + sync);
+  HIP_TRY(launch_train(a, static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+int pdq_learned_features(const uint64_t* d_sorted, size_t m, float* d_x, float* d_t, uint64_t* d_info,
+                         void* stream) {
+  g_last_hip = 0;
+  if (m == 0) return PDQ_OK;
+  if (!d_sorted || !d_x || !d_t || !d_info) return PDQ_ERR_INVALID;
+  HIP_TRY(launch_features(d_sorted, m, d_x, d_t, d_info, static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+int pdq_learned_extract(const uint64_t* d_sorted, const float* d_pred, size_t m, float* d_runmax,
+                        uint64_t* d_splitters, uint32_t* d_count, void* stream) {
+  g_last_hip = 0;
+  if (m == 0 || m >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (!d_sorted || !d_pred || !d_runmax || !d_splitters || !d_count) return PDQ_ERR_INVALID;
+  HIP_TRY(launch_extract(d_sorted, d_pred, m, d_runmax, d_splitters, d_count, static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+size_t pdq_bucket_workspace_bytes(size_t n) { return bucket_layout(n).total + kAlign; }
+
+int pdq_bucket_histogram(const void* d_keys, size_t n, pdq_key_type key_type, const uint64_t* d_splitters,
+                         const uint32_t* d_count, uint64_t* d_hist, void* d_ws, size_t ws_bytes, void* stream) {
+  g_last_hip = 0;
+  if (!valid_key_type(key_type)) return PDQ_ERR_UNSUPPORTED;
+  if (n == 0 || n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (!d_keys || !d_splitters || !d_count || !d_hist) return PDQ_ERR_INVALID;
+  if (!d_ws || ws_bytes < pdq_bucket_workspace_bytes(n)) return PDQ_ERR_WORKSPACE;
+  BucketBufs b = bucket_bufs(align_ptr(d_ws), n, d_splitters, d_count);
+  b.totals = d_hist;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_bucket_hist(static_cast<uint32_t>(key_type), d_keys, n, b, s));
+  HIP_TRY(launch_bucket_scan(b, s));
+  return PDQ_OK;
+}
+
+size_t pdq_learned_fit_workspace_bytes(const pdq_options* opt) {
+  Opts o;
+  if (read_opts(opt, &o) != PDQ_OK) return 0;
+  return fit_scratch_layout(o.grid).total + kAlign;
+}
+
+int pdq_learned_fit(const void* d_keys, size_t n, pdq_key_type key_type, void* d_ws, size_t ws_bytes,
+                    void* stream, const pdq_options* opt, const pdq_fit_buffers* out) {
+  g_last_hip = 0;
+  if (!valid_key_type(key_type)) return PDQ_ERR_UNSUPPORTED;
+  Opts o;
+  const int rc = read_opts(opt, &o);
+  if (rc != PDQ_OK) return rc;
+  if (n == 0 || n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (!d_keys || !out || !out->d_sample || !out->d_x || !out->d_t || !out->d_pred || !out->d_params ||
+      !out->d_losses || !out->d_splitters || !out->d_count || !out->d_info)
+    return PDQ_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(d_keys) % key_bytes(static_cast<uint32_t>(key_type))) return PDQ_ERR_INVALID;
+  if (!d_ws || ws_bytes < pdq_learned_fit_workspace_bytes(opt)) return PDQ_ERR_WORKSPACE;
+  char* scratch = align_ptr(d_ws);
+  const FitScratchLayout fs = fit_scratch_layout(o.grid);
+  FitBufs f;
+  f.sample = out->d_sample;
+  f.x = out->d_x;
+  f.t = out->d_t;
+  f.y = out->d_pred;
+  f.params = out->d_params;
+  f.losses = out->d_losses;
+  f.splitters = out->d_splitters;
+  f.count = out->d_count;
+  f.info = out->d_info;
+  f.runmax = reinterpret_cast<float*>(scratch + fs.runmax);
+  f.partials = reinterpret_cast<float*>(scratch + fs.partials);
+  f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
+  f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  return run_fit(d_keys, n, static_cast<uint32_t>(key_type), o, f, static_cast<hipStream_t>(stream));
+}
 
 }  // extern "C"

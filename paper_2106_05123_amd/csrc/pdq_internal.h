@@ -130,10 +130,20 @@ struct KeyU64 {
   static __device__ __forceinline__ uint64_t inv(uint64_t x) { return x; }
 };
 
+// SplitMix64 output function (Steele, Lea and Flood, 2014): the counter-based
+// generator behind every random choice of the library.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // ---- launch entry points (one translation unit each) ---------------------
 // Every launcher dispatches on ctx.key_type / ctx.has_vals.
 hipError_t launch_reset(const Ctx& c, hipStream_t s);
 hipError_t launch_init(const Ctx& c, hipStream_t s);
+hipError_t launch_bucket_init(const Ctx& c, const uint64_t* begin, hipStream_t s);
 hipError_t launch_pivot(const Ctx& c, int parity, uint32_t nseg, uint32_t src_buf, hipStream_t s);
 hipError_t launch_tilemap(const Ctx& c, int parity, uint32_t ntiles, hipStream_t s);
 hipError_t launch_partition(const Ctx& c, int parity, uint32_t ntiles, uint32_t src_buf, hipStream_t s);

@@ -1,5 +1,6 @@
-"""The C ABI library loads, exports every entry point of include/pdq.h, and
-rejects bad arguments before touching the GPU (no compute call here)."""
+"""The C ABI library loads, exports every entry point of include/pdq.h and
+include/pdq_learned.h, and rejects bad arguments before touching the GPU (no
+compute call here)."""
 import ctypes
 import os
 import re
@@ -9,12 +10,15 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pdq.h")
+HEADERS = [HEADER, os.path.join(ROOT, "include", "pdq_learned.h")]
 
 
 def header_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pdq_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(pdq_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -28,7 +32,8 @@ def pdq():
 
 def test_exports_every_declared_function(pdq):
     names = header_functions()
-    assert {"pdq_sort", "pdq_sort_pairs", "pdq_segmented_sort", "pdq_workspace_bytes"} <= set(names)
+    assert {"pdq_sort", "pdq_sort_pairs", "pdq_segmented_sort", "pdq_workspace_bytes", "pdq_mlp_train",
+            "pdq_learned_fit", "pdq_bucket_histogram"} <= set(names)
     L = pdq.lib()
     for n in names:
         assert hasattr(L, n), n
@@ -98,3 +103,50 @@ def test_binding_has_no_fallback(pdq, monkeypatch):
     monkeypatch.setattr(pdq, "LIB_PATH", "/nonexistent/libpdq.so")
     with pytest.raises(RuntimeError):
         pdq.lib()
+
+
+def test_learned_workspace_and_option_errors(pdq):
+    Opt = pdq.Options
+    plain = pdq.workspace_bytes(1 << 20, 1, "u32")
+    lo = Opt(ctypes.sizeof(Opt), pdq.FLAG_LEARNED, -1, 0, 0, 0.0, 0, 0, 0)
+    learned = pdq.workspace_bytes(1 << 20, 1, "u32", options=lo)
+    # sample (8 B) + features, targets, predictions, running max (4 x 4 B) per sample key,
+    # plus one histogram row of 512 counts per 8192-key tile
+    assert learned >= plain + pdq.LEARN_SAMPLE * 24 + ((1 << 20) // 8192) * 512 * 4
+    assert pdq.workspace_bytes(pdq.LEARN_SAMPLE, 1, "u32", options=lo) == pdq.workspace_bytes(pdq.LEARN_SAMPLE, 1, "u32")
+    bad = Opt(ctypes.sizeof(Opt), pdq.FLAG_LEARNED, -1, 0, 0, 0.0, 0, 1000, 16)   # batch % grid != 0
+    assert _call_sort(pdq, 0x1000, 1 << 20, opt=bad) == -2
+    bad2 = Opt(ctypes.sizeof(Opt), pdq.FLAG_LEARNED, -1, 0, 0, 0.0, 0, 1024, 65)  # grid > 64
+    assert _call_sort(pdq, 0x1000, 1 << 20, opt=bad2) == -2
+    older = Opt(24, pdq.FLAG_LEARNED, -1, 0, 0, 0.0, 0, 1000, 16)  # fields past struct_size are ignored
+    assert pdq.workspace_bytes(1 << 20, 1, "u32", options=older) == learned
+
+
+def test_learned_entry_point_errors_without_gpu(pdq):
+    L = pdq.lib()
+    vp = ctypes.c_void_p
+    # trainer: grid 0, batch not a multiple of grid, zero steps, null pointers, small workspace
+    args = lambda grid, batch, steps, x=0x1000, ws_bytes=1 << 30: (
+        vp(x), vp(0x2000), 65536, 0, steps, batch, grid, 1, None, vp(0x3000), vp(0x4000), vp(0x100000), ws_bytes, None)
+    assert L.pdq_mlp_train(*args(0, 1024, 256)) == -2
+    assert L.pdq_mlp_train(*args(16, 1000, 256)) == -2
+    assert L.pdq_mlp_train(*args(16, 1024, 0)) == -2
+    assert L.pdq_mlp_train(*args(16, 1024, 256, x=0)) == -1
+    assert L.pdq_mlp_train(*args(16, 1024, 256, ws_bytes=16)) == -3
+    assert L.pdq_mlp_train_workspace_bytes(16) >= 2 * 16 * 1153 * 4
+    assert L.pdq_mlp_gradient(vp(0x1000), vp(0x2000), vp(0x3000), 0, 1, vp(0x4000), vp(0x5000), None) == -2
+    assert L.pdq_mlp_gradient(None, vp(0x2000), vp(0x3000), 10, 1, vp(0x4000), vp(0x5000), None) == -1
+    assert L.pdq_mlp_infer(vp(0x1000), vp(0x2000), 0, 1, vp(0x3000), None) == 0
+    assert L.pdq_mlp_infer(None, vp(0x2000), 10, 1, vp(0x3000), None) == -1
+    assert L.pdq_learned_features(None, 10, vp(0x2000), vp(0x3000), vp(0x4000), None) == -1
+    assert L.pdq_learned_extract(vp(0x1000), vp(0x2000), 0, vp(0x3000), vp(0x4000), vp(0x5000), None) == -2
+    n = 1 << 20
+    need = L.pdq_bucket_workspace_bytes(n)
+    assert need >= (n // 8192) * 512 * 4
+    assert L.pdq_bucket_histogram(vp(0x1000), n, 9, vp(0x2000), vp(0x3000), vp(0x4000), vp(0x5000), need, None) == -2
+    assert L.pdq_bucket_histogram(vp(0x1000), 0, 1, vp(0x2000), vp(0x3000), vp(0x4000), vp(0x5000), need, None) == -2
+    assert L.pdq_bucket_histogram(vp(0x1000), n, 1, None, vp(0x3000), vp(0x4000), vp(0x5000), need, None) == -1
+    assert L.pdq_bucket_histogram(vp(0x1000), n, 1, vp(0x2000), vp(0x3000), vp(0x4000), vp(0x5000), 100, None) == -3
+    fb = pdq.FitBuffers()
+    assert L.pdq_learned_fit(vp(0x1000), n, 1, vp(0x100000), 1 << 30, None, None, ctypes.byref(fb)) == -1
+    assert L.pdq_learned_fit_workspace_bytes(None) > 0

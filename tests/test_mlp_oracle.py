@@ -232,11 +232,27 @@ def test_splitters_of_perfect_cdf_are_sample_quantiles():
 
 
 def test_splitters_constant_and_duplicates():
-    samp = np.sort(np.random.default_rng(1).integers(0, 5, 1000)).astype(np.uint64)
-    sp = M.splitters(samp, np.full(1000, 0.5, dtype=np.float32))
+    # distinct keys, constant prediction 0.5: thresholds <= 1/2 all map to the
+    # first key, higher ones are never reached
+    samp = np.sort(W.uniform_u64(4096, seed=2))
+    sp = M.splitters(samp, np.full(4096, 0.5, dtype=np.float32))
     assert np.array_equal(sp, samp[:1])
-    sp2 = M.splitters(samp, M.midrank_targets(samp))
-    assert np.all(np.diff(sp2.astype(np.int64)) > 0) and set(sp2) <= set(samp)
+    # five values, each far above m/256 copies: every one is a splitter, whatever the prediction
+    dup = np.sort(np.random.default_rng(1).integers(0, 5, 1000)).astype(np.uint64)
+    assert np.array_equal(M.splitters(dup, np.full(1000, 0.5, dtype=np.float32)), np.arange(5, dtype=np.uint64))
+    assert np.array_equal(M.splitters(dup, M.midrank_targets(dup)), np.arange(5, dtype=np.uint64))
+
+
+def test_heavy_key_becomes_splitter():
+    # one key with exactly m/256 + 1 copies in the middle of distinct keys is a
+    # splitter even when the prediction is useless (constant 0)
+    m = 1 << 16
+    samp = np.sort(np.concatenate([W.uniform_u64(m - 257, seed=3) | np.uint64(1), np.full(257, 2**62, np.uint64)]))
+    sp = M.splitters(samp, np.zeros(m, dtype=np.float32))
+    assert np.array_equal(sp, np.array([2**62], dtype=np.uint64))
+    # with m/256 - 1 copies it is not heavy
+    samp2 = np.sort(np.concatenate([W.uniform_u64(m - 255, seed=3) | np.uint64(1), np.full(255, 2**62, np.uint64)]))
+    assert M.splitters(samp2, np.zeros(m, dtype=np.float32)).size == 0
 
 
 def test_bins_brute_force_and_histogram():
