@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--cpu-log2n", type=int, default=26)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-segmented", action="store_true")
+    ap.add_argument("--seg-count", type=int, default=65536)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -238,6 +240,10 @@ def main():
             patterns[p] = row
             del pp, wi
 
+    segmented = None
+    if not args.no_segmented:
+        segmented = bench_segmented(pdq, torch, W, dev, args)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -274,8 +280,60 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "patterns_i32": patterns,
+        "segmented_f32_pairs": segmented,
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_segmented(pdq, torch, W, dev, args):
+    """65,536 segments with log-uniform sizes 1 ... 2^16, float32 N(0, 1) keys
+    with 5% in-segment duplicates and 2^10 each of -0.0 / +0.0, uint32
+    payloads; host-driven segmented sort timed like the main workload."""
+    log(f"generating {args.seg_count} segments")
+    keys, off, vals = W.segmented_f32(args.seg_count, max_log2=16, seed=0)
+    n = keys.size
+    pk = torch.from_numpy(keys).to(dev)
+    pv = torch.from_numpy(vals).to(dev)
+    po = torch.from_numpy(off).to(dev)
+    wk = torch.empty_like(pk)
+    wv = torch.empty_like(pv)
+    ws = torch.empty(pdq.workspace_bytes(n, args.seg_count, "f32", has_vals=True), dtype=torch.uint8, device=dev)
+
+    def run(steps, profile):
+        ms, stats = [], []
+        for _ in range(steps):
+            wk.copy_(pk)
+            wv.copy_(pv)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            st = pdq.segmented_sort_(wk, po, wv, workspace=ws, profile=profile, stats=profile)
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+            if st:
+                stats.append(st)
+        return ms, stats
+
+    run(1, False)
+    ms, stats = run(max(2, args.steps // 2), True)
+    # output check on one segment boundary sample: every segment sorted
+    kk = wk.view(torch.int32).to(torch.int64)
+    img = torch.where(kk < 0, ~kk & 0xFFFFFFFF, kk | 0x80000000)
+    starts = po[:-1].to(torch.int64)
+    desc = (img[1:] < img[:-1])
+    seg_start = torch.zeros(n, dtype=torch.bool, device=dev)
+    seg_start[starts[starts < n]] = True
+    if bool((desc & ~seg_start[1:]).any().item()):
+        raise SystemExit("bench: segmented output not sorted within segments")
+    s0 = stats[0]
+    mean = float(np.mean(ms))
+    return {"workload": f"{args.seg_count} segments, log-uniform sizes 1..2^16, float32 N(0,1) keys with 5% "
+                        f"duplicates and signed zeros, uint32 payloads (seed 0)",
+            "n": n, "plain": {"keys/s": round(n / (mean * 1e-3), 0), "ms": round(mean, 3),
+                              "passes": s0["passes"], "partition_ms": round(s0["partition_ms"], 3),
+                              "partition_GBps": round(s0["partition_bytes"] / (s0["partition_ms"] * 1e-3) / 1e9, 1)
+                              if s0["partition_ms"] else None}}
 
 
 def _cpu_model() -> str:

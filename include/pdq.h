@@ -84,9 +84,16 @@ enum pdq_status {
 enum pdq_flags {
   PDQ_VALIDATE = 1u << 0, /* check offsets on the device before sorting (synchronises) */
   PDQ_PROFILE = 1u << 1,  /* time every partition launch with HIP events (needs stats) */
-  PDQ_LEARNED = 1u << 2   /* learned multiway first pass (pdq_sort / pdq_sort_pairs with
+  PDQ_LEARNED = 1u << 2,  /* learned multiway first pass (pdq_sort / pdq_sort_pairs with
                              n > 65536; other calls ignore it); pass the same options to
                              pdq_workspace_bytes */
+  PDQ_BATCHED = 1u << 3,  /* pdq_segmented_sort: one persistent launch over a device work
+                             queue, no host synchronisation (unless stats or PDQ_VALIDATE);
+                             meant for many segments of up to ~2^20 keys each; pass the same
+                             options to pdq_workspace_bytes */
+  PDQ_AUTOTUNE = 1u << 4  /* pdq_plan_create: time every persistent-kernel shape on the
+                             caller's data first and keep the fastest (needs the workspace
+                             pdq_workspace_bytes gives with this flag) */
 };
 
 typedef struct pdq_options {
@@ -101,6 +108,8 @@ typedef struct pdq_options {
   uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps, 0 = 256 (at most 65536) */
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
+  uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
+                            1024x8, 1024x16, 512x8, 512x16 (threads x tile rows) */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */
@@ -137,6 +146,9 @@ typedef struct pdq_stats {
   double learned_scatter_ms;      /* PDQ_PROFILE: scatter into the bins */
   uint64_t learned_hist_bytes;    /* PDQ_PROFILE: algorithmic bytes of the histogram pass */
   uint64_t learned_scatter_bytes; /* PDQ_PROFILE: algorithmic bytes of the scatter */
+  uint32_t batch_items;           /* PDQ_BATCHED: segments that went through the device queue */
+  uint32_t batch_shape;           /* PDQ_BATCHED: persistent-kernel shape used (0 ... 3) */
+  double batch_ms;                /* PDQ_BATCHED + PDQ_PROFILE: duration of the whole launch sequence */
 } pdq_stats;
 
 /* Bytes of device workspace needed for a call with these sizes and options
@@ -161,6 +173,31 @@ int pdq_sort_pairs(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_ty
 int pdq_segmented_sort(void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets,
                        size_t nseg, pdq_key_type key_type, pdq_order order, void* d_ws,
                        size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* stats);
+
+/* A captured batched segmented sort: the launch sequence of
+ * pdq_segmented_sort with PDQ_BATCHED for these exact buffers, instantiated
+ * once as a HIP graph and replayed by pdq_plan_launch. The plan owns host
+ * memory and the graph only; the caller keeps d_keys, d_vals, d_offsets and
+ * d_ws alive and unchanged in size while the plan exists, and may refill
+ * them between launches. With PDQ_AUTOTUNE in opt->flags the persistent
+ * kernel's shape is first chosen by timing every shape on the caller's data
+ * (the keys and payloads are restored afterwards; synchronises `stream`);
+ * the choice is remembered for later calls with the same key type, payload
+ * flag, n and segment count. */
+typedef struct pdq_plan pdq_plan;
+
+int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets,
+                    size_t nseg, pdq_key_type key_type, void* d_ws, size_t ws_bytes, void* stream,
+                    const pdq_options* opt);
+
+/* Replays the plan's graph on `stream`. */
+int pdq_plan_launch(pdq_plan* plan, void* stream);
+
+/* Shape index used (0 ... 3) and, after autotuning, the measured ms per
+ * shape (ms[4]; 0 where not measured). Either pointer may be NULL. */
+int pdq_plan_info(const pdq_plan* plan, uint32_t* shape, double* ms);
+
+void pdq_plan_destroy(pdq_plan* plan);
 
 /* Human-readable text of a status code (static storage). */
 const char* pdq_status_string(int status);

@@ -26,7 +26,8 @@ __all__ = [
     "PdqError", "Options", "Stats", "lib", "workspace_bytes", "sort_", "sort_pairs_",
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
-    "learned_features", "learned_extract", "bucket_histogram", "learned_fit",
+    "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "FLAG_BATCHED", "FLAG_AUTOTUNE",
+    "Plan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +37,9 @@ PDQ_OK = 0
 FLAG_VALIDATE = 1
 FLAG_PROFILE = 2
 FLAG_LEARNED = 4
+FLAG_BATCHED = 8
+FLAG_AUTOTUNE = 16
+BATCH_SHAPES = ((1024, 8), (1024, 16), (512, 8), (512, 16))
 MLP_PARAMS = 1153
 MAX_SPLITTERS = 255
 LEARN_SAMPLE = 65536
@@ -53,6 +57,7 @@ class Options(ctypes.Structure):
         ("learn_steps", ctypes.c_uint32),
         ("learn_batch", ctypes.c_uint32),
         ("learn_grid", ctypes.c_uint32),
+        ("batch_shape", ctypes.c_uint32),
     ]
 
 
@@ -90,6 +95,9 @@ class Stats(ctypes.Structure):
         ("learned_scatter_ms", ctypes.c_double),
         ("learned_hist_bytes", ctypes.c_uint64),
         ("learned_scatter_bytes", ctypes.c_uint64),
+        ("batch_items", ctypes.c_uint32),
+        ("batch_shape", ctypes.c_uint32),
+        ("batch_ms", ctypes.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -150,6 +158,14 @@ def lib():
         L.pdq_learned_fit_workspace_bytes.argtypes = [ctypes.POINTER(Options)]
         L.pdq_learned_fit_workspace_bytes.restype = sz
         L.pdq_learned_fit.argtypes = [vp, sz, i, vp, sz, vp, ctypes.POINTER(Options), ctypes.POINTER(FitBuffers)]
+        L.pdq_plan_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), vp, vp, sz, vp, sz, i, vp, sz, vp,
+                                      ctypes.POINTER(Options)]
+        L.pdq_plan_launch.argtypes = [vp, vp]
+        L.pdq_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]
+        L.pdq_plan_destroy.argtypes = [vp]
+        L.pdq_plan_destroy.restype = None
+        for f in ("pdq_plan_create", "pdq_plan_launch", "pdq_plan_info"):
+            getattr(L, f).restype = ctypes.c_int
         for f in ("pdq_mlp_infer", "pdq_mlp_gradient", "pdq_mlp_train", "pdq_learned_features",
                   "pdq_learned_extract", "pdq_bucket_histogram", "pdq_learned_fit"):
             getattr(L, f).restype = ctypes.c_int
@@ -179,9 +195,9 @@ def _key_type(t) -> int:
 
 
 def _options(force_budget: int, tile: int, flags: int, seed: int = 0, imbalance_limit: float = 0.0,
-             learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0) -> Options:
+             learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, batch_shape: int = 0) -> Options:
     return Options(ctypes.sizeof(Options), flags, force_budget, tile, seed, imbalance_limit, learn_steps,
-                   learn_batch, learn_grid)
+                   learn_batch, learn_grid, batch_shape)
 
 
 def workspace_bytes(n: int, nseg: int = 1, key_type: int | str = "u32", has_vals: bool = False,
@@ -252,15 +268,18 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
 
 
 def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: int = 0,
-                    validate: bool = False, profile: bool = False, stats: bool = False, workspace=None):
+                    validate: bool = False, profile: bool = False, stats: bool = False, workspace=None,
+                    batched: bool = False, batch_shape: int = 0):
     """Sort each segment [offsets[s], offsets[s+1]) of keys in place.
-    offsets: uint64 device tensor of nseg+1 entries."""
+    offsets: uint64 device tensor of nseg+1 entries. batched=True runs the
+    persistent device-queue form (batch_shape 1..4 forces a shape)."""
     import torch
     if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
         raise ValueError("offsets must be a contiguous uint64 device tensor")
     nseg = offsets.numel() - 1
-    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0)
-    kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace)
+    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0)
+    kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace,
+                                         dict(batch_shape=batch_shape))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_segmented_sort(ctypes.c_void_p(keys.data_ptr()),
                                   ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,
@@ -378,3 +397,43 @@ def learned_fit(keys, *, seed: int = 0, learn_steps: int = 0, learn_batch: int =
     u = int(out["count"].cpu().item())
     out["splitters"] = out["splitters"][:u]
     return out
+
+
+class Plan:
+    """A captured batched segmented sort bound to these tensors (see
+    pdq_plan_create). launch() replays the graph on the current stream."""
+
+    def __init__(self, keys, offsets, vals=None, *, autotune: bool = False, batch_shape: int = 0,
+                 force_budget: int = -1, workspace=None):
+        import torch
+        if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise ValueError("offsets must be a contiguous uint64 device tensor")
+        nseg = offsets.numel() - 1
+        flags = FLAG_BATCHED | (FLAG_AUTOTUNE if autotune else 0)
+        kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, 0, flags, workspace,
+                                             dict(batch_shape=batch_shape))
+        self._keep = (keys, offsets, vals, ws)
+        self._h = ctypes.c_void_p()
+        _check(lib().pdq_plan_create(ctypes.byref(self._h), _ptr(keys), _ptr(vals), keys.numel(), _ptr(offsets),
+                                     nseg, kt, _ptr(ws), need, stream, ctypes.byref(opt)))
+
+    def launch(self):
+        import torch
+        _check(lib().pdq_plan_launch(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def info(self):
+        shape = ctypes.c_uint32()
+        ms = (ctypes.c_double * 4)()
+        _check(lib().pdq_plan_info(self._h, ctypes.byref(shape), ms))
+        return int(shape.value), list(ms)
+
+    def destroy(self):
+        if self._h:
+            lib().pdq_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

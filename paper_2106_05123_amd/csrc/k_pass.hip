@@ -3,6 +3,7 @@
 // heapsort fallback.
 #include "learn_internal.h"
 #include "pdq_internal.h"
+#include "pivot.h"
 #include "wave_ops.h"
 
 namespace pdq {
@@ -136,17 +137,8 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->equal_elements), eq ? size : 0);
 }
 
-// Pivot choice for every live segment: Tukey's ninther, the median of the
-// medians of three triples (Section 2). Normally the triples are (first,
-// mid, last), (first+1, mid-1, last-1), (first+2, mid+1, last-2). After a
-// bad partition the segment takes fresh candidates (Section 4.2) at nine
-// positions drawn from a counter-based hash of (seed, begin, end) -- the
-// randomised form of the fresh-candidate rule. The fixed 25%/75% positions
-// of the deterministic form are not used here: a stable out-of-place
-// partition keeps periodic input structure intact, so fixed offsets can
-// keep landing on equally bad candidates pass after pass. Then the
-// predecessor rule of Section 3 selects partition_left when the predecessor
-// is not below the pivot.
+// Pivot choice for every live segment (choose_pivot, pivot.h). The first
+// lane also clears the counters of the list the bookkeeping will fill.
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32_t nseg, uint32_t src) {
   using T = typename K::T;
@@ -160,52 +152,11 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   }
   if (i >= nseg) return;
   Seg* sp = &c.segs[parity][i];
-  const uint64_t b = sp->begin, e = sp->end;
-  const uint64_t size = e - b;
-  const uint64_t m = size / 2;
-  uint64_t off[9] = {0, m, size - 1, 1, m - 1, size - 2, 2, m + 1, size - 3};
-  if (sp->flags & kSegFresh) {
-    const uint64_t h0 = mix64(c.seed ^ mix64(b ^ mix64(e)));
-#pragma unroll
-    for (int k = 0; k < 9; ++k) off[k] = mix64(h0 + static_cast<uint64_t>(k)) % size;
-  }
-  const T* keys = static_cast<const T*>(c.keys[src]);
-  T raw[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) raw[k] = keys[b + off[k]];
-  uint64_t best_ord = 0, best_pos = 0;
-  T best_raw = 0;
-  {
-    // medians of the three triples, then the median of those
-    uint64_t mo[3], mp[3];
-    T mr[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      uint64_t o0 = K::ord(raw[3 * t]), o1 = K::ord(raw[3 * t + 1]), o2 = K::ord(raw[3 * t + 2]);
-      int sel;
-      if (o0 < o1) sel = (o1 < o2) ? 1 : ((o0 < o2) ? 2 : 0);
-      else sel = (o0 < o2) ? 0 : ((o1 < o2) ? 2 : 1);
-      mo[t] = sel == 0 ? o0 : (sel == 1 ? o1 : o2);
-      mp[t] = off[3 * t + sel];
-      mr[t] = raw[3 * t + sel];
-    }
-    int sel;
-    if (mo[0] < mo[1]) sel = (mo[1] < mo[2]) ? 1 : ((mo[0] < mo[2]) ? 2 : 0);
-    else sel = (mo[0] < mo[2]) ? 0 : ((mo[1] < mo[2]) ? 2 : 1);
-    best_ord = mo[sel];
-    best_pos = mp[sel];
-    best_raw = mr[sel];
-  }
-  uint32_t mode = kModeRight;
-  if (!(sp->flags & kSegLeftmost)) {
-    // the predecessor is an ancestor's pivot and already sits at its final
-    // place in the user buffer (Lemma 1)
-    const T pred = static_cast<const T*>(c.keys[0])[b - 1];
-    if (!(static_cast<uint64_t>(K::ord(pred)) < best_ord)) mode = kModeLeft;
-  }
-  sp->pivot = static_cast<uint64_t>(best_raw);
-  sp->pidx = b + best_pos;
-  sp->mode = mode;
+  const PivotChoice<K> pc = choose_pivot<K>(static_cast<const T*>(c.keys[src]), static_cast<const T*>(c.keys[0]),
+                                            sp->begin, sp->end, sp->flags, c.seed);
+  sp->pivot = static_cast<uint64_t>(pc.raw);
+  sp->pidx = pc.pidx;
+  sp->mode = pc.mode;
 }
 
 // Ticket -> segment map for the partition kernel, and a cleared status word
@@ -339,27 +290,8 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c) {
 }
 
 // Heapsort fallback (Section 4.1: a segment that used up its bad-partition
-// budget). Williams' heapsort, one workgroup per segment: the workgroup
-// moves the segment into the user buffer, then one lane sorts it there.
-template <class K>
-__device__ void sift_down(typename K::T* a, uint32_t* v, uint64_t root, uint64_t n) {
-  for (;;) {
-    uint64_t child = 2 * root + 1;
-    if (child >= n) return;
-    if (child + 1 < n && K::ord(a[child]) < K::ord(a[child + 1])) ++child;
-    if (!(K::ord(a[root]) < K::ord(a[child]))) return;
-    typename K::T t = a[root];
-    a[root] = a[child];
-    a[child] = t;
-    if (v) {
-      uint32_t tv = v[root];
-      v[root] = v[child];
-      v[child] = tv;
-    }
-    root = child;
-  }
-}
-
+// budget), one workgroup per segment: the workgroup moves the segment into
+// the user buffer, then one lane sorts it there (heapsort_range, pivot.h).
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c) {
   using T = typename K::T;
@@ -377,19 +309,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c) {
     __threadfence_block();
     __syncthreads();
   }
-  if (threadIdx.x != 0 || len < 2) return;
-  for (uint64_t r = len / 2; r-- > 0;) sift_down<K>(a, v, r, len);
-  for (uint64_t end = len - 1; end > 0; --end) {
-    T t = a[0];
-    a[0] = a[end];
-    a[end] = t;
-    if (v) {
-      uint32_t tv = v[0];
-      v[0] = v[end];
-      v[end] = tv;
-    }
-    sift_down<K>(a, v, 0, end);
-  }
+  if (threadIdx.x == 0) heapsort_range<K>(a, v, len);
 }
 
 template <template <class> class F, class... Args>

@@ -20,10 +20,14 @@
 #include <stdint.h>
 #include <string.h>
 
-#include <vector>
-
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "batch_internal.h"
 #include "learn_internal.h"
 #include "pdq.h"
 #include "pdq_learned.h"
@@ -52,6 +56,10 @@ struct Layout {
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
   size_t fit_out = 0, fit_scratch = 0, bucket = 0;
+  // batched segmented sort: queue words, ring items, ring slot states, and
+  // (autotuning only) a copy of the input
+  size_t bq = 0, bitems = 0, bstate = 0, backup_keys = 0, backup_vals = 0;
+  uint32_t bcap = 0;
 };
 
 // Offsets inside an area, built by the same bump allocator as the layout.
@@ -147,17 +155,33 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
   return L;
 }
 
-Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool learned, uint32_t steps, uint32_t grid) {
+// Ring capacity of the batched queue: queued segments are disjoint and hold
+// more than kBaseMax keys each, plus at most one parent per resident
+// workgroup while it pushes its children.
+uint32_t batch_capacity(size_t n) { return static_cast<uint32_t>(n / (kBaseMax + 1) + 4096); }
+
+Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool learned, uint32_t steps, uint32_t grid,
+                        bool batched = false, bool tune = false) {
   Layout L = make_layout(n, nseg, kt, vals);
-  if (!learned) return L;
-  size_t off = L.total - kAlign;
-  L.fit_out = off;
-  off += fit_out_layout(steps).total;
-  L.fit_scratch = off;
-  off += fit_scratch_layout(grid).total;
-  L.bucket = off;
-  off += bucket_layout(n).total;
-  L.total = off + kAlign;
+  if (!learned && !batched) return L;
+  Bump b;
+  b.off = L.total - kAlign;
+  if (learned) {
+    L.fit_out = b.take(fit_out_layout(steps).total);
+    L.fit_scratch = b.take(fit_scratch_layout(grid).total);
+    L.bucket = b.take(bucket_layout(n).total);
+  }
+  if (batched) {
+    L.bcap = batch_capacity(n);
+    L.bq = b.take(sizeof(BatchQ));
+    L.bitems = b.take(sizeof(BItem) * static_cast<size_t>(L.bcap));
+    L.bstate = b.take(4ull * L.bcap);
+    if (tune) {
+      L.backup_keys = b.take(n * key_bytes(kt));
+      L.backup_vals = b.take(vals ? n * 4 : 0);
+    }
+  }
+  L.total = b.off + kAlign;
   return L;
 }
 
@@ -172,6 +196,7 @@ struct Opts {
   uint32_t steps = 256;
   uint32_t batch = 1024;
   uint32_t grid = 16;
+  uint32_t batch_shape = 0;  // 0 = tuned or default, else shape index + 1
 };
 
 
@@ -189,7 +214,11 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, learn_steps) + sizeof(uint32_t) && o->learn_steps) out->steps = o->learn_steps;
   if (sz >= offsetof(pdq_options, learn_batch) + sizeof(uint32_t) && o->learn_batch) out->batch = o->learn_batch;
   if (sz >= offsetof(pdq_options, learn_grid) + sizeof(uint32_t) && o->learn_grid) out->grid = o->learn_grid;
-  if (out->flags & ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED)) return PDQ_ERR_UNSUPPORTED;
+  if (sz >= offsetof(pdq_options, batch_shape) + sizeof(uint32_t)) out->batch_shape = o->batch_shape;
+  if (out->flags &
+      ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE))
+    return PDQ_ERR_UNSUPPORTED;
+  if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->steps > kMaxLearnSteps || out->grid > kMaxTrainGrid || out->batch > 65536 || out->batch % out->grid)
     return PDQ_ERR_UNSUPPORTED;
   if (out->tile != 0 && out->tile != 1024 && out->tile != 2048 && out->tile != 4096 && out->tile != 8192 &&
@@ -403,35 +432,8 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   return PDQ_OK;
 }
 
-int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
-             void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
-  g_last_hip = 0;
-  if (!valid_key_type(kt) || order != PDQ_ASCENDING) return PDQ_ERR_UNSUPPORTED;
-  Opts o;
-  int rc = read_opts(opt, &o);
-  if (rc != PDQ_OK) return rc;
-  if (n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
-  const uint32_t kb = key_bytes(static_cast<uint32_t>(kt));
-  if (st) {
-    const uint32_t sz = st->struct_size;
-    memset(st, 0, sizeof(pdq_stats));
-    st->struct_size = sz;
-    st->first_mode = -1;
-  }
-  if (offsets && nseg == 0) return n == 0 ? PDQ_OK : PDQ_ERR_INVALID;
-  if (n <= 1 && !offsets) return PDQ_OK;
-  if (n == 0) return PDQ_OK;
-  if (!keys) return PDQ_ERR_INVALID;
-  if (reinterpret_cast<uintptr_t>(keys) % kb) return PDQ_ERR_INVALID;
-  if (vals && (reinterpret_cast<uintptr_t>(vals) % 4)) return PDQ_ERR_INVALID;
-  if (offsets && (reinterpret_cast<uintptr_t>(offsets) % 8)) return PDQ_ERR_INVALID;
-  if (nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
-  const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
-  const Layout L = make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals != nullptr, learned,
-                                    o.steps, o.grid);
-  if (!ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
-
-  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + kAlign - 1) / kAlign * kAlign);
+Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, const Opts& o,
+             const Layout& L, char* base) {
   Ctx c = {};
   c.keys[0] = keys;
   c.keys[1] = base + L.scratch_keys;
@@ -457,8 +459,126 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.has_vals = vals ? 1u : 0u;
   c.single = offsets ? 0u : 1u;
   c.seed = o.seed;
+  return c;
+}
 
+// ---- batched segmented sort --------------------------------------------------
+
+// Autotuned shapes, remembered per (key type, payload, n, segment count).
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, uint32_t, uint64_t, uint64_t>, int> g_tune;
+
+int tuned_shape(const Ctx& c, const Opts& o) {
+  if (o.batch_shape) return static_cast<int>(o.batch_shape) - 1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+BatchArgs batch_args(const Layout& L, char* base) {
+  BatchArgs b;
+  b.q = reinterpret_cast<BatchQ*>(base + L.bq);
+  b.items = reinterpret_cast<BItem*>(base + L.bitems);
+  b.state = reinterpret_cast<uint32_t*>(base + L.bstate);
+  return b;
+}
+
+// The whole launch sequence, with no host synchronisation (capturable):
+// counters, queue and base lists, the persistent kernel, then the base-case
+// kernels over the lists it filled.
+int enqueue_batched(Ctx c, const Layout& L, char* base, int shape, hipStream_t s) {
+  c.device_counts = 1;
+  const BatchArgs b = batch_args(L, base);
+  const uint32_t grid = batch_grid(c, shape);
+  if (grid == 0) return PDQ_ERR_HIP;
+  HIP_TRY(launch_reset(c, s));
+  HIP_TRY(launch_batch_prepare(c, b, L.bcap, s));
+  HIP_TRY(launch_batch(c, b, shape, grid, s));
+  for (int k = 0; k < kBaseClasses; ++k) HIP_TRY(launch_base(c, k, c.max_items, s));
+  return PDQ_OK;
+}
+
+int run_batched(const Ctx& c, const Opts& o, const Layout& L, char* base, pdq_stats* st, hipStream_t s) {
+  const int shape = tuned_shape(c, o);
+  if (o.flags & PDQ_VALIDATE) {
+    // validation needs the offsets checked before anything is moved
+    Ctx v = c;
+    v.device_counts = 1;
+    HIP_TRY(launch_reset(v, s));
+    HIP_TRY(launch_batch_prepare(v, batch_args(L, base), L.bcap, s));
+    Counters snap = {};
+    HIP_TRY(hipMemcpyAsync(&snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (snap.bad_offsets || (snap.errors & kErrCapacity)) return PDQ_ERR_INVALID;
+  }
+  EventPair ev;
+  const bool prof = (o.flags & PDQ_PROFILE) && st;
+  if (prof && !ev.make()) return PDQ_ERR_HIP;
+  if (prof) HIP_TRY(hipEventRecord(ev.a, s));
+  int rc = enqueue_batched(c, L, base, shape, s);
+  if (rc != PDQ_OK) return rc;
+  if (prof) HIP_TRY(hipEventRecord(ev.b, s));
+  if (!st) return PDQ_OK;
+  Counters snap = {};
+  BatchQ q = {};
+  HIP_TRY(hipMemcpyAsync(&snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&q, batch_args(L, base).q, sizeof(BatchQ), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (snap.errors & kErrCapacity) return PDQ_ERR_INVALID;
+  if (snap.errors || q.error) {
+    g_last_hip = 0;
+    return PDQ_ERR_HIP;
+  }
+  st->passes = 0;
+  st->partitions_right = snap.partitions_right;
+  st->partitions_left = snap.partitions_left;
+  st->bad_partitions = snap.bad_partitions;
+  st->heapsort_segments = snap.heap_segments;
+  st->heapsort_elements = snap.heap_elements;
+  st->base_segments = snap.base_segments;
+  st->base_elements = snap.base_elements;
+  st->sorted_segments = snap.sorted_segments;
+  st->sorted_elements = snap.sorted_elements;
+  st->equal_elements = snap.equal_elements;
+  st->batch_items = q.tail;
+  st->batch_shape = static_cast<uint32_t>(shape);
+  if (prof) st->batch_ms = ev.ms();
+  return PDQ_OK;
+}
+
+int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
+             void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
+  g_last_hip = 0;
+  if (!valid_key_type(kt) || order != PDQ_ASCENDING) return PDQ_ERR_UNSUPPORTED;
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc != PDQ_OK) return rc;
+  if (n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  const uint32_t kb = key_bytes(static_cast<uint32_t>(kt));
+  if (st) {
+    const uint32_t sz = st->struct_size;
+    memset(st, 0, sizeof(pdq_stats));
+    st->struct_size = sz;
+    st->first_mode = -1;
+  }
+  if (offsets && nseg == 0) return n == 0 ? PDQ_OK : PDQ_ERR_INVALID;
+  if (n <= 1 && !offsets) return PDQ_OK;
+  if (n == 0) return PDQ_OK;
+  if (!keys) return PDQ_ERR_INVALID;
+  if (reinterpret_cast<uintptr_t>(keys) % kb) return PDQ_ERR_INVALID;
+  if (vals && (reinterpret_cast<uintptr_t>(vals) % 4)) return PDQ_ERR_INVALID;
+  if (offsets && (reinterpret_cast<uintptr_t>(offsets) % 8)) return PDQ_ERR_INVALID;
+  if (nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
+  const bool batched = (o.flags & PDQ_BATCHED) && offsets;
+  const Layout L = make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals != nullptr, learned,
+                                    o.steps, o.grid, batched, false);
+  if (!ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
+
+  char* base = align_ptr(ws);
+  Ctx c = make_ctx(keys, vals, n, offsets, nseg, kt, o, L, base);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (batched) return run_batched(c, o, L, base, st, s);
   const bool prof = (o.flags & PDQ_PROFILE) && st;
   std::vector<Timed> timed;
   auto cleanup = [&]() {
@@ -607,7 +727,10 @@ size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has
   if (read_opts(opt, &o) != PDQ_OK) return 0;
   if (nseg == 0) nseg = 1;
   const bool learned = (o.flags & PDQ_LEARNED) && nseg == 1 && n > kLearnSample;
-  return make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps, o.grid).total;
+  const bool batched = (o.flags & (PDQ_BATCHED | PDQ_AUTOTUNE)) != 0;
+  return make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps, o.grid, batched,
+                          (o.flags & PDQ_AUTOTUNE) != 0)
+      .total;
 }
 
 int pdq_sort(void* d_keys, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws, size_t ws_bytes,
@@ -643,6 +766,128 @@ const char* pdq_status_string(int status) {
 int pdq_last_hip_error(void) { return g_last_hip; }
 
 int pdq_abi_version(void) { return PDQ_ABI_VERSION; }
+
+// ---- captured batched sort --------------------------------------------------
+
+struct pdq_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t shape = 0;
+  double ms[kBatchShapes] = {};
+};
+
+int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets,
+                    size_t nseg, pdq_key_type key_type, void* d_ws, size_t ws_bytes, void* stream,
+                    const pdq_options* opt) {
+  g_last_hip = 0;
+  if (!plan) return PDQ_ERR_INVALID;
+  *plan = nullptr;
+  if (!valid_key_type(key_type)) return PDQ_ERR_UNSUPPORTED;
+  Opts o;
+  int rc = read_opts(opt, &o);
+  if (rc != PDQ_OK) return rc;
+  if (n == 0 || n >= (1ull << 32) || nseg == 0 || nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  const uint32_t kb = key_bytes(static_cast<uint32_t>(key_type));
+  if (!d_keys || !d_offsets || reinterpret_cast<uintptr_t>(d_keys) % kb ||
+      reinterpret_cast<uintptr_t>(d_offsets) % 8 || (d_vals && reinterpret_cast<uintptr_t>(d_vals) % 4))
+    return PDQ_ERR_INVALID;
+  const bool tune = (o.flags & PDQ_AUTOTUNE) != 0;
+  const Layout L = make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), d_vals != nullptr, false, o.steps,
+                                    o.grid, true, tune);
+  if (!d_ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
+  char* base = align_ptr(d_ws);
+  const Ctx c = make_ctx(d_keys, d_vals, n, d_offsets, nseg, key_type, o, L, base);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  pdq_plan* p = new pdq_plan();
+  auto fail = [&](int code) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return code;
+  };
+  int shape = tuned_shape(c, o);
+  if (tune) {
+    // time every shape on a copy of the caller's data, keep the fastest
+    void* bk = base + L.backup_keys;
+    uint32_t* bv = d_vals ? reinterpret_cast<uint32_t*>(base + L.backup_vals) : nullptr;
+    if (hipMemcpyAsync(bk, d_keys, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+    if (bv && hipMemcpyAsync(bv, d_vals, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+    double best = 1e300;
+    for (int sh = 0; sh < kBatchShapes; ++sh) {
+      double total = 0;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run warms the kernel up
+        if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+        if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return fail(PDQ_ERR_HIP);
+        EventPair ev;
+        if (!ev.make() || hipEventRecord(ev.a, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+        rc = enqueue_batched(c, L, base, sh, s);
+        if (rc != PDQ_OK) return fail(rc);
+        if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess)
+          return fail(PDQ_ERR_HIP);
+        if (rep == 1) total = ev.ms();
+      }
+      p->ms[sh] = total;
+      if (total < best) {
+        best = total;
+        shape = sh;
+      }
+    }
+    if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+    if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(PDQ_ERR_HIP);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg)] = shape;
+  }
+  p->shape = static_cast<uint32_t>(shape);
+  // capture the launch sequence on a private stream
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PDQ_ERR_HIP);
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_batched(c, L, base, shape, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cs, &g);
+    p->graph = g;
+    if (rc == PDQ_OK && e2 != hipSuccess) {
+      g_last_hip = static_cast<int>(e2);
+      rc = PDQ_ERR_HIP;
+    }
+    if (rc == PDQ_OK && (e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess) {
+      g_last_hip = static_cast<int>(e);
+      rc = PDQ_ERR_HIP;
+    }
+  } else {
+    g_last_hip = static_cast<int>(e);
+    rc = PDQ_ERR_HIP;
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != PDQ_OK) return fail(rc);
+  *plan = p;
+  return PDQ_OK;
+}
+
+int pdq_plan_launch(pdq_plan* plan, void* stream) {
+  g_last_hip = 0;
+  if (!plan || !plan->exec) return PDQ_ERR_INVALID;
+  HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
+int pdq_plan_info(const pdq_plan* plan, uint32_t* shape, double* ms) {
+  if (!plan) return PDQ_ERR_INVALID;
+  if (shape) *shape = plan->shape;
+  if (ms)
+    for (int i = 0; i < kBatchShapes; ++i) ms[i] = plan->ms[i];
+  return PDQ_OK;
+}
+
+void pdq_plan_destroy(pdq_plan* plan) {
+  if (!plan) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
+}
 
 // ---- learned first pass, step by step (pdq_learned.h) ----------------------
 

@@ -97,7 +97,7 @@ struct Ctx {
   uint32_t key_type;
   uint32_t has_vals;
   uint32_t single;      // 1: one segment [0, n) (records the first partition)
-  uint32_t pad0_;
+  uint32_t device_counts;  // 1: base-case launches take their item counts from ctr (grid is an upper bound)
   uint64_t seed;        // seeds the candidate positions taken after a bad partition
 };
 

@@ -1,0 +1,106 @@
+// Pivot choice and heapsort fallback of one segment, shared by the
+// pass-based partition sort and the batched segmented sort.
+#pragma once
+
+#include "pdq_internal.h"
+
+namespace pdq {
+
+template <class K>
+struct PivotChoice {
+  typename K::T raw;  // pivot key bits
+  uint64_t pidx;      // its absolute position in the source buffer
+  uint32_t mode;      // kModeRight / kModeLeft
+};
+
+// Tukey's ninther, the median of the medians of three triples (Section 2).
+// Normally the triples are (first, mid, last), (first+1, mid-1, last-1),
+// (first+2, mid+1, last-2). After a bad partition the segment takes fresh
+// candidates (Section 4.2) at nine positions drawn from a counter-based hash
+// of (seed, begin, end) -- the randomised form of the fresh-candidate rule.
+// The fixed 25%/75% positions of the deterministic form are not used here:
+// an out-of-place partition that keeps order keeps periodic input structure
+// intact, so fixed offsets can keep landing on equally bad candidates pass
+// after pass. Then the predecessor rule of Section 3 selects partition_left
+// when the predecessor is not below the pivot; the predecessor is an
+// ancestor's pivot and already sits at its final place in the user buffer
+// (Lemma 1). Segments have more than 4096 keys, so every offset is in range.
+template <class K>
+__device__ __forceinline__ PivotChoice<K> choose_pivot(const typename K::T* keys, const typename K::T* user,
+                                                       uint64_t b, uint64_t e, uint32_t flags, uint64_t seed) {
+  using T = typename K::T;
+  const uint64_t size = e - b;
+  const uint64_t m = size / 2;
+  uint64_t off[9] = {0, m, size - 1, 1, m - 1, size - 2, 2, m + 1, size - 3};
+  if (flags & kSegFresh) {
+    const uint64_t h0 = mix64(seed ^ mix64(b ^ mix64(e)));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) off[k] = mix64(h0 + static_cast<uint64_t>(k)) % size;
+  }
+  T raw[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) raw[k] = keys[b + off[k]];
+  uint64_t mo[3], mp[3];
+  T mr[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const uint64_t o0 = K::ord(raw[3 * t]), o1 = K::ord(raw[3 * t + 1]), o2 = K::ord(raw[3 * t + 2]);
+    int sel;
+    if (o0 < o1) sel = (o1 < o2) ? 1 : ((o0 < o2) ? 2 : 0);
+    else sel = (o0 < o2) ? 0 : ((o1 < o2) ? 2 : 1);
+    mo[t] = sel == 0 ? o0 : (sel == 1 ? o1 : o2);
+    mp[t] = off[3 * t + sel];
+    mr[t] = raw[3 * t + sel];
+  }
+  int sel;
+  if (mo[0] < mo[1]) sel = (mo[1] < mo[2]) ? 1 : ((mo[0] < mo[2]) ? 2 : 0);
+  else sel = (mo[0] < mo[2]) ? 0 : ((mo[1] < mo[2]) ? 2 : 1);
+  PivotChoice<K> pc;
+  pc.raw = mr[sel];
+  pc.pidx = b + mp[sel];
+  pc.mode = kModeRight;
+  if (!(flags & kSegLeftmost)) {
+    const T pred = user[b - 1];
+    if (!(static_cast<uint64_t>(K::ord(pred)) < mo[sel])) pc.mode = kModeLeft;
+  }
+  return pc;
+}
+
+// Williams' heapsort of a[0..len) (and payloads v, if any) by one lane.
+template <class K>
+__device__ void sift_down(typename K::T* a, uint32_t* v, uint64_t root, uint64_t n) {
+  for (;;) {
+    uint64_t child = 2 * root + 1;
+    if (child >= n) return;
+    if (child + 1 < n && K::ord(a[child]) < K::ord(a[child + 1])) ++child;
+    if (!(K::ord(a[root]) < K::ord(a[child]))) return;
+    typename K::T t = a[root];
+    a[root] = a[child];
+    a[child] = t;
+    if (v) {
+      uint32_t tv = v[root];
+      v[root] = v[child];
+      v[child] = tv;
+    }
+    root = child;
+  }
+}
+
+template <class K>
+__device__ void heapsort_range(typename K::T* a, uint32_t* v, uint64_t len) {
+  if (len < 2) return;
+  for (uint64_t r = len / 2; r-- > 0;) sift_down<K>(a, v, r, len);
+  for (uint64_t end = len - 1; end > 0; --end) {
+    typename K::T t = a[0];
+    a[0] = a[end];
+    a[end] = t;
+    if (v) {
+      uint32_t tv = v[0];
+      v[0] = v[end];
+      v[end] = tv;
+    }
+    sift_down<K>(a, v, 0, end);
+  }
+}
+
+}  // namespace pdq

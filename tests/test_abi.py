@@ -150,3 +150,26 @@ def test_learned_entry_point_errors_without_gpu(pdq):
     fb = pdq.FitBuffers()
     assert L.pdq_learned_fit(vp(0x1000), n, 1, vp(0x100000), 1 << 30, None, None, ctypes.byref(fb)) == -1
     assert L.pdq_learned_fit_workspace_bytes(None) > 0
+
+
+def test_struct_layouts_match_header(pdq, tmp_path):
+    """The ctypes mirrors of pdq_options / pdq_stats have the header's size and
+    field offsets (compiled with the host C compiler)."""
+    import ctypes
+    fields_o = [f for f, _ in pdq.Options._fields_]
+    fields_s = [f for f, _ in pdq.Stats._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdq.h"', 'int main(void) {',
+             'printf("%zu %zu\\n", sizeof(pdq_options), sizeof(pdq_stats));']
+    lines += [f'printf("%zu\\n", offsetof(pdq_options, {f}));' for f in fields_o]
+    lines += [f'printf("%zu\\n", offsetof(pdq_stats, {f}));' for f in fields_s]
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(pdq.Options) and vals[1] == ctypes.sizeof(pdq.Stats)
+    offs = vals[2:]
+    assert offs[:len(fields_o)] == [getattr(pdq.Options, f).offset for f in fields_o]
+    assert offs[len(fields_o):] == [getattr(pdq.Stats, f).offset for f in fields_s]

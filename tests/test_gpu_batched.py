@@ -1,0 +1,190 @@
+"""The batched segmented sort (one persistent launch over a device queue, and
+its captured HIP-graph plan) against the CPU oracle, through the C ABI.
+
+Keys must match the oracle bit for bit; payloads must be a valid
+permutation that stays inside its segment. Segment sizes cover every path
+of the persistent kernel: base-case lists (<= 4096), one LDS network
+(<= 16384 with 1024 threads, <= 8192 with 512), and single-workgroup
+partitions with queued children above that."""
+import numpy as np
+import pytest
+
+import gen.workloads as W
+import oracle
+import paper_2106_05123_amd as pdq
+from tests._util import as_bytes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pdq.lib()
+    return torch.device("cuda:0")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+EDGE_SIZES = [0, 1, 2, 3, 63, 64, 65, 256, 1000, 4095, 4096, 4097, 5000, 8191, 8192, 8193, 16383, 16384, 16385,
+              20000, 65536, 100003, 300000]
+
+
+def mixed_sizes(seed, extra=300, max_log2=16):
+    rng = np.random.default_rng(seed)
+    sizes = np.concatenate([EDGE_SIZES, W.segment_sizes_loguniform(extra, max_log2, seed)])
+    return sizes[rng.permutation(sizes.size)].astype(np.int64)
+
+
+def check_segmented(keys, off, out, vals_out=None):
+    ref, _, _ = oracle.segmented_sort(keys, off)
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+    if vals_out is not None:
+        cnt = np.bincount(vals_out.astype(np.int64), minlength=keys.size)
+        assert cnt.size == keys.size and np.all(cnt == 1)
+        assert np.array_equal(as_bytes(out), as_bytes(keys[vals_out]))
+        seg_of = np.searchsorted(off, np.arange(keys.size, dtype=np.uint64), side="right") - 1
+        assert np.array_equal(seg_of[vals_out], seg_of)
+
+
+def run_batched(keys, off, vals=None, **kw):
+    t, o = dev(keys), dev(off)
+    v = dev(vals) if vals is not None else None
+    st = pdq.segmented_sort_(t, o, v, batched=True, stats=True, **kw)
+    return host(t), (host(v) if v is not None else None), st
+
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_batched_mixed_sizes(kt, pairs):
+    off = W.offsets_from_sizes(mixed_sizes(7))
+    n = int(off[-1])
+    keys = W.random_keys(kt, n, seed=5)
+    vals = W.index_payload(n) if pairs else None
+    out, vo, st = run_batched(keys, off, vals)
+    check_segmented(keys, off, out, vo)
+    assert st["batch_items"] >= int(np.count_nonzero(np.diff(off) > 4096))
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
+def test_batched_every_shape(shape):
+    off = W.offsets_from_sizes(mixed_sizes(11, extra=100))
+    n = int(off[-1])
+    keys = W.random_keys("f32", n, seed=2)
+    vals = W.index_payload(n)
+    out, vo, st = run_batched(keys, off, vals, batch_shape=shape)
+    assert st["batch_shape"] == shape - 1
+    check_segmented(keys, off, out, vo)
+
+
+def test_batched_segmented_f32_workload():
+    keys, off, vals = W.segmented_f32(3000, max_log2=16, seed=4)
+    out, vo, st = run_batched(keys, off, vals)
+    check_segmented(keys, off, out, vo)
+
+
+@pytest.mark.parametrize("pattern", ["ascending", "descending", "equal", "organ_pipe", "two_values", "sawtooth"])
+def test_batched_patterns_and_equal_keys(pattern):
+    sizes = np.array([5000, 20000, 70000, 131072, 3000, 17000], dtype=np.int64)
+    off = W.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    parts = []
+    rng = np.random.default_rng(1)
+    for sz in sizes:
+        if pattern == "ascending":
+            parts.append(np.arange(sz, dtype=np.int32))
+        elif pattern == "descending":
+            parts.append(np.arange(sz, dtype=np.int32)[::-1].copy())
+        elif pattern == "equal":
+            parts.append(np.full(sz, 7, dtype=np.int32))
+        elif pattern == "organ_pipe":
+            i = np.arange(sz)
+            parts.append(np.where(i < sz // 2, i, sz - 1 - i).astype(np.int32))
+        elif pattern == "two_values":
+            parts.append(rng.integers(0, 2, sz).astype(np.int32))
+        else:
+            parts.append((np.arange(sz) % 1000).astype(np.int32))
+    keys = np.concatenate(parts)
+    vals = W.index_payload(n)
+    out, vo, st = run_batched(keys, off, vals)
+    check_segmented(keys, off, out, vo)
+    if pattern in ("ascending", "descending"):
+        assert st["sorted_segments"] >= 3  # the queued segments were retired as ordered runs
+
+
+def test_batched_forced_heapsort():
+    sizes = np.array([17000, 5000, 20000, 300], dtype=np.int64)
+    off = W.offsets_from_sizes(sizes)
+    keys = W.uniform_u32(int(off[-1]), seed=3)
+    vals = W.index_payload(keys.size)
+    out, vo, st = run_batched(keys, off, vals, force_budget=0)
+    assert st["heapsort_segments"] >= 2
+    check_segmented(keys, off, out, vo)
+
+
+def test_batched_validate_rejects_bad_offsets():
+    a = W.uniform_u32(1000, seed=1)
+    bad = np.array([0, 600, 400, 1000], dtype=np.uint64)
+    with pytest.raises(pdq.PdqError) as ei:
+        pdq.segmented_sort_(dev(a), dev(bad), batched=True, validate=True)
+    assert ei.value.status == -1
+
+
+def test_plan_graph_replays_with_refilled_inputs():
+    """One captured plan (autotuned), replayed on three different inputs in
+    the same buffers, with eager work and synchronisation between replays;
+    every replay is checked against the oracle and against the eager
+    batched call."""
+    keys0, off, vals0 = W.segmented_f32(1500, max_log2=16, seed=9)
+    n = keys0.size
+    tk, to, tv = dev(keys0), dev(off), dev(vals0)
+    plan = pdq.Plan(tk, to, tv, autotune=True)
+    shape, ms = plan.info()
+    assert 0 <= shape < 4 and ms[shape] > 0 and ms[shape] == min(m for m in ms if m > 0)
+    # autotuning restored the caller's data
+    assert np.array_equal(host(tk).view(np.uint32), keys0.view(np.uint32))
+    assert np.array_equal(host(tv), vals0)
+    for rep in range(3):
+        keys = W.random_keys("f32", n, seed=100 + rep)  # new keys, same segments
+        tk.copy_(dev(keys))
+        tv.copy_(dev(vals0))
+        plan.launch()
+        out, vo = host(tk), host(tv)
+        check_segmented(keys, off, out, vo)
+        ek, ev = dev(keys), dev(vals0)
+        pdq.segmented_sort_(ek, to, ev, batched=True, batch_shape=shape + 1)
+        assert np.array_equal(host(ek).view(np.uint32), out.view(np.uint32))
+        _ = torch.ones(1000, device="cuda:0").sum().item()  # eager work between replays
+    plan.destroy()
+
+
+def test_batched_full_workload_sampled():
+    """The 65,536-segment float32 + payload workload in the benchmark's
+    configuration: every segment sorted by canonical order, payloads a
+    permutation that stays in its segment, keys a permutation (hash)."""
+    from tests._util import multiset_hash
+    keys, off, vals = W.segmented_f32(65536, max_log2=16, seed=0)
+    tk, to, tv = dev(keys), dev(off), dev(vals)
+    st = pdq.segmented_sort_(tk, to, tv, batched=True, stats=True)
+    out, vo = host(tk), host(tv)
+    del tk, tv
+    torch.cuda.empty_cache()
+    img = np.where(out.view(np.uint32) >> 31 == 1, ~out.view(np.uint32), out.view(np.uint32) | np.uint32(0x80000000))
+    desc = img[1:] < img[:-1]
+    starts = np.zeros(out.size, dtype=bool)
+    starts[off[:-1][off[:-1] < out.size].astype(np.int64)] = True
+    assert not np.any(desc & ~starts[1:])
+    assert multiset_hash(out) == multiset_hash(keys)
+    assert np.array_equal(np.sort(vo), np.arange(out.size, dtype=np.uint32))
+    assert np.array_equal(out.view(np.uint32), keys[vo].view(np.uint32))
+    assert st["batch_items"] > 0
