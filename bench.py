@@ -297,17 +297,20 @@ def bench_segmented(pdq, torch, W, dev, args):
     po = torch.from_numpy(off).to(dev)
     wk = torch.empty_like(pk)
     wv = torch.empty_like(pv)
-    ws = torch.empty(pdq.workspace_bytes(n, args.seg_count, "f32", has_vals=True), dtype=torch.uint8, device=dev)
+    topt = pdq.Options(ctypes.sizeof(pdq.Options), pdq.FLAG_BATCHED | pdq.FLAG_AUTOTUNE, -1, 0, 0, 0.0, 0, 0, 0, 0)
+    ws = torch.empty(pdq.workspace_bytes(n, args.seg_count, "f32", has_vals=True, options=topt),
+                     dtype=torch.uint8, device=dev)
+    steps = max(3, args.steps)
 
-    def run(steps, profile):
+    def timed(fn, reps, profile):
         ms, stats = [], []
-        for _ in range(steps):
+        for _ in range(reps):
             wk.copy_(pk)
             wv.copy_(pv)
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            st = pdq.segmented_sort_(wk, po, wv, workspace=ws, profile=profile, stats=profile)
+            st = fn(profile)
             b.record()
             b.synchronize()
             ms.append(a.elapsed_time(b))
@@ -315,25 +318,52 @@ def bench_segmented(pdq, torch, W, dev, args):
                 stats.append(st)
         return ms, stats
 
-    run(1, False)
-    ms, stats = run(max(2, args.steps // 2), True)
-    # output check on one segment boundary sample: every segment sorted
-    kk = wk.view(torch.int32).to(torch.int64)
-    img = torch.where(kk < 0, ~kk & 0xFFFFFFFF, kk | 0x80000000)
-    starts = po[:-1].to(torch.int64)
-    desc = (img[1:] < img[:-1])
-    seg_start = torch.zeros(n, dtype=torch.bool, device=dev)
-    seg_start[starts[starts < n]] = True
-    if bool((desc & ~seg_start[1:]).any().item()):
-        raise SystemExit("bench: segmented output not sorted within segments")
-    s0 = stats[0]
-    mean = float(np.mean(ms))
+    def check(what):
+        kk = wk.view(torch.int32).to(torch.int64)
+        img = torch.where(kk < 0, ~kk & 0xFFFFFFFF, kk | 0x80000000)
+        starts = po[:-1].to(torch.int64)
+        seg_start = torch.zeros(n, dtype=torch.bool, device=dev)
+        seg_start[starts[starts < n]] = True
+        bad = bool(((img[1:] < img[:-1]) & ~seg_start[1:]).any().item())
+        same = int(wv.to(torch.int64).sum()) == n * (n - 1) // 2
+        del kk, img
+        if bad or not same:
+            raise SystemExit(f"bench: segmented output ({what}) not sorted within segments")
+
+    plain = lambda prof: pdq.segmented_sort_(wk, po, wv, workspace=ws, profile=prof, stats=prof)
+    timed(plain, 1, False)
+    check("plain")
+    ms_p, st_p = timed(plain, steps, True)
+    log("segmented: autotuning the batched plan")
+    wk.copy_(pk)
+    wv.copy_(pv)
+    plan = pdq.Plan(wk, po, wv, autotune=True, workspace=ws)
+    shape, tune_ms = plan.info()
+    eager = lambda prof: pdq.segmented_sort_(wk, po, wv, workspace=ws, batched=True, batch_shape=shape + 1,
+                                             profile=prof, stats=prof)
+    timed(eager, 1, False)
+    check("batched")
+    ms_b, st_b = timed(eager, steps, True)
+    graph = lambda prof: plan.launch()
+    timed(graph, 1, False)
+    check("graph")
+    ms_g, _ = timed(graph, steps, False)
+    plan.destroy()
+    s0 = st_p[0]
+    mp, mb, mg = float(np.mean(ms_p)), float(np.mean(ms_b)), float(np.mean(ms_g))
     return {"workload": f"{args.seg_count} segments, log-uniform sizes 1..2^16, float32 N(0,1) keys with 5% "
                         f"duplicates and signed zeros, uint32 payloads (seed 0)",
-            "n": n, "plain": {"keys/s": round(n / (mean * 1e-3), 0), "ms": round(mean, 3),
-                              "passes": s0["passes"], "partition_ms": round(s0["partition_ms"], 3),
-                              "partition_GBps": round(s0["partition_bytes"] / (s0["partition_ms"] * 1e-3) / 1e9, 1)
-                              if s0["partition_ms"] else None}}
+            "n": n,
+            "plain": {"keys/s": round(n / (mp * 1e-3), 0), "ms": round(mp, 3), "passes": s0["passes"],
+                      "partition_ms": round(s0["partition_ms"], 3),
+                      "partition_GBps": round(s0["partition_bytes"] / (s0["partition_ms"] * 1e-3) / 1e9, 1)
+                      if s0["partition_ms"] else None},
+            "batched_eager": {"keys/s": round(n / (mb * 1e-3), 0), "ms": round(mb, 3),
+                              "queue_items": st_b[0]["batch_items"], "shape": list(pdq.BATCH_SHAPES[shape])},
+            "batched_graph": {"keys/s": round(n / (mg * 1e-3), 0), "ms": round(mg, 3),
+                              "shape": list(pdq.BATCH_SHAPES[shape]),
+                              "autotune_ms_per_shape": [round(x, 3) for x in tune_ms]},
+            "batched_over_plain": round(mp / mg, 3)}
 
 
 def _cpu_model() -> str:

@@ -405,6 +405,7 @@ class Plan:
 
     def __init__(self, keys, offsets, vals=None, *, autotune: bool = False, batch_shape: int = 0,
                  force_budget: int = -1, workspace=None):
+        # the workspace must be sized with the same flags (batched, autotune)
         import torch
         if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
             raise ValueError("offsets must be a contiguous uint64 device tensor")

@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kBinStride) void k_chunk_sum(BucketBufs b) {
   const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
   const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
   uint32_t sum = 0;
+#pragma unroll 16
   for (uint64_t r = r0; r < r1; ++r) sum += b.rows[r * kBinStride + threadIdx.x];
   b.chunk[static_cast<uint64_t>(blockIdx.x) * kBinStride + threadIdx.x] = sum;
 }
@@ -138,11 +139,16 @@ __global__ __launch_bounds__(kBinStride) void k_chunk_scan(BucketBufs b) {
   __shared__ uint32_t s_wsum[kBinStride / 64];
   const uint32_t tid = threadIdx.x;
   uint64_t run = 0;
-  for (uint64_t c = 0; c < b.nchunks; ++c) {
-    uint32_t* p = b.chunk + c * kBinStride + tid;
-    const uint32_t v = *p;
-    *p = static_cast<uint32_t>(run);
-    run += v;
+  // sixteen independent loads in flight, then their running sums
+  for (uint64_t c0 = 0; c0 < b.nchunks; c0 += 16) {
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = c0 + q < b.nchunks ? b.chunk[(c0 + q) * kBinStride + tid] : 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (c0 + q < b.nchunks) b.chunk[(c0 + q) * kBinStride + tid] = static_cast<uint32_t>(run);
+      run += v[q];
+    }
   }
   b.totals[tid] = run;
   s_tot[tid] = static_cast<uint32_t>(run);
@@ -157,11 +163,15 @@ __global__ __launch_bounds__(kBinStride) void k_tile_rescan(BucketBufs b) {
   const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
   const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
   uint32_t run = static_cast<uint32_t>(b.begin[threadIdx.x]) + b.chunk[static_cast<uint64_t>(blockIdx.x) * kBinStride + threadIdx.x];
-  for (uint64_t r = r0; r < r1; ++r) {
-    uint32_t* p = b.rows + r * kBinStride + threadIdx.x;
-    const uint32_t v = *p;
-    *p = run;
-    run += v;
+  for (uint64_t r0b = r0; r0b < r1; r0b += 16) {
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = r0b + q < r1 ? b.rows[(r0b + q) * kBinStride + threadIdx.x] : 0u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (r0b + q < r1) b.rows[(r0b + q) * kBinStride + threadIdx.x] = run;
+      run += v[q];
+    }
   }
 }
 

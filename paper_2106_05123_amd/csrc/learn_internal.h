@@ -25,7 +25,7 @@ constexpr uint32_t kTrainThreads = 1024;
 constexpr uint32_t kTrainChunk = 64;             // samples a training workgroup handles at a time
 constexpr uint32_t kBucketTile = 8192;           // keys per histogram / scatter tile
 constexpr uint32_t kBucketThreads = 512;
-constexpr uint32_t kScanRows = 64;               // tile rows per scan chunk
+constexpr uint32_t kScanRows = 256;              // tile rows per scan chunk
 
 struct TrainArgs {
   const float* x;         // features of the sorted sample [m]
