@@ -109,7 +109,7 @@ typedef struct pdq_options {
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
-                            1024x8, 1024x16, 512x8, 512x16 (threads x tile rows) */
+                            512x8, 512x16, 1024x8, 1024x16 (threads x tile rows) */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */

@@ -39,7 +39,7 @@ FLAG_PROFILE = 2
 FLAG_LEARNED = 4
 FLAG_BATCHED = 8
 FLAG_AUTOTUNE = 16
-BATCH_SHAPES = ((1024, 8), (1024, 16), (512, 8), (512, 16))
+BATCH_SHAPES = ((512, 8), (512, 16), (1024, 8), (1024, 16))
 MLP_PARAMS = 1153
 MAX_SPLITTERS = 255
 LEARN_SAMPLE = 65536

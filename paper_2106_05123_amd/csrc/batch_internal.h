@@ -42,7 +42,7 @@ struct BatchShape {
 };
 
 constexpr int kBatchShapes = 4;
-constexpr BatchShape kShapes[kBatchShapes] = {{1024, 8}, {1024, 16}, {512, 8}, {512, 16}};
+constexpr BatchShape kShapes[kBatchShapes] = {{512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
 
 struct BatchArgs {
   BatchQ* q;

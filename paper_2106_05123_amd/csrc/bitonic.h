@@ -163,5 +163,71 @@ __device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh
   }
 }
 
+// Merge sort of P = E * NT slots. On entry lane tid holds slots
+// [tid*E, tid*E + E) in any order; on exit the same positions of the sorted
+// sequence. Each lane first sorts its E registers (a bitonic network inside
+// the lane), then log2(NT) merge levels double the sorted run length: all
+// runs go to LDS, and each lane produces its E outputs of the merged pair by
+// a merge-path binary search for its starting split followed by E steps of a
+// sequential merge, one LDS read per step (ties taken from the left run).
+template <class S, int E, int NT>
+__device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char* sh, int tid) {
+  using V = typename S::V;
+  constexpr int e = ilog2(E);
+  constexpr int P = E * NT;
+  constexpr int PL = lds_plane<P, E>();
+  // runs of E inside each lane
+#pragma unroll
+  for (int kb = 1; kb <= e; ++kb) {
+#pragma unroll
+    for (int b = kb - 1; b >= 0; --b) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        if (r & (1 << b)) continue;
+        const int r2 = r | (1 << b);
+        const bool up = ((r >> kb) & 1) == 0;
+        const V a = x[r], c = x[r2];
+        const bool sw = S::lt(c, a) == up;
+        x[r] = sw ? c : a;
+        x[r2] = sw ? a : c;
+      }
+    }
+  }
+  const V pad = S::pad();
+  for (int run = E; run < P; run <<= 1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>(tid * E + r), x[r]);
+    __syncthreads();
+    const int o = (tid * E) & (2 * run - 1);  // output position inside the merged pair
+    const int pa = tid * E - o;               // start of the left run; the right run follows it
+    const int pb = pa + run;
+    int lo = o > run ? o - run : 0, hi = o < run ? o : run;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      // left[mid] <= right[o - mid - 1]: left[mid] is merged before position o
+      if (!S::lt(S::ld(sh, PL, lds_pos<E>(pb + o - mid - 1)), S::ld(sh, PL, lds_pos<E>(pa + mid)))) lo = mid + 1;
+      else hi = mid;
+    }
+    int i = lo, j = o - lo;
+    V a = i < run ? S::ld(sh, PL, lds_pos<E>(pa + i)) : pad;
+    V c = j < run ? S::ld(sh, PL, lds_pos<E>(pb + j)) : pad;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const bool take_left = !S::lt(c, a);
+      x[r] = take_left ? a : c;
+      if (take_left) ++i;
+      else ++j;
+      if (r + 1 < E) {
+        const bool more = take_left ? i < run : j < run;
+        const int at = take_left ? pa + i : pb + j;
+        const V nv = more ? S::ld(sh, PL, lds_pos<E>(at)) : pad;
+        a = take_left ? nv : a;
+        c = take_left ? c : nv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace net
 }  // namespace pdq

@@ -45,7 +45,8 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls) {
   for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
   __syncthreads();
 
-  net::bitonic<S, E, NT>(x, sh, tid);
+  if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
+  else net::bitonic<S, E, NT>(x, sh, tid);
 
   // back through LDS so that the final writes are coalesced
 #pragma unroll

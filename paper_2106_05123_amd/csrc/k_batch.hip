@@ -165,8 +165,9 @@ __global__ __launch_bounds__(256) void k_batch_prepare(Ctx c, BatchArgs b) {
 // ---------------------------------------------------------------- persistent kernel
 
 // LDS sort of in[0..len) into out[0..len) by NTS threads holding E slots
-// each (the base case's network). With NTS == 64 only wave 0 takes part and
-// the network has no workgroup barrier.
+// each (the base case's merge sort, or its bitonic network below 1024
+// slots). With NTS == 64 only wave 0 takes part and nothing waits at a
+// workgroup barrier.
 template <class K, bool PAIRS, int E, int NTS>
 __device__ void lds_sort(const typename K::T* in, const uint32_t* vin, typename K::T* out, uint32_t* vout, int len,
                          unsigned char* sh) {
@@ -195,7 +196,8 @@ __device__ void lds_sort(const typename K::T* in, const uint32_t* vin, typename 
 #pragma unroll
   for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, net::lds_pos<E>((tid << net::ilog2(E)) | r));
   sync();
-  net::bitonic<S, E, NTS>(x, sh, tid);
+  if constexpr (P >= 1024) net::merge_sort<S, E, NTS>(x, sh, tid);
+  else net::bitonic<S, E, NTS>(x, sh, tid);
 #pragma unroll
   for (int r = 0; r < E; ++r) S::st(sh, PL, net::lds_pos<E>((tid << net::ilog2(E)) | r), x[r]);
   sync();
@@ -232,7 +234,8 @@ struct Batch {
   using T = typename K::T;
   using S = net::Slot<K, PAIRS>;
   static constexpr int NW = NT / 64;
-  static constexpr int EB = (sizeof(T) == 8 && PAIRS) ? 8 : 16;  // largest network: NT * EB slots
+  // largest network: NT * EB slots (8 per lane at 1024 lanes, where a lane has 128 VGPRs)
+  static constexpr int EB = (NT >= 1024 || (sizeof(T) == 8 && PAIRS)) ? 8 : 16;
   static constexpr int kLdsMax = NT * EB;
   static constexpr int kSortBytes = net::lds_plane<NT * EB, EB>() * S::kLdsBytes;
   static constexpr int kCells = IT * NW;  // (row, wave) cells of a partition tile
@@ -246,7 +249,7 @@ struct Batch {
 template <class K, bool PAIRS, int NT>
 __device__ void sort_segment(const Ctx& c, uint64_t b, uint64_t e, uint32_t buf, unsigned char* sh) {
   using T = typename K::T;
-  constexpr int EB = (sizeof(T) == 8 && PAIRS) ? 8 : 16;
+  constexpr int EB = Batch<K, PAIRS, NT, 8>::EB;
   const int len = static_cast<int>(e - b);
   const T* in = static_cast<const T*>(c.keys[buf]) + b;
   T* out = static_cast<T*>(c.keys[0]) + b;
@@ -525,10 +528,10 @@ __global__ __launch_bounds__(NT) void k_batch(Ctx c, BatchArgs bq) {
 template <class K, bool PAIRS>
 hipError_t run_shape(const Ctx& c, const BatchArgs& b, int shape, uint32_t grid, hipStream_t s) {
   switch (shape) {
-    case 0: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 8>), dim3(grid), dim3(1024), 0, s, c, b); break;
-    case 1: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 16>), dim3(grid), dim3(1024), 0, s, c, b); break;
-    case 2: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 8>), dim3(grid), dim3(512), 0, s, c, b); break;
-    case 3: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 16>), dim3(grid), dim3(512), 0, s, c, b); break;
+    case 0: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 8>), dim3(grid), dim3(512), 0, s, c, b); break;
+    case 1: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 16>), dim3(grid), dim3(512), 0, s, c, b); break;
+    case 2: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 8>), dim3(grid), dim3(1024), 0, s, c, b); break;
+    case 3: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 16>), dim3(grid), dim3(1024), 0, s, c, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -537,10 +540,10 @@ hipError_t run_shape(const Ctx& c, const BatchArgs& b, int shape, uint32_t grid,
 template <class K, bool PAIRS>
 const void* kernel_of(int shape) {
   switch (shape) {
-    case 0: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 8>);
-    case 1: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 16>);
-    case 2: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 8>);
-    case 3: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 16>);
+    case 0: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 8>);
+    case 1: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 16>);
+    case 2: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 8>);
+    case 3: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 16>);
     default: return nullptr;
   }
 }
@@ -572,7 +575,7 @@ hipError_t launch_batch_prepare(const Ctx& c, const BatchArgs& b, uint32_t cap, 
 uint32_t batch_lds_max(const Ctx& c, int shape) {
   const uint32_t nt = kShapes[shape].nt;
   const bool wide_pairs = c.key_type == 4 && c.has_vals;
-  return nt * (wide_pairs ? 8u : 16u);
+  return nt * ((nt >= 1024 || wide_pairs) ? 8u : 16u);
 }
 
 uint32_t batch_grid(const Ctx& c, int shape) {
