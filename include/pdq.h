@@ -109,7 +109,12 @@ typedef struct pdq_options {
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
-                            512x8, 512x16, 1024x8, 1024x16 (threads x tile rows) */
+                            (partition tile, slots per lane of the two widest LDS classes):
+                            (16384, 16), (32768, 16), (8192, 16), (16384, 32) */
+  uint32_t batch_passes; /* PDQ_BATCHED: 0 = automatic (the halvings that bring the largest
+                            segment to the widest LDS class, plus 2); k > 0 = k - 1 passes (at
+                            most 20); segments still live after them finish in the persistent
+                            tail */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */

@@ -58,6 +58,7 @@ class Options(ctypes.Structure):
         ("learn_batch", ctypes.c_uint32),
         ("learn_grid", ctypes.c_uint32),
         ("batch_shape", ctypes.c_uint32),
+        ("batch_passes", ctypes.c_uint32),
     ]
 
 
@@ -195,9 +196,10 @@ def _key_type(t) -> int:
 
 
 def _options(force_budget: int, tile: int, flags: int, seed: int = 0, imbalance_limit: float = 0.0,
-             learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, batch_shape: int = 0) -> Options:
+             learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, batch_shape: int = 0,
+             batch_passes: int | None = None) -> Options:
     return Options(ctypes.sizeof(Options), flags, force_budget, tile, seed, imbalance_limit, learn_steps,
-                   learn_batch, learn_grid, batch_shape)
+                   learn_batch, learn_grid, batch_shape, 0 if batch_passes is None else batch_passes + 1)
 
 
 def workspace_bytes(n: int, nseg: int = 1, key_type: int | str = "u32", has_vals: bool = False,
@@ -269,17 +271,18 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
 
 def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: int = 0,
                     validate: bool = False, profile: bool = False, stats: bool = False, workspace=None,
-                    batched: bool = False, batch_shape: int = 0):
+                    batched: bool = False, batch_shape: int = 0, batch_passes: int | None = None):
     """Sort each segment [offsets[s], offsets[s+1]) of keys in place.
     offsets: uint64 device tensor of nseg+1 entries. batched=True runs the
-    persistent device-queue form (batch_shape 1..4 forces a shape)."""
+    batched form (batch_shape 1..4 forces a shape, batch_passes the number of
+    partition passes before the persistent tail; None = automatic)."""
     import torch
     if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
         raise ValueError("offsets must be a contiguous uint64 device tensor")
     nseg = offsets.numel() - 1
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0)
     kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace,
-                                         dict(batch_shape=batch_shape))
+                                         dict(batch_shape=batch_shape, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_segmented_sort(ctypes.c_void_p(keys.data_ptr()),
                                   ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,
@@ -404,7 +407,7 @@ class Plan:
     pdq_plan_create). launch() replays the graph on the current stream."""
 
     def __init__(self, keys, offsets, vals=None, *, autotune: bool = False, batch_shape: int = 0,
-                 force_budget: int = -1, workspace=None):
+                 batch_passes: int | None = None, force_budget: int = -1, workspace=None):
         # the workspace must be sized with the same flags (batched, autotune)
         import torch
         if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
@@ -412,7 +415,7 @@ class Plan:
         nseg = offsets.numel() - 1
         flags = FLAG_BATCHED | (FLAG_AUTOTUNE if autotune else 0)
         kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, 0, flags, workspace,
-                                             dict(batch_shape=batch_shape))
+                                             dict(batch_shape=batch_shape, batch_passes=batch_passes))
         self._keep = (keys, offsets, vals, ws)
         self._h = ctypes.c_void_p()
         _check(lib().pdq_plan_create(ctypes.byref(self._h), _ptr(keys), _ptr(vals), keys.numel(), _ptr(offsets),

@@ -1,5 +1,6 @@
-// Internal declarations of the batched segmented sort: one persistent launch
-// works through a device queue of segments; not part of the public C ABI.
+// Internal declarations of the batched segmented sort (captured partition
+// passes with device-side counts, wide LDS classes, and a persistent tail
+// launch over a device queue); not part of the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,7 +10,7 @@
 
 namespace pdq {
 
-// One queued segment of more than kBaseMax keys: [begin, end) in buffer buf.
+// One queued segment: [begin, end) in buffer buf.
 struct BItem {
   uint64_t begin;
   uint64_t end;
@@ -34,15 +35,30 @@ struct BatchQ {
 
 constexpr uint32_t kErrQueue = 16u;  // a queue wait did not end (ring too small or a lost item)
 
-// Tunable shape of the persistent kernel: threads per workgroup and rows per
+// Shapes of the persistent tail kernel: threads per workgroup and rows per
 // partition tile (a tile is NT * IT keys).
-struct BatchShape {
+struct TailShape {
   uint32_t nt;
   uint32_t it;
 };
+constexpr int kTailShapes = 4;
+constexpr TailShape kTail[kTailShapes] = {{512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
 
+// Tunable shape of the batched form: the tile of the captured partition
+// passes, the slots per lane of the two widest LDS classes (16: 512 and 1024
+// threads for 8192 and 16384 keys; 32: 256 and 512 threads), and the tail
+// kernel's shape.
+struct BatchShape {
+  uint32_t tile;
+  uint32_t wide_e;
+  uint32_t tail;
+};
 constexpr int kBatchShapes = 4;
-constexpr BatchShape kShapes[kBatchShapes] = {{512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
+constexpr BatchShape kShapes[kBatchShapes] = {{16384, 16, 0}, {32768, 16, 0}, {8192, 16, 0}, {16384, 32, 0}};
+
+// Passes the batched form captures at most; deeper recursions finish in the
+// persistent tail.
+constexpr uint32_t kMaxBatchPasses = 20;
 
 struct BatchArgs {
   BatchQ* q;
@@ -50,11 +66,11 @@ struct BatchArgs {
   uint32_t* state;
 };
 
-hipError_t launch_batch_prepare(const Ctx& c, const BatchArgs& b, uint32_t cap, hipStream_t s);
-hipError_t launch_batch(const Ctx& c, const BatchArgs& b, int shape, uint32_t grid, hipStream_t s);
-// Largest segment the persistent kernel of this shape sorts in LDS at once.
-uint32_t batch_lds_max(const Ctx& c, int shape);
-// Workgroups of the persistent kernel that fit on the device at once.
-uint32_t batch_grid(const Ctx& c, int shape);
+hipError_t launch_batch_zero(const BatchArgs& b, uint32_t cap, hipStream_t s);
+hipError_t launch_batch_from_list(const Ctx& c, const BatchArgs& b, int parity, uint32_t src, hipStream_t s);
+hipError_t launch_batch(const Ctx& c, const BatchArgs& b, int tail, uint32_t grid, hipStream_t s);
+// Workgroups of the persistent kernel of this tail shape that fit on the
+// device at once.
+uint32_t batch_grid(const Ctx& c, int tail);
 
 }  // namespace pdq

@@ -1,5 +1,6 @@
-// LDS-resident base case: every segment of at most 4096 keys is sorted by
-// one workgroup and written to its final place in the user buffer.
+// LDS-resident base case: every segment of at most 4096 keys (16384 in the
+// batched form) is sorted by one workgroup and written to its final place in
+// the user buffer.
 //
 // The paper sorts small subsequences with insertion sort (Section 5.1) and
 // notes that sorting networks lost on its CPU through code size (Section 2);
@@ -18,84 +19,130 @@ using net::lds_plane;
 using net::lds_pos;
 using net::Slot;
 
-// One workgroup per base-case segment of at most E * NT keys.
+// One workgroup per base-case segment of at most E * NT keys; a workgroup
+// takes items blockIdx.x, blockIdx.x + gridDim.x, ... of its class list
+// (the list length comes from the device counters in the batched form).
 template <class K, bool PAIRS, int E, int NT>
-__global__ __launch_bounds__(NT) void k_base(Ctx c, int cls) {
+__global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   using T = typename K::T;
   using S = Slot<K, PAIRS>;
   using V = typename S::V;
   constexpr int P = E * NT;
   constexpr int PL = lds_plane<P, E>();
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
-  if (c.device_counts && blockIdx.x >= c.ctr->nbase[cls]) return;
-  const Item it = c.base[cls][blockIdx.x];
-  const int len = static_cast<int>(it.end - it.begin);
-  const int tid = threadIdx.x;
-  const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
+  // a list longer than its capacity (only invalid offsets make one; it is
+  // flagged) is read no further than its capacity
+  uint32_t count = c.device_counts ? c.ctr->nbase[cls] : nitems;
+  if (count > c.max_items) count = c.max_items;
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    // an opaque copy of the lane index keeps the per-slot addresses inside
+    // the loop instead of holding dozens of them in registers across items
+    int tid = static_cast<int>(threadIdx.x);
+    asm volatile("" : "+v"(tid));
+    const Item it = c.base[cls][item];
+    const int len = static_cast<int>(it.end - it.begin);
+    const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
 
-  // coalesced load into LDS, then each lane picks up its E consecutive slots
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int j = r * NT + tid;
-    S::st(sh, PL, lds_pos<E>(j), j < len ? S::make(in[j], static_cast<uint32_t>(j)) : S::pad());
-  }
-  __syncthreads();
-  V x[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
-  __syncthreads();
-
-  if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
-  else net::bitonic<S, E, NT>(x, sh, tid);
-
-  // back through LDS so that the final writes are coalesced
-#pragma unroll
-  for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
-  __syncthreads();
-  V y[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) y[r] = S::ld(sh, PL, lds_pos<E>(r * NT + tid));
-  T* out = static_cast<T*>(c.keys[0]) + it.begin;
-  if constexpr (PAIRS) {
-    // gather every payload before anything is written: the segment may be
-    // sorted in place, in the buffer the payloads are read from
-    const uint32_t* vin = c.vals[it.buf] + it.begin;
-    uint32_t pv[E];
+    // coalesced load into LDS, then each lane picks up its E consecutive slots
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int j = r * NT + tid;
-      pv[r] = j < len ? vin[S::idx(y[r])] : 0u;
+      S::st(sh, PL, lds_pos<E>(j), j < len ? S::make(in[j], static_cast<uint32_t>(j)) : S::pad());
     }
     __syncthreads();
-    uint32_t* vout = c.vals[0] + it.begin;
+    V x[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int j = r * NT + tid;
-      if (j < len) {
-        out[j] = S::key(y[r]);
-        vout[j] = pv[r];
+    for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
+    __syncthreads();
+
+    if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
+    else net::bitonic<S, E, NT>(x, sh, tid);
+
+    // back through LDS so that the final writes are coalesced
+#pragma unroll
+    for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
+    __syncthreads();
+    V y[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) y[r] = S::ld(sh, PL, lds_pos<E>(r * NT + tid));
+    T* out = static_cast<T*>(c.keys[0]) + it.begin;
+    if constexpr (PAIRS) {
+      // gather every payload before anything is written: the segment may be
+      // sorted in place, in the buffer the payloads are read from
+      const uint32_t* vin = c.vals[it.buf] + it.begin;
+      uint32_t pv[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int j = r * NT + tid;
+        pv[r] = j < len ? vin[S::idx(y[r])] : 0u;
+      }
+      __syncthreads();
+      uint32_t* vout = c.vals[0] + it.begin;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int j = r * NT + tid;
+        if (j < len) {
+          out[j] = S::key(y[r]);
+          vout[j] = pv[r];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int j = r * NT + tid;
+        if (j < len) out[j] = S::key(y[r]);
       }
     }
-  } else {
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int j = r * NT + tid;
-      if (j < len) out[j] = S::key(y[r]);
-    }
+    __syncthreads();  // LDS is rewritten by the next item
   }
+}
+
+// Workgroups of a base-case launch: one per item, or, with device counts,
+// as many as the device holds at once (each then loops over the list).
+template <class F>
+uint32_t base_grid(F* f, int nt, uint32_t nitems, bool device_counts) {
+  if (!device_counts) return nitems;
+  static thread_local int dev_cached = -1;
+  static thread_local int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev != dev_cached) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    dev_cached = dev;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, nt, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+  const uint64_t g = static_cast<uint64_t>(per_cu) * cus;
+  return static_cast<uint32_t>(g < nitems ? g : nitems);
+}
+
+template <class K, bool PAIRS, int E, int NT>
+hipError_t launch_shape(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
+  const uint32_t grid = base_grid(k_base<K, PAIRS, E, NT>, NT, nitems, c.device_counts != 0);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_base<K, PAIRS, E, NT>), dim3(grid), dim3(NT), 0, s, c, cls, nitems);
+  return hipGetLastError();
 }
 
 template <class K, bool PAIRS>
 hipError_t launch_cls(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
   switch (cls) {
-    case 0: hipLaunchKernelGGL((k_base<K, PAIRS, 1, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
-    case 1: hipLaunchKernelGGL((k_base<K, PAIRS, 4, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
-    case 2: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 64>), dim3(nitems), dim3(64), 0, s, c, cls); break;
-    case 3: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 128>), dim3(nitems), dim3(128), 0, s, c, cls); break;
-    case 4: hipLaunchKernelGGL((k_base<K, PAIRS, 16, 256>), dim3(nitems), dim3(256), 0, s, c, cls); break;
+    case 0: return launch_shape<K, PAIRS, 1, 64>(c, cls, nitems, s);
+    case 1: return launch_shape<K, PAIRS, 4, 64>(c, cls, nitems, s);
+    case 2: return launch_shape<K, PAIRS, 16, 64>(c, cls, nitems, s);
+    case 3: return launch_shape<K, PAIRS, 16, 128>(c, cls, nitems, s);
+    case 4: return launch_shape<K, PAIRS, 16, 256>(c, cls, nitems, s);
+    case 5:
+      return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 256>(c, cls, nitems, s)
+                            : launch_shape<K, PAIRS, 16, 512>(c, cls, nitems, s);
+    case 6:
+      // 64-bit keys with a payload need 12 LDS bytes a slot: their widest class is 8192
+      if constexpr (sizeof(typename K::T) == 8 && PAIRS) return hipErrorInvalidValue;
+      else
+        return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 512>(c, cls, nitems, s)
+                              : launch_shape<K, PAIRS, 16, 1024>(c, cls, nitems, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <class K>

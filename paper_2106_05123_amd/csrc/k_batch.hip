@@ -1,11 +1,9 @@
-// Batched segmented sort: one persistent launch works through a device
-// queue, so a whole batch of uneven segments is sorted without the host
-// reading anything back (and the launch sequence can be captured in a HIP
-// graph).
+// The persistent tail of the batched segmented sort. The captured partition
+// passes leave some segments live (those whose recursion is deeper than the
+// passes that were queued); this launch works through them with a device
+// queue, so the whole sort ends without the host reading anything back.
 //
-//   prepare   segments of at most 4096 keys go to the base-case lists (their
-//             kernels run after the persistent one, reading the list lengths
-//             on the device); larger ones become queue items
+//   from_list the live segments become queue items
 //   batch     persistent workgroups take items in order. An item that fits
 //             the workgroup's LDS network (NT * E keys) is sorted there in
 //             one read and one write. A larger one is partitioned by the
@@ -113,53 +111,35 @@ __global__ void k_batch_zero(BatchArgs b, uint32_t cap) {
   }
 }
 
-// Every input segment: validated and clamped like the pass path's k_init,
-// then filed as base-case item (<= 4096 keys) or queue item.
-__global__ __launch_bounds__(256) void k_batch_prepare(Ctx c, BatchArgs b) {
-  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool live = i < c.nseg;
-  uint64_t sb = 0, se = 0;
-  if (live) {
-    sb = c.offsets[i];
-    se = c.offsets[i + 1];
-    const bool bad = se < sb || se > c.n || sb > c.n || (i == 0 && sb != 0) || (i + 1 == c.nseg && se != c.n);
-    if (bad) atomicOr(&c.ctr->bad_offsets, 1u);
-    if (sb > c.n) sb = c.n;
-    if (se > c.n) se = c.n;
-    if (se < sb) se = sb;
-  }
-  const uint64_t size = se - sb;
-  const bool small = live && size >= 2 && size <= kBaseMax;
-  const bool big = live && size > kBaseMax;
-  const int cls = small ? base_class(size) : -1;
-#pragma unroll
-  for (int k = 0; k < kBaseClasses; ++k) {
-    const uint32_t slot = wave_reserve(&c.ctr->nbase[k], cls == k);
-    if (cls == k) {
-      if (slot < c.max_items) c.base[k][slot] = Item{sb, se, 0u, 0u};
-      else atomicOr(&c.ctr->errors, kErrCapacity);
+// The segments still live after the captured partition passes (list
+// `parity`, keys in buffer `src`) become the queue's first items, with the
+// budget and flags their bookkeeping gave them.
+__global__ __launch_bounds__(256) void k_batch_from_list(Ctx c, BatchArgs b, int parity, uint32_t src) {
+  uint32_t nlive = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  if (nlive > c.max_active) nlive = c.max_active;
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nlive; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
+    const bool live = i < nlive;
+    const uint32_t j = wave_reserve(&b.q->tail, live);
+    if (live) {
+      const Seg sg = c.segs[parity][i];
+      if (j < b.q->cap) {
+        BItem it;
+        it.begin = sg.begin;
+        it.end = sg.end;
+        it.buf = src;
+        it.budget = sg.budget;
+        it.flags = sg.flags;
+        it.pad = 0;
+        b.items[j] = it;
+        b.state[j] = 2u * (j + 1u);
+      } else {
+        atomicOr(&b.q->error, kErrQueue);
+      }
     }
+    const uint64_t nq = __popcll(__ballot(live));
+    if (lane_id() == 0 && nq) atomicAdd(&b.q->pending, static_cast<uint32_t>(nq));
   }
-  const uint32_t j = wave_reserve(&b.q->tail, big);
-  if (big) {
-    if (j < b.q->cap) {
-      BItem it;
-      it.begin = sb;
-      it.end = se;
-      it.buf = 0;
-      it.budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2(size);
-      it.flags = kSegLeftmost;
-      it.pad = 0;
-      b.items[j] = it;
-      b.state[j] = 2u * (j + 1u);
-    } else {
-      atomicOr(&b.q->error, kErrQueue);
-    }
-  }
-  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), small ? 1 : 0);
-  wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), small ? size : 0);
-  const uint64_t nbig = __popcll(__ballot(big));
-  if (lane_id() == 0 && nbig) atomicAdd(&b.q->pending, static_cast<uint32_t>(nbig));
 }
 
 // ---------------------------------------------------------------- persistent kernel
@@ -566,24 +546,22 @@ const void* kernel_for(const Ctx& c, int shape) {
 
 }  // namespace
 
-hipError_t launch_batch_prepare(const Ctx& c, const BatchArgs& b, uint32_t cap, hipStream_t s) {
+hipError_t launch_batch_zero(const BatchArgs& b, uint32_t cap, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_zero, dim3((cap + 255) / 256), dim3(256), 0, s, b, cap);
-  hipLaunchKernelGGL(k_batch_prepare, dim3(static_cast<uint32_t>((c.nseg + 255) / 256)), dim3(256), 0, s, c, b);
   return hipGetLastError();
 }
 
-uint32_t batch_lds_max(const Ctx& c, int shape) {
-  const uint32_t nt = kShapes[shape].nt;
-  const bool wide_pairs = c.key_type == 4 && c.has_vals;
-  return nt * ((nt >= 1024 || wide_pairs) ? 8u : 16u);
+hipError_t launch_batch_from_list(const Ctx& c, const BatchArgs& b, int parity, uint32_t src, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_from_list, dim3(64), dim3(256), 0, s, c, b, parity, src);
+  return hipGetLastError();
 }
 
-uint32_t batch_grid(const Ctx& c, int shape) {
-  const void* f = kernel_for(c, shape);
+uint32_t batch_grid(const Ctx& c, int tail) {
+  const void* f = kernel_for(c, tail);
   int per_cu = 0, dev = 0, cus = 0;
   if (!f || hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, static_cast<int>(kShapes[shape].nt), 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, static_cast<int>(kTail[tail].nt), 0) != hipSuccess)
     return 0;
   return static_cast<uint32_t>(per_cu > 0 ? per_cu : 1) * static_cast<uint32_t>(cus);
 }

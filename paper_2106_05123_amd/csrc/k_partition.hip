@@ -190,7 +190,8 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
   const uint32_t* __restrict__ srcv = c.vals[src_buf];
   uint32_t* __restrict__ dstv = c.vals[src_buf ^ 1];
   Seg* segs = c.segs[parity];
-  const uint32_t ntiles = static_cast<uint32_t>(c.ctr->list[parity]);
+  uint32_t ntiles = static_cast<uint32_t>(c.ctr->list[parity]);
+  if (ntiles > c.max_tiles) ntiles = c.max_tiles;  // an overfull list is flagged, never read past
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;

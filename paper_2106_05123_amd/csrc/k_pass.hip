@@ -93,7 +93,9 @@ __global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
   const uint64_t size = e - b;
   uint32_t budget = 0;
   if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
-  const bool big = size > kBaseMax;
+  const bool big = size > c.base_max;
+  const uint64_t wmax = wave_max_u64(size);
+  if (lane_id() == 0 && wmax) atomicMax(reinterpret_cast<unsigned long long*>(&c.ctr->max_seg), wmax);
   push_seg(c, 0, big && budget > 0, b, e, budget, kSegLeftmost);
   const bool to_base = size >= 2 && !big;
   const bool to_heap = big && budget == 0;
@@ -123,7 +125,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
   const bool range = in && !(i & 1u) && size > 0;
   uint32_t budget = 0;
   if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
-  const bool big = size > kBaseMax;
+  const bool big = size > c.base_max;
   push_item(c, c.copy, &c.ctr->ncopy, eq, b, e, 1u, 0u);
   push_seg(c, 0, range && big && budget > 0, b, e, budget, kSegLeftmost);
   const bool to_base = range && !big;
@@ -138,55 +140,60 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
 }
 
 // Pivot choice for every live segment (choose_pivot, pivot.h). The first
-// lane also clears the counters of the list the bookkeeping will fill.
+// lane also clears the counters of the list the bookkeeping will fill (and,
+// unless the item lists accumulate over the passes, the item counts).
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32_t nseg, uint32_t src) {
   using T = typename K::T;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c.device_counts) nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  if (nseg > c.max_active) nseg = c.max_active;  // an overfull list is flagged, never read past
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.ctr->visits += c.ctr->elems[parity];
     c.ctr->list[parity ^ 1] = 0;
     c.ctr->elems[parity ^ 1] = 0;
-    for (int k = 0; k < kBaseClasses; ++k) c.ctr->nbase[k] = 0;
-    c.ctr->nheap = 0;
-    c.ctr->ncopy = 0;
+    if (!c.device_counts) {
+      for (int k = 0; k < kBaseClasses; ++k) c.ctr->nbase[k] = 0;
+      c.ctr->nheap = 0;
+      c.ctr->ncopy = 0;
+    }
   }
-  if (i >= nseg) return;
-  Seg* sp = &c.segs[parity][i];
-  const PivotChoice<K> pc = choose_pivot<K>(static_cast<const T*>(c.keys[src]), static_cast<const T*>(c.keys[0]),
-                                            sp->begin, sp->end, sp->flags, c.seed);
-  sp->pivot = static_cast<uint64_t>(pc.raw);
-  sp->pidx = pc.pidx;
-  sp->mode = pc.mode;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+    Seg* sp = &c.segs[parity][i];
+    const PivotChoice<K> pc = choose_pivot<K>(static_cast<const T*>(c.keys[src]), static_cast<const T*>(c.keys[0]),
+                                              sp->begin, sp->end, sp->flags, c.seed);
+    sp->pivot = static_cast<uint64_t>(pc.raw);
+    sp->pidx = pc.pidx;
+    sp->mode = pc.mode;
+  }
 }
 
 // Ticket -> segment map for the partition kernel, and a cleared status word
 // per ticket.
 __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint32_t ntiles) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) c.ctr->ticket = 0;
-  if (t >= ntiles) return;
-  const uint32_t nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) c.ctr->ticket = 0;
+  if (c.device_counts) ntiles = static_cast<uint32_t>(c.ctr->list[parity]);
+  if (ntiles > c.max_tiles) ntiles = c.max_tiles;
+  uint32_t nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  if (nseg > c.max_active) nseg = c.max_active;
   const Seg* segs = c.segs[parity];
-  uint32_t lo = 0, hi = nseg - 1;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi + 1) >> 1;
-    if (segs[mid].tile_base <= t) lo = mid;
-    else hi = mid - 1;
+  for (uint32_t t = t0; t < ntiles; t += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile_base <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    c.tilemap[t] = lo;
+    c.status[t] = 0;
   }
-  c.tilemap[t] = lo;
-  c.status[t] = 0;
 }
 
-// After a partition pass: place each pivot at its final position in the user
-// buffer, retire segments that were already ordered (Section 5.2) and the
-// equal-to-pivot side of partition_left (Section 3), count bad partitions and
-// charge the budget (Section 4.1), and file every child as live segment, base
-// case or heapsort.
+// One live segment after its partition (every lane of the wave calls).
 template <class K>
-__global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uint32_t nseg, uint32_t src,
-                                                         uint32_t pass) {
+__device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t i, uint32_t nseg, uint32_t src,
+                                             uint32_t pass) {
   using T = typename K::T;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < nseg;
   const uint32_t dst = src ^ 1u;
   Seg s = {};
@@ -232,9 +239,9 @@ __global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uin
     const uint64_t ce = side == 0 ? s.begin + L : s.end;
     const uint64_t cs = has ? ce - cb : 0;
     const uint32_t cflags = cflag_fresh | (side == 0 ? (s.flags & kSegLeftmost) : 0u);
-    const bool to_base = has && cs >= 1 && cs <= kBaseMax && !(cs == 1 && dst == 0);
-    const bool to_heap = has && cs > kBaseMax && cbudget == 0;
-    const bool to_live = has && cs > kBaseMax && cbudget > 0;
+    const bool to_base = has && cs >= 1 && cs <= c.base_max && !(cs == 1 && dst == 0);
+    const bool to_heap = has && cs > c.base_max && cbudget == 0;
+    const bool to_live = has && cs > c.base_max && cbudget > 0;
     push_base(c, to_base, cb, ce, dst);
     push_item(c, c.heap, &c.ctr->nheap, to_heap, cb, ce, dst, 0u);
     push_seg(c, parity ^ 1, to_live, cb, ce, cbudget, cflags);
@@ -252,39 +259,59 @@ __global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uin
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->equal_elements), split && is_left ? L : 0);
 }
 
-// Copies into the user buffer: plain, reversed, or reversed in place.
+// After a partition pass: place each pivot at its final position in the user
+// buffer, retire segments that were already ordered (Section 5.2) and the
+// equal-to-pivot side of partition_left (Section 3), count bad partitions and
+// charge the budget (Section 4.1), and file every child as live segment, base
+// case or heapsort.
 template <class K>
-__global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c) {
+__global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uint32_t nseg, uint32_t src,
+                                                         uint32_t pass) {
+  if (c.device_counts) nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
+  if (nseg > c.max_active) nseg = c.max_active;
+  // the loop bound is uniform over each wave: the wave-wide appends see every lane
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < nseg; i0 += gridDim.x * blockDim.x)
+    bookkeep_one<K>(c, parity, i0 + threadIdx.x, nseg, src, pass);
+}
+
+// Copies into the user buffer: plain, reversed, or reversed in place. The
+// blocks of row blockIdx.y share the items blockIdx.x, + gridDim.x, ...
+template <class K>
+__global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
   using T = typename K::T;
-  const Item it = c.copy[blockIdx.x];
-  const uint64_t len = it.end - it.begin;
+  uint32_t count = c.device_counts ? c.ctr->ncopy : nitems;
+  if (count > c.max_items) count = c.max_items;  // an overfull list is flagged, never read past
   T* out = static_cast<T*>(c.keys[0]);
-  const T* in = static_cast<const T*>(c.keys[it.buf]);
   uint32_t* outv = c.vals[0];
-  const uint32_t* inv = c.vals[it.buf];
   const uint64_t stride = static_cast<uint64_t>(gridDim.y) * blockDim.x;
   const uint64_t start = static_cast<uint64_t>(blockIdx.y) * blockDim.x + threadIdx.x;
-  if (it.reverse && it.buf == 0) {
-    for (uint64_t j = start; j < len / 2; j += stride) {
-      const uint64_t a = it.begin + j, z = it.end - 1 - j;
-      T ka = out[a], kz = out[z];
-      out[a] = kz;
-      out[z] = ka;
-      if (c.has_vals) {
-        uint32_t va = outv[a], vz = outv[z];
-        outv[a] = vz;
-        outv[z] = va;
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const Item it = c.copy[item];
+    const uint64_t len = it.end - it.begin;
+    const T* in = static_cast<const T*>(c.keys[it.buf]);
+    const uint32_t* inv = c.vals[it.buf];
+    if (it.reverse && it.buf == 0) {
+      for (uint64_t j = start; j < len / 2; j += stride) {
+        const uint64_t a = it.begin + j, z = it.end - 1 - j;
+        T ka = out[a], kz = out[z];
+        out[a] = kz;
+        out[z] = ka;
+        if (c.has_vals) {
+          uint32_t va = outv[a], vz = outv[z];
+          outv[a] = vz;
+          outv[z] = va;
+        }
       }
-    }
-  } else if (it.reverse) {
-    for (uint64_t j = start; j < len; j += stride) {
-      out[it.begin + j] = in[it.end - 1 - j];
-      if (c.has_vals) outv[it.begin + j] = inv[it.end - 1 - j];
-    }
-  } else {
-    for (uint64_t j = start; j < len; j += stride) {
-      out[it.begin + j] = in[it.begin + j];
-      if (c.has_vals) outv[it.begin + j] = inv[it.begin + j];
+    } else if (it.reverse) {
+      for (uint64_t j = start; j < len; j += stride) {
+        out[it.begin + j] = in[it.end - 1 - j];
+        if (c.has_vals) outv[it.begin + j] = inv[it.end - 1 - j];
+      }
+    } else {
+      for (uint64_t j = start; j < len; j += stride) {
+        out[it.begin + j] = in[it.begin + j];
+        if (c.has_vals) outv[it.begin + j] = inv[it.begin + j];
+      }
     }
   }
 }
@@ -293,23 +320,28 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c) {
 // budget), one workgroup per segment: the workgroup moves the segment into
 // the user buffer, then one lane sorts it there (heapsort_range, pivot.h).
 template <class K>
-__global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c) {
+__global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c, uint32_t nitems) {
   using T = typename K::T;
-  const Item it = c.heap[blockIdx.x];
-  const uint64_t len = it.end - it.begin;
-  T* a = static_cast<T*>(c.keys[0]) + it.begin;
-  uint32_t* v = c.has_vals ? c.vals[0] + it.begin : nullptr;
-  if (it.buf != 0) {
-    const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
-    const uint32_t* inv = c.has_vals ? c.vals[it.buf] + it.begin : nullptr;
-    for (uint64_t j = threadIdx.x; j < len; j += blockDim.x) {
-      a[j] = in[j];
-      if (v) v[j] = inv[j];
+  uint32_t count = c.device_counts ? c.ctr->nheap : nitems;
+  if (count > c.max_items) count = c.max_items;
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const Item it = c.heap[item];
+    const uint64_t len = it.end - it.begin;
+    T* a = static_cast<T*>(c.keys[0]) + it.begin;
+    uint32_t* v = c.has_vals ? c.vals[0] + it.begin : nullptr;
+    if (it.buf != 0) {
+      const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
+      const uint32_t* inv = c.has_vals ? c.vals[it.buf] + it.begin : nullptr;
+      for (uint64_t j = threadIdx.x; j < len; j += blockDim.x) {
+        a[j] = in[j];
+        if (v) v[j] = inv[j];
+      }
+      __threadfence_block();
+      __syncthreads();
     }
-    __threadfence_block();
+    if (threadIdx.x == 0) heapsort_range<K>(a, v, len);
     __syncthreads();
   }
-  if (threadIdx.x == 0) heapsort_range<K>(a, v, len);
 }
 
 template <template <class> class F, class... Args>
@@ -325,32 +357,47 @@ hipError_t dispatch_key(uint32_t kt, Args&&... args) {
 
 inline uint32_t blocks_for(uint64_t n, uint32_t per) { return static_cast<uint32_t>((n + per - 1) / per); }
 
+// Blocks of a control launch over n entries: one entry per lane, or, with
+// device counts (n is then a capacity), at most `cap` blocks that loop.
+inline uint32_t ctl_blocks(const Ctx& c, uint64_t n, uint32_t cap) {
+  const uint32_t b = blocks_for(n, kCtlThreads);
+  return c.device_counts && b > cap ? cap : b;
+}
+constexpr uint32_t kDevCtlBlocks = 512;
+
 template <class K>
 struct PivotL {
   static hipError_t run(const Ctx& c, int parity, uint32_t nseg, uint32_t src, hipStream_t s) {
-    hipLaunchKernelGGL(k_pivot<K>, dim3(blocks_for(nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, nseg, src);
+    const uint32_t g = ctl_blocks(c, nseg, kDevCtlBlocks);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pivot<K>, dim3(g), dim3(kCtlThreads), 0, s, c, parity, nseg, src);
     return hipGetLastError();
   }
 };
 template <class K>
 struct BookL {
   static hipError_t run(const Ctx& c, int parity, uint32_t nseg, uint32_t src, uint32_t pass, hipStream_t s) {
-    hipLaunchKernelGGL(k_bookkeep<K>, dim3(blocks_for(nseg, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, nseg,
-                       src, pass);
+    const uint32_t g = ctl_blocks(c, nseg, kDevCtlBlocks);
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bookkeep<K>, dim3(g), dim3(kCtlThreads), 0, s, c, parity, nseg, src, pass);
     return hipGetLastError();
   }
 };
 template <class K>
 struct CopyL {
   static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy<K>, dim3(nitems, 64), dim3(kCtlThreads), 0, s, c);
+    const uint32_t g = c.device_counts && nitems > 2048 ? 2048 : nitems;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy<K>, dim3(g, c.device_counts ? 8 : 64), dim3(kCtlThreads), 0, s, c, nitems);
     return hipGetLastError();
   }
 };
 template <class K>
 struct HeapL {
   static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
-    hipLaunchKernelGGL(k_heap<K>, dim3(nitems), dim3(kCtlThreads), 0, s, c);
+    const uint32_t g = c.device_counts && nitems > 2048 ? 2048 : nitems;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_heap<K>, dim3(g), dim3(kCtlThreads), 0, s, c, nitems);
     return hipGetLastError();
   }
 };
@@ -377,7 +424,9 @@ hipError_t launch_pivot(const Ctx& c, int parity, uint32_t nseg, uint32_t src, h
 }
 
 hipError_t launch_tilemap(const Ctx& c, int parity, uint32_t ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(k_tilemap, dim3(blocks_for(ntiles, kCtlThreads)), dim3(kCtlThreads), 0, s, c, parity, ntiles);
+  const uint32_t g = ctl_blocks(c, ntiles, 4 * kDevCtlBlocks);
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tilemap, dim3(g), dim3(kCtlThreads), 0, s, c, parity, ntiles);
   return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ struct Bump {
   }
 };
 
-Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals);
+Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched);
 
 // Outputs of the fit (sample, features, targets, prediction, parameters,
 // losses, splitters, count, info).
@@ -127,7 +127,11 @@ BucketLayout bucket_layout(size_t n) {
   return L;
 }
 
-Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
+// Widest LDS class of the batched form: 16384 keys, 8192 for 64-bit keys
+// with a payload (12 LDS bytes a slot).
+uint32_t batch_base_max(uint32_t kt, bool vals) { return kt == PDQ_U64 && vals ? 8192u : kWideBaseMax; }
+
+Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -140,6 +144,12 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals) {
   L.max_tiles = static_cast<uint32_t>(n / kMinTile + 2ull * L.max_active + 64);
   size_t items = 2ull * L.max_active;
   if (nseg > items) items = nseg;
+  if (batched) {
+    // the item lists accumulate over the passes: the input segments, then at
+    // most two children (or one ordered run and one equal run) for each of
+    // the disjoint live segments of every pass
+    items = nseg + 2ull * kMaxBatchPasses * (n / (batch_base_max(kt, vals) + 1) + 2);
+  }
   L.max_items = static_cast<uint32_t>(items + 64);
   L.scratch_keys = take(n * key_bytes(kt));
   L.scratch_vals = take(vals ? n * 4 : 0);
@@ -162,7 +172,7 @@ uint32_t batch_capacity(size_t n) { return static_cast<uint32_t>(n / (kBaseMax +
 
 Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool learned, uint32_t steps, uint32_t grid,
                         bool batched = false, bool tune = false) {
-  Layout L = make_layout(n, nseg, kt, vals);
+  Layout L = make_layout(n, nseg, kt, vals, batched);
   if (!learned && !batched) return L;
   Bump b;
   b.off = L.total - kAlign;
@@ -197,6 +207,7 @@ struct Opts {
   uint32_t batch = 1024;
   uint32_t grid = 16;
   uint32_t batch_shape = 0;  // 0 = tuned or default, else shape index + 1
+  uint32_t batch_passes = 0; // 0 = automatic, else passes + 1
 };
 
 
@@ -215,10 +226,12 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, learn_batch) + sizeof(uint32_t) && o->learn_batch) out->batch = o->learn_batch;
   if (sz >= offsetof(pdq_options, learn_grid) + sizeof(uint32_t) && o->learn_grid) out->grid = o->learn_grid;
   if (sz >= offsetof(pdq_options, batch_shape) + sizeof(uint32_t)) out->batch_shape = o->batch_shape;
+  if (sz >= offsetof(pdq_options, batch_passes) + sizeof(uint32_t)) out->batch_passes = o->batch_passes;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
+  if (out->batch_passes > kMaxBatchPasses + 1) return PDQ_ERR_UNSUPPORTED;
   if (out->steps > kMaxLearnSteps || out->grid > kMaxTrainGrid || out->batch > 65536 || out->batch % out->grid)
     return PDQ_ERR_UNSUPPORTED;
   if (out->tile != 0 && out->tile != 1024 && out->tile != 2048 && out->tile != 4096 && out->tile != 8192 &&
@@ -459,6 +472,8 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.has_vals = vals ? 1u : 0u;
   c.single = offsets ? 0u : 1u;
   c.seed = o.seed;
+  c.base_max = kBaseMax;
+  c.wide_e = 16;
   return c;
 }
 
@@ -483,39 +498,91 @@ BatchArgs batch_args(const Layout& L, char* base) {
   return b;
 }
 
-// The whole launch sequence, with no host synchronisation (capturable):
-// counters, queue and base lists, the persistent kernel, then the base-case
-// kernels over the lists it filled.
-int enqueue_batched(Ctx c, const Layout& L, char* base, int shape, hipStream_t s) {
+// The batched form's context: device-side counts, accumulating item lists,
+// the wide LDS classes, and the shape's partition tile.
+Ctx batch_ctx(Ctx c, const Opts& o, int shape) {
   c.device_counts = 1;
-  const BatchArgs b = batch_args(L, base);
-  const uint32_t grid = batch_grid(c, shape);
-  if (grid == 0) return PDQ_ERR_HIP;
+  c.base_max = batch_base_max(c.key_type, c.has_vals != 0);
+  c.tile = o.tile ? o.tile : kShapes[shape].tile;
+  c.wide_e = kShapes[shape].wide_e;
+  return c;
+}
+
+// Passes queued for a largest segment of m keys: the halvings that bring it
+// to the widest LDS class, plus two for uneven splits. Anything deeper
+// finishes in the persistent tail.
+uint32_t batch_passes(uint64_t m, uint32_t base_max) {
+  uint32_t p = 0;
+  while (m > base_max && p < kMaxBatchPasses) {
+    m = (m + 1) / 2;
+    ++p;
+  }
+  if (p == 0) return 0;
+  p += 2;
+  return p < kMaxBatchPasses ? p : kMaxBatchPasses;
+}
+
+// First step, the same for every shape: counters, and the input segments
+// filed into the item lists and live list 0.
+int enqueue_batch_init(const Ctx& c, hipStream_t s) {
   HIP_TRY(launch_reset(c, s));
-  HIP_TRY(launch_batch_prepare(c, b, L.bcap, s));
-  HIP_TRY(launch_batch(c, b, shape, grid, s));
-  for (int k = 0; k < kBaseClasses; ++k) HIP_TRY(launch_base(c, k, c.max_items, s));
+  HIP_TRY(launch_init(c, s));
   return PDQ_OK;
 }
 
-int run_batched(const Ctx& c, const Opts& o, const Layout& L, char* base, pdq_stats* st, hipStream_t s) {
-  const int shape = tuned_shape(c, o);
-  if (o.flags & PDQ_VALIDATE) {
-    // validation needs the offsets checked before anything is moved
-    Ctx v = c;
-    v.device_counts = 1;
-    HIP_TRY(launch_reset(v, s));
-    HIP_TRY(launch_batch_prepare(v, batch_args(L, base), L.bcap, s));
-    Counters snap = {};
-    HIP_TRY(hipMemcpyAsync(&snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (snap.bad_offsets || (snap.errors & kErrCapacity)) return PDQ_ERR_INVALID;
+// Reads the counters after the first step: offsets, capacity, and the
+// number of passes to queue.
+int batch_probe(const Ctx& c, const Opts& o, hipStream_t s, uint32_t* passes) {
+  Counters snap = {};
+  HIP_TRY(hipMemcpyAsync(&snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (snap.bad_offsets || (snap.errors & kErrCapacity)) return PDQ_ERR_INVALID;
+  *passes = o.batch_passes ? o.batch_passes - 1 : batch_passes(snap.max_seg, c.base_max);
+  return PDQ_OK;
+}
+
+// The rest, with no host synchronisation (capturable): `passes` partition
+// passes whose kernels read their counts on the device, the persistent tail
+// over whatever is still live, then every item list finished once.
+int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passes, int tail, hipStream_t s) {
+  const BatchArgs b = batch_args(L, base);
+  const uint32_t grid = batch_grid(c, tail);
+  if (grid == 0) return PDQ_ERR_HIP;
+  int parity = 0;
+  uint32_t src = 0;
+  for (uint32_t p = 0; p < passes; ++p) {
+    HIP_TRY(launch_pivot(c, parity, c.max_active, src, s));
+    HIP_TRY(launch_tilemap(c, parity, c.max_tiles, s));
+    HIP_TRY(launch_partition(c, parity, c.max_tiles, src, s));
+    HIP_TRY(launch_bookkeep(c, parity, c.max_active, src, p, s));
+    parity ^= 1;
+    src ^= 1u;
   }
+  HIP_TRY(launch_batch_zero(b, L.bcap, s));
+  HIP_TRY(launch_batch_from_list(c, b, parity, src, s));
+  HIP_TRY(launch_batch(c, b, tail, grid, s));
+  for (int k = 0; k < kBaseClasses; ++k) {
+    if (k == 6 && c.base_max < kWideBaseMax) continue;
+    HIP_TRY(launch_base(c, k, c.max_items, s));
+  }
+  HIP_TRY(launch_heap(c, c.max_items, s));
+  HIP_TRY(launch_copy(c, c.max_items, s));
+  return PDQ_OK;
+}
+
+int run_batched(const Ctx& c0, const Opts& o, const Layout& L, char* base, pdq_stats* st, hipStream_t s) {
+  const int shape = tuned_shape(c0, o);
+  const Ctx c = batch_ctx(c0, o, shape);
   EventPair ev;
   const bool prof = (o.flags & PDQ_PROFILE) && st;
   if (prof && !ev.make()) return PDQ_ERR_HIP;
+  int rc = enqueue_batch_init(c, s);
+  if (rc != PDQ_OK) return rc;
+  uint32_t passes = 0;
+  rc = batch_probe(c, o, s, &passes);
+  if (rc != PDQ_OK) return rc;
   if (prof) HIP_TRY(hipEventRecord(ev.a, s));
-  int rc = enqueue_batched(c, L, base, shape, s);
+  rc = enqueue_batch_rest(c, L, base, passes, kShapes[shape].tail, s);
   if (rc != PDQ_OK) return rc;
   if (prof) HIP_TRY(hipEventRecord(ev.b, s));
   if (!st) return PDQ_OK;
@@ -529,7 +596,8 @@ int run_batched(const Ctx& c, const Opts& o, const Layout& L, char* base, pdq_st
     g_last_hip = 0;
     return PDQ_ERR_HIP;
   }
-  st->passes = 0;
+  st->passes = passes;
+  st->element_visits = snap.visits;
   st->partitions_right = snap.partitions_right;
   st->partitions_left = snap.partitions_left;
   st->bad_partitions = snap.bad_partitions;
@@ -773,6 +841,7 @@ struct pdq_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint32_t shape = 0;
+  uint32_t passes = 0;
   double ms[kBatchShapes] = {};
 };
 
@@ -806,6 +875,14 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
     return code;
   };
   int shape = tuned_shape(c, o);
+  // the first step (shape-independent) gives the number of passes to capture
+  uint32_t passes = 0;
+  {
+    const Ctx c0 = batch_ctx(c, o, shape);
+    rc = enqueue_batch_init(c0, s);
+    if (rc == PDQ_OK) rc = batch_probe(c0, o, s, &passes);
+    if (rc != PDQ_OK) return fail(rc);
+  }
   if (tune) {
     // time every shape on a copy of the caller's data, keep the fastest
     void* bk = base + L.backup_keys;
@@ -814,14 +891,16 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
     if (bv && hipMemcpyAsync(bv, d_vals, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
     double best = 1e300;
     for (int sh = 0; sh < kBatchShapes; ++sh) {
+      const Ctx cs = batch_ctx(c, o, sh);
       double total = 0;
-      for (int rep = 0; rep < 2; ++rep) {  // the first run warms the kernel up
+      for (int rep = 0; rep < 2; ++rep) {  // the first run warms the kernels up
         if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
         if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
           return fail(PDQ_ERR_HIP);
         EventPair ev;
         if (!ev.make() || hipEventRecord(ev.a, s) != hipSuccess) return fail(PDQ_ERR_HIP);
-        rc = enqueue_batched(c, L, base, sh, s);
+        rc = enqueue_batch_init(cs, s);
+        if (rc == PDQ_OK) rc = enqueue_batch_rest(cs, L, base, passes, kShapes[sh].tail, s);
         if (rc != PDQ_OK) return fail(rc);
         if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess)
           return fail(PDQ_ERR_HIP);
@@ -840,12 +919,15 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
     g_tune[std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg)] = shape;
   }
   p->shape = static_cast<uint32_t>(shape);
+  p->passes = passes;
   // capture the launch sequence on a private stream
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PDQ_ERR_HIP);
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    rc = enqueue_batched(c, L, base, shape, cs);
+    const Ctx cc = batch_ctx(c, o, shape);
+    rc = enqueue_batch_init(cc, cs);
+    if (rc == PDQ_OK) rc = enqueue_batch_rest(cc, L, base, passes, kShapes[shape].tail, cs);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     p->graph = g;

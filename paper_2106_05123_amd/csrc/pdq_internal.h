@@ -8,7 +8,8 @@
 namespace pdq {
 
 constexpr uint32_t kBaseMax = 4096;     // segments of at most this many keys go to the LDS base case
-constexpr int kBaseClasses = 5;         // base-case size classes: <= 64, 256, 1024, 2048, 4096 keys
+constexpr uint32_t kWideBaseMax = 16384;  // the batched form's widest LDS class
+constexpr int kBaseClasses = 7;         // base-case size classes: <= 64, 256, 1024, 2048, 4096, 8192, 16384 keys
 constexpr uint32_t kWave = 64;          // CDNA wavefront width
 constexpr uint32_t kSegLeftmost = 1u;   // segment has no predecessor (Section 3)
 constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh candidates (Section 4.2)
@@ -64,6 +65,8 @@ struct Counters {
   uint64_t base_segments, base_elements;
   uint64_t sorted_segments, sorted_elements, equal_elements;
   uint64_t first_pivot_image;
+  uint64_t max_seg;        // largest input segment (initial lists)
+  uint64_t visits;         // keys of every partitioned segment, summed over the passes
   int64_t first_left;
   int32_t first_mode;
   uint32_t bad_offsets;    // validation: offsets not monotone / not covering [0, n)
@@ -97,8 +100,11 @@ struct Ctx {
   uint32_t key_type;
   uint32_t has_vals;
   uint32_t single;      // 1: one segment [0, n) (records the first partition)
-  uint32_t device_counts;  // 1: base-case launches take their item counts from ctr (grid is an upper bound)
+  uint32_t device_counts;  // 1 (batched form): every kernel takes its counts from ctr, item lists
+                           // accumulate over the passes and are finished once at the end
   uint64_t seed;        // seeds the candidate positions taken after a bad partition
+  uint32_t base_max;    // segments of at most this many keys go to the LDS base case
+  uint32_t wide_e;      // slots per lane of the 8192 / 16384 classes (16 or 32)
 };
 
 // ---- key traits: canonical unsigned image in registers only ---------------
@@ -155,9 +161,9 @@ hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s);
 
 inline uint32_t key_bytes(uint32_t key_type) { return key_type == 4 ? 8u : 4u; }
 
-// Size class of a base-case segment of n keys (1 <= n <= kBaseMax).
+// Size class of a base-case segment of n keys (1 <= n <= kWideBaseMax).
 __host__ __device__ inline int base_class(uint64_t n) {
-  return n <= 64 ? 0 : n <= 256 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 3 : 4;
+  return n <= 64 ? 0 : n <= 256 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 3 : n <= 4096 ? 4 : n <= 8192 ? 5 : 6;
 }
 
 // Number of tile tickets a segment [b, e) takes: tiles are aligned to

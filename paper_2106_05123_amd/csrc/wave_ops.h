@@ -19,6 +19,14 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
   for (int d = 32; d >= 1; d >>= 1) v |= __shfl_xor(v, d, 64);
   return v;

@@ -1,11 +1,13 @@
-"""The batched segmented sort (one persistent launch over a device queue, and
-its captured HIP-graph plan) against the CPU oracle, through the C ABI.
+"""The batched segmented sort (partition passes with device-side counts, the
+wide LDS classes, the persistent tail over a device queue, and the captured
+HIP-graph plan) against the CPU oracle, through the C ABI.
 
 Keys must match the oracle bit for bit; payloads must be a valid
-permutation that stays inside its segment. Segment sizes cover every path
-of the persistent kernel: base-case lists (<= 4096), one LDS network
-(<= 16384 with 1024 threads, <= 8192 with 512), and single-workgroup
-partitions with queued children above that."""
+permutation that stays inside its segment. Segment sizes cover every size
+class (<= 64 ... 16384 keys, 8192 for 64-bit keys with payloads), segments
+that need partition passes, and, with the passes cut short, the persistent
+tail: LDS networks of its workgroup, single-workgroup partitions and queued
+children."""
 import numpy as np
 import pytest
 
@@ -73,7 +75,21 @@ def test_batched_mixed_sizes(kt, pairs):
     vals = W.index_payload(n) if pairs else None
     out, vo, st = run_batched(keys, off, vals)
     check_segmented(keys, off, out, vo)
-    assert st["batch_items"] >= int(np.count_nonzero(np.diff(off) > 4096))
+    assert st["passes"] >= 1 and st["element_visits"] > 0
+
+
+@pytest.mark.parametrize("kt", ["f32", "u64"])
+@pytest.mark.parametrize("passes", [0, 1, 2])
+def test_batched_tail(kt, passes):
+    """Passes cut short: the persistent tail takes every segment still live."""
+    off = W.offsets_from_sizes(mixed_sizes(13, extra=120, max_log2=17))
+    n = int(off[-1])
+    keys = W.random_keys(kt, n, seed=6)
+    vals = W.index_payload(n)
+    out, vo, st = run_batched(keys, off, vals, batch_passes=passes)
+    check_segmented(keys, off, out, vo)
+    assert st["passes"] == passes
+    assert st["batch_items"] > 0
 
 
 @pytest.mark.parametrize("shape", [1, 2, 3, 4])
@@ -187,4 +203,4 @@ def test_batched_full_workload_sampled():
     assert multiset_hash(out) == multiset_hash(keys)
     assert np.array_equal(np.sort(vo), np.arange(out.size, dtype=np.uint32))
     assert np.array_equal(out.view(np.uint32), keys[vo].view(np.uint32))
-    assert st["batch_items"] > 0
+    assert st["passes"] > 0
