@@ -100,7 +100,9 @@ typedef struct pdq_options {
   uint32_t struct_size;  /* sizeof(pdq_options); 0 or a smaller value = older layout */
   uint32_t flags;        /* pdq_flags */
   int32_t force_budget;  /* < 0: floor(log2 size) per segment (Section 4.1); >= 0: that budget */
-  uint32_t tile;         /* keys per partition tile: 0 = auto (32768), else 1024 ... 65536, a power of two */
+  uint32_t tile;         /* keys per partition tile: 0 = chosen per pass from the average segment
+                            size (32768, or 8192 below 2^18 keys), else 1024 ... 65536, a power
+                            of two; PDQ_BATCHED uses its shape's tile unless this is set */
   uint64_t seed;         /* seeds the hashed pivot candidates taken after a bad partition, and
                             the sample, initial weights and minibatches of PDQ_LEARNED */
   float learned_imbalance_limit; /* PDQ_LEARNED: fall back to the plain path when a range bin holds
@@ -110,7 +112,7 @@ typedef struct pdq_options {
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
                             (partition tile, slots per lane of the two widest LDS classes):
-                            (16384, 16), (32768, 16), (8192, 16), (16384, 32) */
+                            (8192, 16), (16384, 16), (32768, 16), (8192, 32) */
   uint32_t batch_passes; /* PDQ_BATCHED: 0 = automatic (the halvings that bring the largest
                             segment to the widest LDS class, plus 2); k > 0 = k - 1 passes (at
                             most 20); segments still live after them finish in the persistent

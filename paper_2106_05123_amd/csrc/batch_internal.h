@@ -54,7 +54,7 @@ struct BatchShape {
   uint32_t tail;
 };
 constexpr int kBatchShapes = 4;
-constexpr BatchShape kShapes[kBatchShapes] = {{16384, 16, 0}, {32768, 16, 0}, {8192, 16, 0}, {16384, 32, 0}};
+constexpr BatchShape kShapes[kBatchShapes] = {{8192, 16, 0}, {16384, 16, 0}, {32768, 16, 0}, {8192, 32, 0}};
 
 // Passes the batched form captures at most; deeper recursions finish in the
 // persistent tail.

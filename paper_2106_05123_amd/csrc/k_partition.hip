@@ -5,27 +5,28 @@
 // partition_left) with the branchless block classification of Section 5.3,
 // recast for a wave64 GPU:
 //   * a tile of TILE keys per workgroup, read with coalesced loads (lane l of
-//     row i reads position i*NT + l of the tile);
+//     row i reads position i*NT + l of a sub-tile), kept in registers from
+//     the count to the scatter for tiles up to 32768 keys;
 //   * classification with one comparison per key (x < p for partition_right,
 //     x <= p for partition_left), the pivot element itself excluded;
 //   * per-row wave ballots + mbcnt give each key its rank among the keys of
 //     its class, an LDS scan over (row, wave) counts gives tile offsets;
-//   * a decoupled look-back over the tiles of the segment (tile tickets come
-//     from an atomic counter, so every tile waits only on tiles already
-//     running) gives the number of left keys before the tile;
+//   * the tile reserves its places with one 64-bit atomic on the segment's
+//     packed cursor: left keys upward from the segment start, the others
+//     downward from its end. The order of the tiles' blocks inside each side
+//     is the order their reservations arrived in; the partition does not
+//     need any particular order inside a side (the paper's partition is not
+//     stable either), and no tile ever waits for another;
 //   * keys are written straight from registers: within a (row, wave) the
 //     ranks of one class are consecutive, so every store instruction writes
-//     at most two contiguous runs -- left keys upward from the segment
-//     start, right keys downward from the segment end (the right side is
-//     thus reversed, which no later step depends on);
-//   * a tile that finds its prefix also publishes the inclusive prefixes of
-//     the predecessors it summed, so one finished look-back moves the
-//     frontier for a whole window;
-//   * the next tile's ticket, descriptor and keys are fetched while the
-//     current tile does its look-back and scatter;
+//     at most two contiguous runs (the right side of a tile is written in
+//     descending order of its ranks, which no later step depends on);
+//   * payloads are loaded before the reservation, so they travel while the
+//     tile's counts are scanned;
 //   * the tile also records whether its adjacent pairs ever descend or
-//     ascend; the look-back ORs these bits so that the segment's last tile
-//     knows whether the whole segment was already ordered (Section 5.2).
+//     ascend (including the pair across its end) and ORs these bits into
+//     the segment, which thus learns whether it was already ordered
+//     (Section 5.2).
 #include "pdq_internal.h"
 #include "wave_ops.h"
 
@@ -155,18 +156,19 @@ __device__ __forceinline__ void classify(const typename K::T (&k)[IT], const Til
 }
 
 // The partition kernel. A workgroup takes one tile of NSUB sub-tiles (SUB =
-// NT*IT keys each) and makes two streaming passes over it:
+// NT*IT keys each) and makes two passes over it:
 //   count:   load each sub-tile, classify, record per (row, wave) group its
 //            left count and first / last key; no barrier inside the pass;
-//   publish: one barrier, then wave 0 scans the group counts, publishes the
-//            tile's aggregate and runs the decoupled look-back;
-//   scatter: load each sub-tile again (it was just read, so it comes from
-//            the caches), classify again and write every key straight from
-//            registers to its final place; no barrier inside the pass.
-// Keys therefore cross HBM once on the way in and once on the way out, while
-// the look-back, the only wait on other workgroups, is paid once per NSUB
-// sub-tiles.
-template <class K, bool PAIRS, int NT, int IT, int NSUB>
+//   reserve: one barrier, then wave 0 scans the group counts and reserves the
+//            tile's places in the segment with one atomic;
+//   scatter: write every key straight from registers to its final place; no
+//            barrier inside the pass.
+// REG (register-resident tile): every lane keeps its NSUB*IT keys in
+// registers from the count pass to the scatter and loads its payloads
+// before the reservation, so each key and payload crosses HBM exactly once
+// each way. Otherwise (tiles larger than the registers hold) the scatter
+// pass loads each sub-tile again and classifies it again.
+template <class K, bool PAIRS, int NT, int IT, int NSUB, bool REG>
 __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t src_buf) {
   using T = typename K::T;
   constexpr int NW = NT / 64;
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
   constexpr int TILE = SUB * NSUB;
   constexpr int NG = NSUB * IT * NW;  // (sub-tile, row, wave) groups; group q covers slots [64q, 64q + 64)
   constexpr int GPL = (NG + 63) / 64;  // groups per lane of wave 0
+  constexpr int RS = REG ? NSUB : 1;   // sub-tiles held in registers
   static_assert(IT <= 32, "row masks are 32-bit");
 
   __shared__ uint32_t s_cnt[NG];  // per group left counts, then exclusive prefixes over the tile
@@ -220,22 +223,22 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
     const int j0 = static_cast<int>(g.lo / SUB);
     const int j1 = static_cast<int>((g.hi + SUB - 1) / SUB);
 
-    // ---- count pass (the next sub-tile is loaded while this one is classified)
+    T kr[RS][IT];                           // REG: the tile's keys
+    uint32_t vr[(REG && PAIRS) ? RS : 1][IT];  // REG: its payloads
+    uint32_t lmr[RS], vmr[RS];              // REG: class and validity masks per sub-tile
+
+    // ---- count pass
     {
       for (int j = 0; j < NSUB; ++j)
         if ((j < j0 || j >= j1) && lane < IT) s_cnt[(j * IT + lane) * NW + wv] = 0;
       bool has_d = false, has_a = false;
-      T k[IT], kn[IT];
-      load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
-#pragma unroll 1
-      for (int j = j0; j < j1; ++j) {
+      // one sub-tile: classify, then per (row, wave) group its left count and edge keys
+      auto count_sub = [&](int j, const T (&k)[IT], uint32_t& lmask, uint32_t& vmask) {
         const uint32_t s0 = static_cast<uint32_t>(j * SUB);
-        if (j + 1 < j1) load_sub<T, NT, IT>(d.chunk + s0 + SUB, c.n, src, tid, kn);
         uint32_t* gc = s_cnt + j * IT * NW;
         T* gf = s_first + j * IT * NW;
         T* gl = s_last + j * IT * NW;
         const bool full = s0 >= g.lo && s0 + SUB <= g.hi && s0 + SUB < g.erel && !(g.pl >= s0 && g.pl < s0 + SUB);
-        uint32_t lmask, vmask;
         if (full)
           classify<K, NT, IT, true, true>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, has_d, has_a);
         else
@@ -249,8 +252,34 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
           }
           if (lane == 63) gl[i * NW + wv] = k[i];
         }
+      };
+      if constexpr (REG) {
+        // every sub-tile's loads are issued at once
 #pragma unroll
-        for (int i = 0; i < IT; ++i) k[i] = kn[i];
+        for (int j = 0; j < NSUB; ++j)
+          if (j >= j0 && j < j1) load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j * SUB), c.n, src, tid, kr[j]);
+#pragma unroll
+        for (int j = 0; j < NSUB; ++j)
+          if (j >= j0 && j < j1) count_sub(j, kr[j], lmr[j], vmr[j]);
+        if constexpr (PAIRS) {
+          // payloads travel while the counts are scanned
+#pragma unroll
+          for (int j = 0; j < NSUB; ++j)
+            if (j >= j0 && j < j1)
+              load_sub<uint32_t, NT, IT>(d.chunk + static_cast<uint32_t>(j * SUB), c.n, srcv, tid, vr[j]);
+        }
+      } else {
+        // the next sub-tile is loaded while this one is classified
+        T k[IT], kn[IT];
+        load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+#pragma unroll 1
+        for (int j = j0; j < j1; ++j) {
+          if (j + 1 < j1) load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>((j + 1) * SUB), c.n, src, tid, kn);
+          uint32_t lmask, vmask;
+          count_sub(j, k, lmask, vmask);
+#pragma unroll
+          for (int i = 0; i < IT; ++i) k[i] = kn[i];
+        }
       }
       const bool wd = __any(has_d), wa = __any(has_a);
       if (lane == 0 && (wd || wa))
@@ -259,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
     }
     lds_barrier();  // B1: group counts, group edge keys, in-group pair bits
 
-    // ---- wave 0: edge pairs, scan, publish, decoupled look-back -------------
+    // ---- wave 0: edge pairs, scan, reservation ----------------------------------
     if (wv == 0) {
       uint32_t loc[GPL];
       uint32_t sum = 0;
@@ -281,118 +310,60 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
       const uint64_t incl = wave_incl_scan_u64(sum);
       const uint32_t nl = static_cast<uint32_t>(__shfl(incl, 63, 64));
       const bool wd = __any(ed), wa = __any(ea);
-      const uint64_t own_bits = (static_cast<uint64_t>(s_bits) << 32) | (wd ? kStDesc : 0ull) | (wa ? kStAsc : 0ull);
-      // publish this tile's aggregate (or its inclusive prefix) at once
-      if (lane == 0) store_status(&c.status[t], (d.tis == 0 ? kStIncl : kStAgg) | nl | own_bits);
+      const uint32_t own_bits = s_bits | (wd ? static_cast<uint32_t>(kStDesc >> 32) : 0u) |
+                                (wa ? static_cast<uint32_t>(kStAsc >> 32) : 0u);
       uint32_t run = static_cast<uint32_t>(incl) - sum;
 #pragma unroll
       for (int kk = 0; kk < GPL; ++kk) {
         if (lane * GPL + kk < NG) s_cnt[lane * GPL + kk] = run;
         run += loc[kk];
       }
-      uint64_t ex = 0, exb = 0;
-      if (d.tis != 0) {
-        uint32_t look = t - 1;
-        uint32_t rem = d.tis;  // tiles of this segment before this one
-        for (;;) {
-          uint64_t w = kStIncl;  // lanes past the segment's first tile read as an empty prefix
-          if (static_cast<uint32_t>(lane) < rem) w = load_status(&c.status[look - lane]);
-          const uint64_t st = w & kStStateMask;
-          const uint64_t im = __ballot(st == kStIncl);
-          const uint64_t nm = __ballot(st == 0);
-          const int fi = im ? static_cast<int>(__builtin_ctzll(im)) : 64;
-          const uint64_t upto = fi >= 63 ? ~0ull : ((2ull << fi) - 1);
-          if (nm & upto) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          const bool take = lane <= fi;
-          const uint64_t cnt = take ? (w & kStCountMask) : 0ull;
-          const uint64_t bb = take ? (w & (kStDesc | kStAsc)) : 0ull;
-          if (fi < 64) {
-            // suffix sums over lanes k..fi are the inclusive prefixes of the
-            // tiles between the one found and this one: publish them too
-            uint64_t sc = cnt, sb = bb;
-            for (int dd = 1; dd < 64; dd <<= 1) {
-              const uint64_t tc = __shfl_down(sc, dd, 64);
-              const uint64_t tb = __shfl_down(sb, dd, 64);
-              if (lane + dd < 64) {
-                sc += tc;
-                sb |= tb;
-              }
-            }
-            if (lane < fi) store_status(&c.status[look - lane], kStIncl | sc | sb);
-            ex += __shfl(sc, 0, 64);
-            exb |= __shfl(sb, 0, 64);
-            break;
-          }
-          ex += wave_sum_u64(cnt);
-          exb |= wave_or_u64(bb);
-          look -= 64;
-          rem -= 64;
-        }
-        if (lane == 0) store_status(&c.status[t], kStIncl | (ex + nl) | exb | own_bits);
-      }
       if (lane == 0) {
-        s_lpre = ex;
+        // reserve this tile's places: left keys from the segment start, the
+        // others from its end, in one atomic on the segment's packed cursor
+        const bool piv_in = g.pl >= g.lo && g.pl < g.hi;
+        const uint32_t nvalid = (g.hi - g.lo) - (piv_in ? 1u : 0u);
+        const uint64_t add = static_cast<uint64_t>(nl) | (static_cast<uint64_t>(nvalid - nl) << 32);
+        const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&segs[d.si].left), add);
+        if (own_bits) atomicOr(&segs[d.si].order_bits, own_bits);
+        s_lpre = old;
         s_nl = nl;
         s_bits = 0;  // ready for the next tile (all reads of it are done)
-        if (d.tis == d.nts - 1) {
-          segs[d.si].left = ex + nl;
-          segs[d.si].order_bits = static_cast<uint32_t>((exb | own_bits) >> 32);
-        }
       }
     }
-    lds_barrier();  // B2: group prefixes, tile prefix and count
+    lds_barrier();  // B2: group prefixes, the tile's places
 
     uint32_t nticket = 0;
     if (tid == 0) nticket = atomicAdd(&c.ctr->ticket, 1u);  // returns while the tile is written out
 
-    // ---- scatter pass: reload, classify again, write from registers ---------
+    // ---- scatter pass: write from registers ---------------------------------
     {
       const uint32_t nl = __builtin_amdgcn_readfirstlane(s_nl);
-      const uint64_t lpre = (static_cast<uint64_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre >> 32)))
-                             << 32) |
-                            __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre));
-      const uint64_t tlo = d.chunk + g.lo;
-      const uint64_t pre_valid = (tlo - d.b) - (d.pidx < tlo ? 1u : 0u);
+      const uint64_t lpre = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre));        // left keys placed before
+      const uint64_t gpre = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(s_lpre >> 32));  // right keys placed before
       const bool piv_in = g.pl >= g.lo && g.pl < g.hi;
       const uint32_t nvalid = (g.hi - g.lo) - (piv_in ? 1u : 0u);
-      // lpre <= pre_valid and nl <= nvalid bound every write below inside
-      // [b, e); they always hold unless the look-back is broken, in which
-      // case the tile writes nothing and flags the call
-      const bool sane = lpre <= pre_valid && nl <= nvalid;
+      // the reservations of all tiles add up to the segment's size minus the
+      // pivot, so every write below stays inside [b, e); a tile whose
+      // reservation does not fit (a broken counter) writes nothing and
+      // flags the call
+      const bool sane = nl <= nvalid && lpre + gpre + nvalid <= (d.e - d.b) - 1u;
       if (!sane && tid == 0) atomicOr(&c.ctr->errors, kErrLookback);
       if (sane) {
         const uint32_t nr = nvalid - nl;
-        const uint64_t gpre = pre_valid - lpre;
         // left keys of this tile occupy [b + lpre, b + lpre + nl); right keys
         // occupy [e - gpre - nr, e - gpre) in descending order of their rank
         T* __restrict__ dl = dst + (d.b + lpre);
         T* __restrict__ drl = dst + (d.e - gpre - nr);
         uint32_t* __restrict__ dlv = PAIRS ? dstv + (d.b + lpre) : nullptr;
         uint32_t* __restrict__ drlv = PAIRS ? dstv + (d.e - gpre - nr) : nullptr;
-        T k[IT], kn[IT];
-        uint32_t v[PAIRS ? IT : 1], vn[PAIRS ? IT : 1];
-        load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
-        if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, srcv, tid, v);
-#pragma unroll 1
-        for (int j = j0; j < j1; ++j) {
+        // one sub-tile's writes, given its keys, payloads and masks
+        auto scatter_sub = [&](int j, const T (&k)[IT], const uint32_t* v, uint32_t lmask, uint32_t vmask) {
           const uint32_t s0 = static_cast<uint32_t>(j * SUB);
-          if (j + 1 < j1) {
-            load_sub<T, NT, IT>(d.chunk + s0 + SUB, c.n, src, tid, kn);
-            if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + s0 + SUB, c.n, srcv, tid, vn);
-          }
           const bool full = s0 >= g.lo && s0 + SUB <= g.hi && !(g.pl >= s0 && g.pl < s0 + SUB);
           // real keys of the tile before slot s0 + x are x + adj for x in a
           // full sub-tile: adj = s0 - lo - (pivot before s0)
           const uint32_t adj = s0 - g.lo - ((piv_in && g.pl < s0) ? 1u : 0u);
-          uint32_t lmask, vmask;
-          bool dd_, da_;
-          if (full)
-            classify<K, NT, IT, true, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
-          else
-            classify<K, NT, IT, false, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
           const uint32_t* gc = s_cnt + j * IT * NW;
 #pragma unroll
           for (int i = 0; i < IT; ++i) {
@@ -413,10 +384,36 @@ __global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t sr
               }
             }
           }
+        };
+        if constexpr (REG) {
 #pragma unroll
-          for (int i = 0; i < IT; ++i) {
-            k[i] = kn[i];
-            if constexpr (PAIRS) v[i] = vn[i];
+          for (int j = 0; j < NSUB; ++j)
+            if (j >= j0 && j < j1) scatter_sub(j, kr[j], (REG && PAIRS) ? vr[j] : nullptr, lmr[j], vmr[j]);
+        } else {
+          T k[IT], kn[IT];
+          uint32_t v[PAIRS ? IT : 1], vn[PAIRS ? IT : 1];
+          load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+          if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, srcv, tid, v);
+#pragma unroll 1
+          for (int j = j0; j < j1; ++j) {
+            const uint32_t s0 = static_cast<uint32_t>(j * SUB);
+            if (j + 1 < j1) {
+              load_sub<T, NT, IT>(d.chunk + s0 + SUB, c.n, src, tid, kn);
+              if constexpr (PAIRS) load_sub<uint32_t, NT, IT>(d.chunk + s0 + SUB, c.n, srcv, tid, vn);
+            }
+            uint32_t lmask, vmask;
+            bool dd_ = false, da_ = false;
+            const bool fullc = s0 >= g.lo && s0 + SUB <= g.hi && !(g.pl >= s0 && g.pl < s0 + SUB);
+            if (fullc)
+              classify<K, NT, IT, true, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
+            else
+              classify<K, NT, IT, false, false>(k, g, s0, d.left_mode, pv, tid, lmask, vmask, dd_, da_);
+            scatter_sub(j, k, PAIRS ? v : nullptr, lmask, vmask);
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+              k[i] = kn[i];
+              if constexpr (PAIRS) v[i] = vn[i];
+            }
           }
         }
       }
@@ -443,12 +440,12 @@ int device_cus() {
   return cus;
 }
 
-template <class K, bool PAIRS, int NT, int IT, int NSUB>
+template <class K, bool PAIRS, int NT, int IT, int NSUB, bool REG>
 hipError_t launch_one(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, hipStream_t s) {
   static int per_cu = 0;
   if (per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_partition<K, PAIRS, NT, IT, NSUB>, NT, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_partition<K, PAIRS, NT, IT, NSUB, REG>, NT, 0) !=
             hipSuccess ||
         nb <= 0)
       nb = 1;
@@ -457,21 +454,21 @@ hipError_t launch_one(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, h
   uint64_t grid = static_cast<uint64_t>(per_cu) * device_cus();
   if (grid > ntiles) grid = ntiles;
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_partition<K, PAIRS, NT, IT, NSUB>), dim3(static_cast<uint32_t>(grid)), dim3(NT), 0, s, c, parity,
-                     src);
+  hipLaunchKernelGGL((k_partition<K, PAIRS, NT, IT, NSUB, REG>), dim3(static_cast<uint32_t>(grid)), dim3(NT), 0, s, c,
+                     parity, src);
   return hipGetLastError();
 }
 
 template <class K, bool PAIRS>
 hipError_t launch_tiles(const Ctx& c, int parity, uint32_t ntiles, uint32_t src, hipStream_t s) {
   switch (c.tile) {
-    case 1024: return launch_one<K, PAIRS, 256, 4, 1>(c, parity, ntiles, src, s);
-    case 2048: return launch_one<K, PAIRS, 256, 8, 1>(c, parity, ntiles, src, s);
-    case 4096: return launch_one<K, PAIRS, 256, 16, 1>(c, parity, ntiles, src, s);
-    case 8192: return launch_one<K, PAIRS, 256, 8, 4>(c, parity, ntiles, src, s);
-    case 16384: return launch_one<K, PAIRS, 256, 8, 8>(c, parity, ntiles, src, s);
-    case 32768: return launch_one<K, PAIRS, 256, 8, 16>(c, parity, ntiles, src, s);
-    case 65536: return launch_one<K, PAIRS, 256, 16, 16>(c, parity, ntiles, src, s);
+    case 1024: return launch_one<K, PAIRS, 256, 4, 1, true>(c, parity, ntiles, src, s);
+    case 2048: return launch_one<K, PAIRS, 256, 8, 1, true>(c, parity, ntiles, src, s);
+    case 4096: return launch_one<K, PAIRS, 256, 16, 1, true>(c, parity, ntiles, src, s);
+    case 8192: return launch_one<K, PAIRS, 256, 8, 4, true>(c, parity, ntiles, src, s);
+    case 16384: return launch_one<K, PAIRS, 512, 8, 4, true>(c, parity, ntiles, src, s);
+    case 32768: return launch_one<K, PAIRS, 1024, 8, 4, true>(c, parity, ntiles, src, s);
+    case 65536: return launch_one<K, PAIRS, 256, 16, 16, false>(c, parity, ntiles, src, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -167,8 +167,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   }
 }
 
-// Ticket -> segment map for the partition kernel, and a cleared status word
-// per ticket.
+// Ticket -> segment map for the partition kernel.
 __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint32_t ntiles) {
   const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (t0 == 0) c.ctr->ticket = 0;
@@ -185,7 +184,6 @@ __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint
       else hi = mid - 1;
     }
     c.tilemap[t] = lo;
-    c.status[t] = 0;
   }
 }
 
@@ -204,12 +202,14 @@ __device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t 
   const bool asc_sorted = no_desc;           // non-decreasing in the source buffer
   const bool desc_sorted = !no_desc && no_asc; // non-increasing in the source buffer
   bool split = live && !asc_sorted && !desc_sorted;
-  if (split && s.left >= size) {
+  // the partition kernel's packed cursor: keys placed left (low half) and
+  // right (high half) of the pivot
+  const uint64_t L = static_cast<uint32_t>(s.left);
+  if (split && L >= size) {
     atomicOr(&c.ctr->errors, kErrSplit);
     split = false;
   }
   const bool is_left = s.mode == kModeLeft;
-  const uint64_t L = s.left;
   const uint64_t R = size - 1 - L;
   const bool bad = split && !is_left && (L < (size >> 3) || R < (size >> 3));
 

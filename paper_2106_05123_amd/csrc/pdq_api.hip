@@ -3,8 +3,9 @@
 // One call runs partition passes until no live segment is left. Every pass
 // launches, on the caller's stream:
 //   pivot    one lane per live segment: ninther + predecessor rule
-//   tilemap  one lane per tile ticket: ticket -> segment, cleared status
-//   partition  persistent tiles with decoupled look-back (the hot kernel)
+//   tilemap  one lane per tile ticket: ticket -> segment
+//   partition  persistent tiles, each reserving its places in its segment
+//            with one atomic (the hot kernel)
 //   bookkeep one lane per live segment: pivot placement, retirement,
 //            budget, children filed as live / base case / heapsort / copy
 // then reads a few counters back to size the next pass and runs the
@@ -42,6 +43,12 @@ thread_local int g_last_hip = 0;
 constexpr size_t kAlign = 256;
 constexpr uint32_t kMinTile = 1024;
 constexpr uint32_t kDefaultTile = 32768;
+
+// Partition tile for segments of `avg` keys on average, when the caller did
+// not fix one: large tiles while segments span many of them (fewer
+// reservations on each segment's cursor), 8192 once they hold a few hundred
+// thousand keys or less (less of each tile lies outside its segment).
+uint32_t auto_tile(uint64_t avg) { return avg >= (1ull << 18) ? 32768u : 8192u; }
 constexpr uint32_t kMaxPasses = 20000;  // far above any reachable pass count; a guard against bugs
 
 constexpr uint64_t kLearnSample = PDQ_LEARN_SAMPLE;
@@ -51,7 +58,7 @@ constexpr uint32_t kMaxLearnSteps = 65536;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0, status = 0;
+  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0;
   size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
@@ -156,7 +163,6 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
   L.segs0 = take(sizeof(Seg) * L.max_active);
   L.segs1 = take(sizeof(Seg) * L.max_active);
   L.tilemap = take(4ull * L.max_tiles);
-  L.status = take(8ull * L.max_tiles);
   for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
   L.heap = take(sizeof(Item) * L.max_items);
   L.copy = take(sizeof(Item) * L.max_items);
@@ -456,7 +462,6 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.segs[0] = reinterpret_cast<Seg*>(base + L.segs0);
   c.segs[1] = reinterpret_cast<Seg*>(base + L.segs1);
   c.tilemap = reinterpret_cast<uint32_t*>(base + L.tilemap);
-  c.status = reinterpret_cast<uint64_t*>(base + L.status);
   for (int k = 0; k < kBaseClasses; ++k) c.base[k] = reinterpret_cast<Item*>(base + L.base[k]);
   c.heap = reinterpret_cast<Item*>(base + L.heap);
   c.copy = reinterpret_cast<Item*>(base + L.copy);
@@ -658,6 +663,8 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
+  // the tile of the first pass, from the average size of its segments
+  if (!o.tile) c.tile = auto_tile(learned ? n / 256 : n / (offsets ? nseg : 1));
   LearnedResult lres;
   uint32_t src = 0;
   if (learned) {
@@ -665,6 +672,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     rc = run_learned(c, o, L, base, prof, lres, s);
     if (rc != PDQ_OK) return rc;
     if (lres.state == 1) src = 1;
+    else if (!o.tile) c.tile = auto_tile(n);  // judged and fell back: one segment [0, n)
   }
   if (src == 0) HIP_TRY(launch_init(c, s));
   rc = read_counters(c, &snap, s);
@@ -703,6 +711,9 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
         (void)hipEventRecord(tm.b, s);
         timed.push_back(tm);
       }
+      // the children filed now are tiled for the next pass: about two per
+      // segment, sharing its keys
+      if (!o.tile) c.tile = auto_tile(snap.elems[parity] / (2ull * nact));
       if ((e = launch_bookkeep(c, parity, nact, src, pass, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
     } while (0);
     if (r2 == PDQ_OK) r2 = read_counters(c, &snap, s);

@@ -16,17 +16,12 @@ constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh c
 constexpr uint32_t kModeRight = 0u;
 constexpr uint32_t kModeLeft = 1u;
 
-// Tile status word of the decoupled look-back (64 bits):
-//   [63:62] state (0 empty, 1 aggregate, 2 inclusive prefix)
-//   [61]    some adjacent pair descends   (OR over the covered tiles)
-//   [60]    some adjacent pair ascends
-//   [59:0]  count of keys going left
-constexpr uint64_t kStAgg = 1ull << 62;
-constexpr uint64_t kStIncl = 2ull << 62;
-constexpr uint64_t kStStateMask = 3ull << 62;
+// Order bits of a segment, as ORed by its tiles (positions in a 64-bit word;
+// Seg::order_bits holds them shifted down by 32):
+//   kStDesc  some adjacent pair descends
+//   kStAsc   some adjacent pair ascends
 constexpr uint64_t kStDesc = 1ull << 61;
 constexpr uint64_t kStAsc = 1ull << 60;
-constexpr uint64_t kStCountMask = (1ull << 60) - 1;
 
 // One live segment of a partition pass. Positions are absolute indices into
 // the key arrays; the segment's keys sit in the pass's source buffer.
@@ -35,13 +30,14 @@ struct Seg {
   uint64_t end;
   uint64_t pivot;      // raw key bits of the pivot (pivot kernel)
   uint64_t pidx;       // absolute position of the pivot element in the source buffer
-  uint64_t left;       // keys that went left, pivot excluded (last tile of the segment)
+  uint64_t left;       // partition cursor: keys placed left of the pivot (low 32 bits) and
+                       // right of it (high 32 bits), reserved tile by tile
   uint32_t tile_base;  // first tile ticket of the segment in this pass
   uint32_t ntiles;
   uint32_t budget;     // bad partitions still allowed (Section 4.1)
   uint32_t flags;      // kSegLeftmost | kSegFresh
   uint32_t mode;       // kModeRight / kModeLeft (pivot kernel)
-  uint32_t order_bits; // kStDesc | kStAsc >> 32 of the whole segment (last tile)
+  uint32_t order_bits; // kStDesc | kStAsc >> 32 of the whole segment (ORed by its tiles)
 };
 
 // A range handed to a finishing kernel: base case, heapsort or a plain
@@ -75,7 +71,7 @@ struct Counters {
 };
 
 constexpr uint32_t kErrCapacity = 1u;  // a list append found its list full (only reachable with bad offsets)
-constexpr uint32_t kErrLookback = 2u;  // a tile's prefix did not fit its segment
+constexpr uint32_t kErrLookback = 2u;  // a tile's reservation did not fit its segment
 constexpr uint32_t kErrSplit = 4u;     // a segment's left count did not fit the segment
 
 // Everything a kernel needs to know about one sort call.
@@ -85,7 +81,6 @@ struct Ctx {
   uint64_t n;
   Seg* segs[2];         // live-segment lists, indexed by pass parity
   uint32_t* tilemap;    // ticket -> segment index
-  uint64_t* status;     // ticket -> look-back status word
   Item* base[kBaseClasses];
   Item* heap;
   Item* copy;
@@ -94,7 +89,7 @@ struct Ctx {
   uint64_t nseg;
   uint32_t tile;        // keys per partition tile
   uint32_t max_active;  // capacity of each live-segment list
-  uint32_t max_tiles;   // capacity of tilemap / status
+  uint32_t max_tiles;   // capacity of tilemap
   uint32_t max_items;   // capacity of each item list
   int32_t force_budget;
   uint32_t key_type;
