@@ -76,7 +76,7 @@ def profiled_traffic():
     """HBM bytes per partition launch measured with rocprofv3 counters (see
     profiles/), or None when the kernel source changed since."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "partition_i32_2p28_traffic.md")
+    prof = os.path.join(ROOT, "profiles", "partition_u32_2p28_learned_traffic.md")
     src = os.path.join(ROOT, "paper_2106_05123_amd", "csrc", "k_partition.hip")
     try:
         fields = {}
@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-segmented", action="store_true")
     ap.add_argument("--seg-count", type=int, default=65536)
+    ap.add_argument("--forms", default="plain,learned",
+                    help="comma list of the 2^n forms to time (the learned one is the headline value)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -160,7 +162,11 @@ def main():
     lopt = pdq.Options(ctypes.sizeof(pdq.Options), pdq.FLAG_LEARNED, -1, args.tile, 0, 0.0, 0, 0, 0)
     ws = torch.empty(pdq.workspace_bytes(n, 1, "u32", options=lopt), dtype=torch.uint8, device=dev)
 
-    forms = {"plain": dict(tile=args.tile), "learned": dict(tile=args.tile, learned=True)}
+    wanted = [f for f in args.forms.split(",") if f]
+    if "learned" not in wanted or any(f not in ("plain", "learned") for f in wanted):
+        raise SystemExit("bench: --forms must list 'learned' (the headline form), optionally with 'plain'")
+    forms = {k: v for k, v in (("plain", dict(tile=args.tile)), ("learned", dict(tile=args.tile, learned=True)))
+             if k in wanted}
     results = {}
     for name, kw in forms.items():
         work.copy_(pristine)
@@ -179,14 +185,16 @@ def main():
 
     ms, stats, wall = results["learned"]
     learned, part_ms, part_bytes, launches = summarize(ms, stats, n)
-    plain, p_part_ms, p_part_bytes, p_launches = summarize(*results["plain"][:2], n)
-    p_stats = results["plain"][1]
+    plain = None
+    if "plain" in results:
+        plain, p_part_ms, p_part_bytes, p_launches = summarize(*results["plain"][:2], n)
+        p_stats = results["plain"][1]
+        fp_ms = float(np.mean([s["first_pass_ms"] for s in p_stats]))
+        fp_bytes = p_stats[0]["first_pass_bytes"]
+        fp_gbs = fp_bytes / (fp_ms * 1e-3) / 1e9
     ms_step = float(np.mean(ms))
     value = n / (ms_step * 1e-3)
     achieved = part_bytes / (part_ms * 1e-3) / 1e9 if part_ms > 0 else 0.0
-    fp_ms = float(np.mean([s["first_pass_ms"] for s in p_stats]))
-    fp_bytes = p_stats[0]["first_pass_bytes"]
-    fp_gbs = fp_bytes / (fp_ms * 1e-3) / 1e9
 
     # achievable ceiling on this machine: a device-to-device copy of the same bytes
     cms = []
@@ -219,9 +227,9 @@ def main():
                             if "scatter_GBps" in learned else None},
         "plain_partition": {"GB/s": plain["partition_GBps"],
                             "frac": round(plain["partition_GBps"] / HBM_PEAK_GBS, 4),
-                            "avg_launch_ms": round(p_part_ms / max(p_launches, 1), 4)},
+                            "avg_launch_ms": round(p_part_ms / max(p_launches, 1), 4)} if plain else None,
         "plain_first_pass": {"ms": round(fp_ms, 4), "bytes": int(fp_bytes), "GB/s": round(fp_gbs, 1),
-                             "frac": round(fp_gbs / HBM_PEAK_GBS, 4)},
+                             "frac": round(fp_gbs / HBM_PEAK_GBS, 4)} if plain else None,
         "copy_ceiling_GBps": round(copy_gbs, 1),
     }
 
@@ -274,9 +282,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pdq_sort with the learned first pass of 2^{args.log2n} uint32 keys, "
                                f"uniform random (seed 0), keys only",
-                   "n": n, "key_type": "u32", "tile": args.tile or 32768},
+                   "n": n, "key_type": "u32",
+                   "tile": args.tile or "per pass: 32768 while segments average >= 2^18 keys, else 8192"},
         "forms": {"learned": learned, "plain": plain,
-                  "learned_over_plain": round(plain["ms"] / learned["ms"], 3)},
+                  "learned_over_plain": round(plain["ms"] / learned["ms"], 3) if plain else None},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "patterns_i32": patterns,
@@ -359,9 +368,10 @@ def bench_segmented(pdq, torch, W, dev, args):
                       "partition_GBps": round(s0["partition_bytes"] / (s0["partition_ms"] * 1e-3) / 1e9, 1)
                       if s0["partition_ms"] else None},
             "batched_eager": {"keys/s": round(n / (mb * 1e-3), 0), "ms": round(mb, 3),
-                              "queue_items": st_b[0]["batch_items"], "shape": list(pdq.BATCH_SHAPES[shape])},
+                              "queue_items": st_b[0]["batch_items"], "passes": st_b[0]["passes"],
+                              "shape": {"tile": pdq.BATCH_SHAPES[shape][0], "wide_class_slots": pdq.BATCH_SHAPES[shape][1]}},
             "batched_graph": {"keys/s": round(n / (mg * 1e-3), 0), "ms": round(mg, 3),
-                              "shape": list(pdq.BATCH_SHAPES[shape]),
+                              "shape": {"tile": pdq.BATCH_SHAPES[shape][0], "wide_class_slots": pdq.BATCH_SHAPES[shape][1]},
                               "autotune_ms_per_shape": [round(x, 3) for x in tune_ms]},
             "batched_over_plain": round(mp / mg, 3)}
 

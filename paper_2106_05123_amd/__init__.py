@@ -39,7 +39,8 @@ FLAG_PROFILE = 2
 FLAG_LEARNED = 4
 FLAG_BATCHED = 8
 FLAG_AUTOTUNE = 16
-BATCH_SHAPES = ((512, 8), (512, 16), (1024, 8), (1024, 16))
+# batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
+BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
 MAX_SPLITTERS = 255
 LEARN_SAMPLE = 65536
