@@ -77,7 +77,7 @@ def profiled_traffic():
     profiles/), or None when the kernel source changed since."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "partition_u32_2p28_learned_traffic.md")
-    src = os.path.join(ROOT, "paper_2106_05123_amd", "csrc", "k_partition.hip")
+    src = os.path.join(ROOT, "paper_2106_05123_amd", "csrc", "partition_kernel.h")
     try:
         fields = {}
         for ln in open(prof):

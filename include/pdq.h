@@ -91,9 +91,14 @@ enum pdq_flags {
                              queue, no host synchronisation (unless stats or PDQ_VALIDATE);
                              meant for many segments of up to ~2^20 keys each; pass the same
                              options to pdq_workspace_bytes */
-  PDQ_AUTOTUNE = 1u << 4  /* pdq_plan_create: time every persistent-kernel shape on the
-                             caller's data first and keep the fastest (needs the workspace
+  PDQ_AUTOTUNE = 1u << 4, /* pdq_plan_create: time every batched shape on the caller's data
+                             first and keep the fastest (needs the workspace
                              pdq_workspace_bytes gives with this flag) */
+  PDQ_DETERMINISTIC = 1u << 5 /* partition tiles take their places in tile order by a decoupled
+                             look-back instead of one atomic reservation each: every run then
+                             arranges the keys (and the payloads of equal keys) identically.
+                             Slower. The learned pass's scatter still orders keys inside a bin
+                             by LDS atomics, so with PDQ_LEARNED it covers the passes only */
 };
 
 typedef struct pdq_options {

@@ -26,7 +26,7 @@ __all__ = [
     "PdqError", "Options", "Stats", "lib", "workspace_bytes", "sort_", "sort_pairs_",
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
-    "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "FLAG_BATCHED", "FLAG_AUTOTUNE",
+    "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
     "Plan",
 ]
 
@@ -39,6 +39,7 @@ FLAG_PROFILE = 2
 FLAG_LEARNED = 4
 FLAG_BATCHED = 8
 FLAG_AUTOTUNE = 16
+FLAG_DETERMINISTIC = 32
 # batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
 BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
@@ -242,12 +243,14 @@ def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_
 
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
           workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
-          learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0):
+          learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False):
     """Sort a 1-D device tensor in place (ascending canonical order).
-    learned=True runs the learned multiway first pass (see pdq_learned.h)."""
+    learned=True runs the learned multiway first pass (see pdq_learned.h);
+    deterministic=True selects the look-back partition (PDQ_DETERMINISTIC)."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
-                                         (FLAG_PROFILE if profile else 0) | lf, workspace, learn)
+                                         (FLAG_PROFILE if profile else 0) | lf |
+                                         (FLAG_DETERMINISTIC if deterministic else 0), workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
                         need, stream, ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
@@ -257,11 +260,13 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
 
 def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
-                imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0):
+                imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
+                deterministic: bool = False):
     """Sort keys in place and move the uint32 payload `vals` with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
-                                         (FLAG_PROFILE if profile else 0) | lf, workspace, learn)
+                                         (FLAG_PROFILE if profile else 0) | lf |
+                                         (FLAG_DETERMINISTIC if deterministic else 0), workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),
                               kt, 0, ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
@@ -272,7 +277,8 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
 
 def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: int = 0,
                     validate: bool = False, profile: bool = False, stats: bool = False, workspace=None,
-                    batched: bool = False, batch_shape: int = 0, batch_passes: int | None = None):
+                    batched: bool = False, batch_shape: int = 0, batch_passes: int | None = None,
+                    deterministic: bool = False):
     """Sort each segment [offsets[s], offsets[s+1]) of keys in place.
     offsets: uint64 device tensor of nseg+1 entries. batched=True runs the
     batched form (batch_shape 1..4 forces a shape, batch_passes the number of
@@ -281,7 +287,8 @@ def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: i
     if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
         raise ValueError("offsets must be a contiguous uint64 device tensor")
     nseg = offsets.numel() - 1
-    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0)
+    flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0) \
+        | (FLAG_DETERMINISTIC if deterministic else 0)
     kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace,
                                          dict(batch_shape=batch_shape, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None

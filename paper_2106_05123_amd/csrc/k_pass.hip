@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   }
 }
 
-// Ticket -> segment map for the partition kernel.
+// Ticket -> segment map for the partition kernel (and, for the look-back
+// partition, a cleared status word per ticket).
 __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint32_t ntiles) {
   const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (t0 == 0) c.ctr->ticket = 0;
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint
       else hi = mid - 1;
     }
     c.tilemap[t] = lo;
+    if (c.lookback) c.status[t] = 0;
   }
 }
 

@@ -58,7 +58,7 @@ constexpr uint32_t kMaxLearnSteps = 65536;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0;
+  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0, status = 0;
   size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
@@ -163,6 +163,7 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
   L.segs0 = take(sizeof(Seg) * L.max_active);
   L.segs1 = take(sizeof(Seg) * L.max_active);
   L.tilemap = take(4ull * L.max_tiles);
+  L.status = take(8ull * L.max_tiles);
   for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
   L.heap = take(sizeof(Item) * L.max_items);
   L.copy = take(sizeof(Item) * L.max_items);
@@ -234,7 +235,8 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, batch_shape) + sizeof(uint32_t)) out->batch_shape = o->batch_shape;
   if (sz >= offsetof(pdq_options, batch_passes) + sizeof(uint32_t)) out->batch_passes = o->batch_passes;
   if (out->flags &
-      ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE))
+      ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
+                             PDQ_DETERMINISTIC))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->batch_passes > kMaxBatchPasses + 1) return PDQ_ERR_UNSUPPORTED;
@@ -462,6 +464,7 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.segs[0] = reinterpret_cast<Seg*>(base + L.segs0);
   c.segs[1] = reinterpret_cast<Seg*>(base + L.segs1);
   c.tilemap = reinterpret_cast<uint32_t*>(base + L.tilemap);
+  c.status = reinterpret_cast<uint64_t*>(base + L.status);
   for (int k = 0; k < kBaseClasses; ++k) c.base[k] = reinterpret_cast<Item*>(base + L.base[k]);
   c.heap = reinterpret_cast<Item*>(base + L.heap);
   c.copy = reinterpret_cast<Item*>(base + L.copy);
@@ -479,6 +482,7 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.seed = o.seed;
   c.base_max = kBaseMax;
   c.wide_e = 16;
+  c.lookback = (o.flags & PDQ_DETERMINISTIC) ? 1u : 0u;
   return c;
 }
 

@@ -16,12 +16,21 @@ constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh c
 constexpr uint32_t kModeRight = 0u;
 constexpr uint32_t kModeLeft = 1u;
 
-// Order bits of a segment, as ORed by its tiles (positions in a 64-bit word;
-// Seg::order_bits holds them shifted down by 32):
+// Order bits of a segment (positions in a 64-bit word; Seg::order_bits holds
+// them shifted down by 32):
 //   kStDesc  some adjacent pair descends
 //   kStAsc   some adjacent pair ascends
+// They also sit in the tile status words of the deterministic (look-back)
+// partition, whose layout is:
+//   [63:62] state (0 empty, 1 aggregate, 2 inclusive prefix)
+//   [61:60] kStDesc | kStAsc, ORed over the covered tiles
+//   [59:0]  count of keys going left
+constexpr uint64_t kStAgg = 1ull << 62;
+constexpr uint64_t kStIncl = 2ull << 62;
+constexpr uint64_t kStStateMask = 3ull << 62;
 constexpr uint64_t kStDesc = 1ull << 61;
 constexpr uint64_t kStAsc = 1ull << 60;
+constexpr uint64_t kStCountMask = (1ull << 60) - 1;
 
 // One live segment of a partition pass. Positions are absolute indices into
 // the key arrays; the segment's keys sit in the pass's source buffer.
@@ -31,7 +40,8 @@ struct Seg {
   uint64_t pivot;      // raw key bits of the pivot (pivot kernel)
   uint64_t pidx;       // absolute position of the pivot element in the source buffer
   uint64_t left;       // partition cursor: keys placed left of the pivot (low 32 bits) and
-                       // right of it (high 32 bits), reserved tile by tile
+                       // right of it (high 32 bits), reserved tile by tile; with the
+                       // look-back, the left count written by the segment's last tile
   uint32_t tile_base;  // first tile ticket of the segment in this pass
   uint32_t ntiles;
   uint32_t budget;     // bad partitions still allowed (Section 4.1)
@@ -81,6 +91,7 @@ struct Ctx {
   uint64_t n;
   Seg* segs[2];         // live-segment lists, indexed by pass parity
   uint32_t* tilemap;    // ticket -> segment index
+  uint64_t* status;     // ticket -> look-back status word (deterministic partition only)
   Item* base[kBaseClasses];
   Item* heap;
   Item* copy;
@@ -89,7 +100,7 @@ struct Ctx {
   uint64_t nseg;
   uint32_t tile;        // keys per partition tile
   uint32_t max_active;  // capacity of each live-segment list
-  uint32_t max_tiles;   // capacity of tilemap
+  uint32_t max_tiles;   // capacity of tilemap / status
   uint32_t max_items;   // capacity of each item list
   int32_t force_budget;
   uint32_t key_type;
@@ -100,6 +111,8 @@ struct Ctx {
   uint64_t seed;        // seeds the candidate positions taken after a bad partition
   uint32_t base_max;    // segments of at most this many keys go to the LDS base case
   uint32_t wide_e;      // slots per lane of the 8192 / 16384 classes (16 or 32)
+  uint32_t lookback;    // 1: tiles take their places by a decoupled look-back (deterministic order)
+  uint32_t pad1_;
 };
 
 // ---- key traits: canonical unsigned image in registers only ---------------

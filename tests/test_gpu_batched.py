@@ -204,3 +204,18 @@ def test_batched_full_workload_sampled():
     assert np.array_equal(np.sort(vo), np.arange(out.size, dtype=np.uint32))
     assert np.array_equal(out.view(np.uint32), keys[vo].view(np.uint32))
     assert st["passes"] > 0
+
+
+def test_batched_deterministic_repeat_exactly():
+    """PDQ_DETERMINISTIC with the batched form: the captured passes use the
+    look-back partition, and the tail and LDS classes are deterministic
+    anyway, so two runs agree on every payload."""
+    off = W.offsets_from_sizes(mixed_sizes(21, extra=150, max_log2=17))
+    n = int(off[-1])
+    keys = (W.uniform_u32(n, seed=9) % np.uint32(50)).astype(np.uint32)
+    vals = W.index_payload(n)
+    o1, v1, s1 = run_batched(keys, off, vals, deterministic=True)
+    o2, v2, s2 = run_batched(keys, off, vals, deterministic=True)
+    check_segmented(keys, off, o1, v1)
+    assert np.array_equal(v1, v2)
+    assert s1["element_visits"] == s2["element_visits"]

@@ -218,3 +218,53 @@ def test_full_size_random_i32_sampled():
         lt = int(np.count_nonzero(a < v))
         le = int(np.count_nonzero(a <= v))
         assert lt <= r < le
+
+
+# ------------------------------------------------------------------ deterministic (look-back) form
+
+DET_STATS = ("passes", "element_visits", "partitions_right", "partitions_left", "bad_partitions",
+             "base_segments", "sorted_segments", "equal_elements")
+
+
+@pytest.mark.parametrize("tile", [0, 8192, 32768, 65536])
+@pytest.mark.parametrize("kt", ["u32", "u64"])
+def test_deterministic_pairs_repeat_exactly(kt, tile):
+    """PDQ_DETERMINISTIC: keys bit-exact against the oracle, and two runs give
+    the same payload order (also among equal keys) and the same recursion."""
+    n = (1 << 21) + 4321
+    if kt == "u64":
+        a = W.k_distinct_u64(n, 16, seed=3)
+    else:
+        a = (W.uniform_u32(n, seed=3) % np.uint32(1000)).astype(np.uint32)
+    vals = W.index_payload(n)
+    out1, v1, st1 = gpu_sort(a, vals, tile=tile, deterministic=True)
+    out2, v2, st2 = gpu_sort(a, vals, tile=tile, deterministic=True)
+    assert np.array_equal(as_bytes(out1), as_bytes(oracle.sort(a)[0]))
+    check_pairs(a, out1, v1)
+    assert np.array_equal(v1, v2)
+    assert np.array_equal(as_bytes(out1), as_bytes(out2))
+    assert {k: st1[k] for k in DET_STATS} == {k: st2[k] for k in DET_STATS}
+
+
+def test_deterministic_segmented_repeat_exactly():
+    keys, off, vals = W.segmented_f32(800, max_log2=17, seed=8)
+    res = []
+    for _ in range(2):
+        t, o, v = to_dev(keys), to_dev(off), to_dev(vals)
+        pdq.segmented_sort_(t, o, v, deterministic=True)
+        torch.cuda.synchronize()
+        res.append((t.cpu().numpy(), v.cpu().numpy()))
+    ref, _, _ = oracle.segmented_sort(keys, off)
+    assert np.array_equal(as_bytes(res[0][0]), as_bytes(ref))
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_default_form_agrees_with_deterministic_on_keys_and_first_pass():
+    """The default (reservation) form and the look-back form sort to the same
+    keys, and their first partitions coincide (same pivot, same left size)."""
+    a = W.uniform_u32((1 << 22) + 77, seed=12)
+    o1, _, s1 = gpu_sort(a)
+    o2, _, s2 = gpu_sort(a, deterministic=True)
+    assert np.array_equal(o1, o2)
+    assert s1["first_pivot_image"] == s2["first_pivot_image"]
+    assert s1["first_left_size"] == s2["first_left_size"]
