@@ -175,8 +175,13 @@ __device__ __forceinline__ void classify(const typename K::T (&k)[IT], const Til
 // before the reservation, so each key and payload crosses HBM exactly once
 // each way. Otherwise (tiles larger than the registers hold) the scatter
 // pass loads each sub-tile again and classifies it again.
-template <class K, bool PAIRS, int NT, int IT, int NSUB, bool REG, bool LB>
-__global__ __launch_bounds__(NT) void k_partition(Ctx c, int parity, uint32_t src_buf) {
+// WPE: waves per SIMD the register allocation must leave room for. 32-bit
+// register-resident tiles fit 4 (128 VGPRs) without spilling, which doubles
+// the workgroups a CU holds at once; 64-bit keys would spill, so they keep
+// the compiler's choice.
+template <class K, bool PAIRS, int NT, int IT, int NSUB, bool REG, bool LB,
+          int WPE = (REG && sizeof(typename K::T) == 4) ? 4 : 1>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_partition(Ctx c, int parity, uint32_t src_buf) {
   using T = typename K::T;
   constexpr int NW = NT / 64;
   constexpr int SUB = NT * IT;
