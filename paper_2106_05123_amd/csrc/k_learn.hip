@@ -203,7 +203,7 @@ struct TrainSmem {
   float w2t[kH * kH];             // W2 transposed: [u][v]
   float h1[kTrainChunk * kRow];   // [s][u]
   float h1t[kH * kRowT];          // [u][s]
-  float z2[kTrainChunk * kRow];   // [s][v]
+
   float z2t[kH * kRowT];          // [v][s]
   float dz2[kTrainChunk * kRow];  // [s][v]
   float dz2t[kH * kRowT];         // [v][s]
@@ -228,77 +228,84 @@ __device__ __forceinline__ void rebuild_w2t(TrainSmem& sm) {
   for (int i = threadIdx.x; i < kH * kH; i += kTrainThreads) sm.w2t[(i & 31) * kH + (i >> 5)] = sm.p[kOffW2 + i];
 }
 
+// Orders the LDS accesses of one wave (its lanes exchange values through
+// LDS without waiting for the rest of the workgroup).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Forward and backward of the chunk in sm.x / sm.t (cs valid samples, the
 // rest zero); adds its contribution to the gradient of the mean squared
 // error over `batch`. Padded samples get dL/dy = 0, so every gradient term
 // they would add is zero.
+//
+// Sixteen lanes handle one sample, two hidden units each; they share a wave,
+// so the whole forward and backward pass of a sample needs no workgroup
+// barrier. Only the parameter sums over the chunk's samples wait for the
+// workgroup.
 __device__ void chunk_grad(TrainSmem& sm, uint32_t cs, uint32_t batch, uint32_t residual, GradAcc& g) {
   const int tid = threadIdx.x;
-  // layer 1
-  for (int e = tid; e < static_cast<int>(kTrainChunk) * kH; e += kTrainThreads) {
-    const int s = e >> 5, u = e & 31;
-    const float h = relu(fmaf(sm.p[kOffW1 + u], sm.x[s], sm.p[kOffB1 + u]));
-    sm.h1[s * kRow + u] = h;
-    sm.h1t[u * kRowT + s] = h;
-  }
-  lds_barrier();
+  const int lane = tid & 63;
   const int s = tid >> 4, c0 = (tid & 15) * 2;  // one sample, two units
+  const float xs = sm.x[s];
+  // layer 1
+  const float h0 = relu(fmaf(sm.p[kOffW1 + c0], xs, sm.p[kOffB1 + c0]));
+  const float h1 = relu(fmaf(sm.p[kOffW1 + c0 + 1], xs, sm.p[kOffB1 + c0 + 1]));
+  sm.h1[s * kRow + c0] = h0;
+  sm.h1[s * kRow + c0 + 1] = h1;
+  sm.h1t[c0 * kRowT + s] = h0;
+  sm.h1t[(c0 + 1) * kRowT + s] = h1;
+  wave_sync();
   // layer 2
-  {
-    float a0 = sm.p[kOffB2 + c0], a1 = sm.p[kOffB2 + c0 + 1];
+  float a0 = sm.p[kOffB2 + c0], a1 = sm.p[kOffB2 + c0 + 1];
 #pragma unroll 8
-    for (int u = 0; u < kH; ++u) {
-      const float2 w = *reinterpret_cast<const float2*>(&sm.w2t[u * kH + c0]);
-      const float h = sm.h1[s * kRow + u];
-      a0 = fmaf(w.x, h, a0);
-      a1 = fmaf(w.y, h, a1);
-    }
-    sm.z2[s * kRow + c0] = a0;
-    sm.z2[s * kRow + c0 + 1] = a1;
-    sm.z2t[c0 * kRowT + s] = a0;
-    sm.z2t[(c0 + 1) * kRowT + s] = a1;
+  for (int u = 0; u < kH; ++u) {
+    const float2 w = *reinterpret_cast<const float2*>(&sm.w2t[u * kH + c0]);
+    const float h = sm.h1[s * kRow + u];
+    a0 = fmaf(w.x, h, a0);
+    a1 = fmaf(w.y, h, a1);
   }
-  lds_barrier();
-  // output: sixteen lanes per sample, combined by shuffles
-  {
-    float part = fmaf(sm.p[kOffW3 + c0], relu(sm.z2[s * kRow + c0]), 0.0f);
-    part = fmaf(sm.p[kOffW3 + c0 + 1], relu(sm.z2[s * kRow + c0 + 1]), part);
-    for (int d = 8; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
-    if ((tid & 15) == 0) {
-      float dy = 0.0f;
-      if (s < static_cast<int>(cs)) {
-        float y = part + sm.p[kOffB3];
-        if (residual) y = y + sm.x[s];
-        const float r = y - sm.t[s];
-        g.loss = fmaf(r, r, g.loss);
-        dy = 2.0f * r / static_cast<float>(batch);
-      }
-      sm.dy[s] = dy;
-    }
+  sm.z2t[c0 * kRowT + s] = a0;
+  sm.z2t[(c0 + 1) * kRowT + s] = a1;
+  // output: the sixteen lanes' parts combined by shuffles; every lane takes
+  // the first lane's sum, so all use one value
+  float part = fmaf(sm.p[kOffW3 + c0], relu(a0), 0.0f);
+  part = fmaf(sm.p[kOffW3 + c0 + 1], relu(a1), part);
+  for (int d = 8; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+  part = __shfl(part, lane & ~15, 64);
+  float dy = 0.0f;
+  if (s < static_cast<int>(cs)) {
+    float y = part + sm.p[kOffB3];
+    if (residual) y = y + xs;
+    const float r = y - sm.t[s];
+    if ((tid & 15) == 0) g.loss = fmaf(r, r, g.loss);
+    dy = 2.0f * r / static_cast<float>(batch);
   }
-  lds_barrier();
+  if ((tid & 15) == 0) sm.dy[s] = dy;
   // dL/dz2 = dL/dy * W3, masked by the second layer's ReLU
-  for (int e = tid; e < static_cast<int>(kTrainChunk) * kH; e += kTrainThreads) {
-    const int q = e >> 5, v = e & 31;
-    const float d = sm.z2[q * kRow + v] > 0.0f ? sm.dy[q] * sm.p[kOffW3 + v] : 0.0f;
-    sm.dz2[q * kRow + v] = d;
-    sm.dz2t[v * kRowT + q] = d;
-  }
-  lds_barrier();
+  const float d0 = a0 > 0.0f ? dy * sm.p[kOffW3 + c0] : 0.0f;
+  const float d1 = a1 > 0.0f ? dy * sm.p[kOffW3 + c0 + 1] : 0.0f;
+  sm.dz2[s * kRow + c0] = d0;
+  sm.dz2[s * kRow + c0 + 1] = d1;
+  sm.dz2t[c0 * kRowT + s] = d0;
+  sm.dz2t[(c0 + 1) * kRowT + s] = d1;
+  wave_sync();
   // dL/dz1 = W2^T dL/dz2, masked by the first layer's ReLU
   {
-    float a0 = 0.0f, a1 = 0.0f;
+    float e0 = 0.0f, e1 = 0.0f;
 #pragma unroll 8
     for (int v = 0; v < kH; ++v) {
       const float2 w = *reinterpret_cast<const float2*>(&sm.p[kOffW2 + v * kH + c0]);
       const float d = sm.dz2[s * kRow + v];
-      a0 = fmaf(w.x, d, a0);
-      a1 = fmaf(w.y, d, a1);
+      e0 = fmaf(w.x, d, e0);
+      e1 = fmaf(w.y, d, e1);
     }
-    sm.dz1t[c0 * kRowT + s] = sm.h1[s * kRow + c0] > 0.0f ? a0 : 0.0f;
-    sm.dz1t[(c0 + 1) * kRowT + s] = sm.h1[s * kRow + c0 + 1] > 0.0f ? a1 : 0.0f;
+    sm.dz1t[c0 * kRowT + s] = h0 > 0.0f ? e0 : 0.0f;
+    sm.dz1t[(c0 + 1) * kRowT + s] = h1 > 0.0f ? e1 : 0.0f;
   }
-  lds_barrier();
+  lds_barrier();  // every sample's columns are in place
   // parameter gradients of the chunk, sums over samples four at a time
   {
     const int v = tid >> 5, u = tid & 31;
