@@ -175,6 +175,16 @@ __global__ __launch_bounds__(kBinStride) void k_tile_rescan(BucketBufs b) {
   }
 }
 
+// Tile of workgroup b among g. Workgroups are handed to the 8 XCDs in turn
+// (b on XCD b % 8), each with its own L2; this gives every XCD one
+// contiguous range of tiles, so the short runs that neighbouring tiles write
+// into the same bin meet in one L2 and leave it as whole cache lines.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t g) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t x = b % kXcd, q = g / kXcd, r = g % kXcd;
+  return x * q + (x < r ? x : r) + b / kXcd;
+}
+
 template <class K, bool PAIRS>
 __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict__ kin,
                                                  const uint32_t* __restrict__ vin, typename K::T* __restrict__ kout,
@@ -189,13 +199,14 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
   __shared__ uint32_t s_val[PAIRS ? kBucketTile : 1];
   uint32_t u;
   load_splitters(s_sp, b, u);
-  const uint32_t* row = b.rows + static_cast<uint64_t>(blockIdx.x) * kBinStride;
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t* row = b.rows + static_cast<uint64_t>(tile) * kBinStride;
   for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) {
     s_loc[i] = 0;
     s_goff[i] = row[i];
   }
   __syncthreads();
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBucketTile;
+  const uint64_t base = static_cast<uint64_t>(tile) * kBucketTile;
   const uint32_t cnt = static_cast<uint32_t>(n - base < kBucketTile ? n - base : kBucketTile);
   T v[kPer];
   uint32_t pv[PAIRS ? kPer : 1];
