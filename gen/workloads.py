@@ -196,13 +196,23 @@ def lognormal_u64(n: int, mu: float = 20.0, sigma: float = 3.0, seed: int = 0) -
     return x.astype(np.uint64)
 
 
-def zipf_u64(n: int, s: float = 1.1, ranks: int = 1 << 24, seed: int = 0) -> np.ndarray:
-    """Zipf(s) over ranks 1..`ranks`, drawn by inverse CDF; key = rank."""
-    rng = np.random.default_rng(seed)
+def zipf_cdf(s: float = 1.1, ranks: int = 1 << 24) -> np.ndarray:
+    """Cumulative probabilities of Zipf(s) over ranks 1..`ranks` (float64)."""
     w = np.arange(1, ranks + 1, dtype=np.float64) ** (-s)
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
-    u = rng.random(n)
+    return cdf
+
+
+def zipf_uniforms(n: int, seed: int = 0) -> np.ndarray:
+    """The uniform draws behind zipf_u64 (same seed, same stream)."""
+    return np.random.default_rng(seed).random(n)
+
+
+def zipf_u64(n: int, s: float = 1.1, ranks: int = 1 << 24, seed: int = 0) -> np.ndarray:
+    """Zipf(s) over ranks 1..`ranks`, drawn by inverse CDF; key = rank."""
+    cdf = zipf_cdf(s, ranks)
+    u = zipf_uniforms(n, seed)
     r = np.searchsorted(cdf, u, side="right") + 1
     return np.minimum(r, ranks).astype(np.uint64)
 
