@@ -248,6 +248,57 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
   }
 }
 
+// Whether keys[0..n) are ordered, before anything else is spent on them:
+// bit 0 of *flags = some adjacent pair descends, bit 1 = some pair ascends.
+// Rows of 256 keys are read coalesced, each key with its successor. A
+// workgroup ORs its waves' bits in LDS and sends only news to the shared
+// word (same-address atomics are slow), and stops as soon as both bits are
+// known, so an unordered input costs a few chunks and an ordered one a
+// single read.
+template <class K>
+__global__ __launch_bounds__(256) void k_order_scan(const typename K::T* __restrict__ keys, uint64_t n,
+                                                    uint32_t* flags) {
+  constexpr uint32_t kRowsPer = 64;  // 16384 keys between two looks at the shared word
+  constexpr uint64_t kChunk = 256ull * kRowsPer;
+  __shared__ uint32_t s_flags, s_bits;
+  const uint64_t nchunks = (n + kChunk - 1) / kChunk;
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    if (threadIdx.x == 0) {
+      s_flags = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_bits = 0;
+    }
+    __syncthreads();
+    const uint32_t f = s_flags;
+    if (f == 3u) return;  // the same value for the whole workgroup
+    bool d = false, a = false;
+#pragma unroll 16
+    for (uint32_t r = 0; r < kRowsPer; ++r) {
+      const uint64_t i = ch * kChunk + static_cast<uint64_t>(r) * 256u + threadIdx.x;
+      if (i + 1 < n) {
+        const auto x = K::ord(keys[i]), y = K::ord(keys[i + 1]);
+        d |= y < x;
+        a |= y > x;
+      }
+    }
+    const uint32_t bits = (__any(d) ? 1u : 0u) | (__any(a) ? 2u : 0u);
+    if (lane_id() == 0 && bits) atomicOr(&s_bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0 && (s_bits & ~f)) atomicOr(flags, s_bits);
+  }
+}
+
+template <class K>
+struct OrderL {
+  static hipError_t run(const void* keys, uint64_t n, uint32_t* flags, hipStream_t s) {
+    const uint64_t nchunks = (n + 16383) / 16384;
+    const uint32_t grid = static_cast<uint32_t>(nchunks < 512 ? nchunks : 512);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order_scan<K>, dim3(grid), dim3(256), 0, s, static_cast<const typename K::T*>(keys), n,
+                       flags);
+    return hipGetLastError();
+  }
+};
+
 template <class K>
 struct HistL {
   static hipError_t run(const void* keys, uint64_t n, const BucketBufs& b, hipStream_t s) {
@@ -283,6 +334,17 @@ hipError_t launch_bucket_hist(uint32_t kt, const void* keys, uint64_t n, const B
     case 2: return HistL<KeyI32>::run(keys, n, b, s);
     case 3: return HistL<KeyF32>::run(keys, n, b, s);
     case 4: return HistL<KeyU64>::run(keys, n, b, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_order_scan(uint32_t kt, const void* keys, uint64_t n, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, flags);
+  switch (kt) {
+    case 1: return OrderL<KeyU32>::run(keys, n, flags, s);
+    case 2: return OrderL<KeyI32>::run(keys, n, flags, s);
+    case 3: return OrderL<KeyF32>::run(keys, n, flags, s);
+    case 4: return OrderL<KeyU64>::run(keys, n, flags, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -89,6 +89,8 @@ hipError_t launch_extract(const uint64_t* sorted, const float* y, uint64_t m, fl
                           uint32_t* count, hipStream_t s);
 
 // k_bucket.hip
+// bit 0 of *flags: some adjacent pair of keys[0..n) descends; bit 1: some pair ascends.
+hipError_t launch_order_scan(uint32_t kt, const void* keys, uint64_t n, uint32_t* flags, hipStream_t s);
 hipError_t launch_bucket_hist(uint32_t kt, const void* keys, uint64_t n, const BucketBufs& b, hipStream_t s);
 hipError_t launch_bucket_scan(const BucketBufs& b, hipStream_t s);
 hipError_t launch_bucket_scatter(uint32_t kt, bool pairs, const void* keys_in, const uint32_t* vals_in,

@@ -393,6 +393,19 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   b.errors = &c.ctr->errors;
   EventPair e_fit, e_hist, e_scat;
   if (prof && !(e_fit.make() && e_hist.make() && e_scat.make())) return PDQ_ERR_HIP;
+  {
+    // an input that is already non-decreasing or non-increasing is retired
+    // by the plain path's first pass: find out before the fit is paid for
+    uint32_t order_bits = 0;
+    HIP_TRY(launch_order_scan(kt, c.keys[0], n, b.order, s));
+    HIP_TRY(hipMemcpyAsync(&order_bits, b.order, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((order_bits & 1u) == 0 || (order_bits & 2u) == 0) {
+      res.ordered = 1;
+      res.state = 2;
+      return PDQ_OK;
+    }
+  }
   if (prof) HIP_TRY(hipEventRecord(e_fit.a, s));
   int rc = run_fit(c.keys[0], n, kt, o, f, s);
   if (rc != PDQ_OK) return rc;
