@@ -35,6 +35,7 @@ struct Slot<K, false, false> {
   static constexpr int kLdsBytes = 4;
   __device__ static V make(uint32_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return 0xFFFFFFFFu; }
+  __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
   __device__ static uint32_t key(V v) { return K::inv(v); }
@@ -50,6 +51,7 @@ struct Slot<K, true, false> {
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint32_t raw, uint32_t i) { return (static_cast<uint64_t>(K::ord(raw)) << 32) | i; }
   __device__ static V pad() { return ~0ull; }
+  __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
   __device__ static uint32_t key(V v) { return K::inv(static_cast<uint32_t>(v >> 32)); }
@@ -65,6 +67,7 @@ struct Slot<K, false, true> {
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint64_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return ~0ull; }
+  __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
   __device__ static uint64_t key(V v) { return K::inv(v); }
@@ -80,6 +83,8 @@ struct Slot<K, true, true> {
   static constexpr int kLdsBytes = 12;
   __device__ static V make(uint64_t raw, uint32_t i) { return KV{K::ord(raw), i}; }
   __device__ static V pad() { return KV{~0ull, 0xFFFFFFFFu}; }
+  // field by field: a select of whole structs goes through scratch memory
+  __device__ static V sel(bool c, V a, V b) { return KV{c ? a.k : b.k, c ? a.i : b.i}; }
   __device__ static bool lt(V a, V b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
   __device__ static V xch(V a, int m) { return KV{__shfl_xor(a.k, m, 64), static_cast<uint32_t>(__shfl_xor(a.i, m, 64))}; }
   __device__ static uint64_t key(V v) { return K::inv(v.k); }
@@ -128,8 +133,8 @@ __device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh
           const bool up = (((base | r) >> kb) & 1) == 0;
           const V a = x[r], c = x[r2];
           const bool sw = S::lt(c, a) == up;  // out of order for this block's direction
-          x[r] = sw ? c : a;
-          x[r2] = sw ? a : c;
+          x[r] = S::sel(sw, c, a);
+          x[r2] = S::sel(sw, a, c);
         }
       } else if (b < e + 6) {
         // partners in lane ^ m, same register
@@ -141,7 +146,7 @@ __device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh
           const V y = S::xch(x[r], m);
           const bool take_min = lower == up;
           const bool y_less = S::lt(y, x[r]);
-          x[r] = (y_less == take_min) ? y : x[r];
+          x[r] = S::sel(y_less == take_min, y, x[r]);
         }
       } else {
         // partners in another wave: exchange through LDS
@@ -155,7 +160,7 @@ __device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh
           const V y = S::ld(sh, PL, lds_pos<E>((base | r) ^ (1 << b)));
           const bool take_min = lower == up;
           const bool y_less = S::lt(y, x[r]);
-          x[r] = (y_less == take_min) ? y : x[r];
+          x[r] = S::sel(y_less == take_min, y, x[r]);
         }
         __syncthreads();
       }
@@ -188,8 +193,8 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
         const bool up = ((r >> kb) & 1) == 0;
         const V a = x[r], c = x[r2];
         const bool sw = S::lt(c, a) == up;
-        x[r] = sw ? c : a;
-        x[r2] = sw ? a : c;
+        x[r] = S::sel(sw, c, a);
+        x[r2] = S::sel(sw, a, c);
       }
     }
   }
@@ -209,20 +214,22 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
       else hi = mid;
     }
     int i = lo, j = o - lo;
-    V a = i < run ? S::ld(sh, PL, lds_pos<E>(pa + i)) : pad;
-    V c = j < run ? S::ld(sh, PL, lds_pos<E>(pb + j)) : pad;
+    V a = pad, c = pad;
+    if (i < run) a = S::ld(sh, PL, lds_pos<E>(pa + i));
+    if (j < run) c = S::ld(sh, PL, lds_pos<E>(pb + j));
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const bool take_left = !S::lt(c, a);
-      x[r] = take_left ? a : c;
+      x[r] = S::sel(take_left, a, c);
       if (take_left) ++i;
       else ++j;
       if (r + 1 < E) {
         const bool more = take_left ? i < run : j < run;
         const int at = take_left ? pa + i : pb + j;
-        const V nv = more ? S::ld(sh, PL, lds_pos<E>(at)) : pad;
-        a = take_left ? nv : a;
-        c = take_left ? c : nv;
+        V nv = pad;
+        if (more) nv = S::ld(sh, PL, lds_pos<E>(at));
+        a = S::sel(take_left, nv, a);
+        c = S::sel(take_left, c, nv);
       }
     }
     __syncthreads();

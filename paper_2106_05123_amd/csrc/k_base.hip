@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int j = r * NT + tid;
-      S::st(sh, PL, lds_pos<E>(j), j < len ? S::make(in[j], static_cast<uint32_t>(j)) : S::pad());
+      S::st(sh, PL, lds_pos<E>(j), S::sel(j < len, S::make(j < len ? in[j] : T(0), static_cast<uint32_t>(j)), S::pad()));
     }
     __syncthreads();
     V x[E];
@@ -126,18 +126,29 @@ hipError_t launch_shape(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
 
 template <class K, bool PAIRS>
 hipError_t launch_cls(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
+  // 64-bit keys with a payload hold three registers a slot: 8 slots per lane
+  // (twice the threads) keep them out of the register limit that 16 would hit
+  constexpr bool kWidePairs = sizeof(typename K::T) == 8 && PAIRS;
   switch (cls) {
     case 0: return launch_shape<K, PAIRS, 1, 64>(c, cls, nitems, s);
     case 1: return launch_shape<K, PAIRS, 4, 64>(c, cls, nitems, s);
-    case 2: return launch_shape<K, PAIRS, 16, 64>(c, cls, nitems, s);
-    case 3: return launch_shape<K, PAIRS, 16, 128>(c, cls, nitems, s);
-    case 4: return launch_shape<K, PAIRS, 16, 256>(c, cls, nitems, s);
+    case 2:
+      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 128>(c, cls, nitems, s);
+      else return launch_shape<K, PAIRS, 16, 64>(c, cls, nitems, s);
+    case 3:
+      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 256>(c, cls, nitems, s);
+      else return launch_shape<K, PAIRS, 16, 128>(c, cls, nitems, s);
+    case 4:
+      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 512>(c, cls, nitems, s);
+      else return launch_shape<K, PAIRS, 16, 256>(c, cls, nitems, s);
     case 5:
-      return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 256>(c, cls, nitems, s)
-                            : launch_shape<K, PAIRS, 16, 512>(c, cls, nitems, s);
+      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 1024>(c, cls, nitems, s);
+      else
+        return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 256>(c, cls, nitems, s)
+                              : launch_shape<K, PAIRS, 16, 512>(c, cls, nitems, s);
     case 6:
       // 64-bit keys with a payload need 12 LDS bytes a slot: their widest class is 8192
-      if constexpr (sizeof(typename K::T) == 8 && PAIRS) return hipErrorInvalidValue;
+      if constexpr (kWidePairs) return hipErrorInvalidValue;
       else
         return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 512>(c, cls, nitems, s)
                               : launch_shape<K, PAIRS, 16, 1024>(c, cls, nitems, s);

@@ -169,7 +169,9 @@ __device__ void lds_sort(const typename K::T* in, const uint32_t* vin, typename 
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int j = r * NTS + tid;
-    S::st(sh, PL, net::lds_pos<E>(j), j < len ? S::make(cload(in + j), static_cast<uint32_t>(j)) : S::pad());
+    V v = S::pad();
+    if (j < len) v = S::make(cload(in + j), static_cast<uint32_t>(j));
+    S::st(sh, PL, net::lds_pos<E>(j), v);
   }
   sync();
   V x[E];
