@@ -283,7 +283,7 @@ def main():
         "config": {"workload": f"pdq_sort with the learned first pass of 2^{args.log2n} uint32 keys, "
                                f"uniform random (seed 0), keys only",
                    "n": n, "key_type": "u32",
-                   "tile": args.tile or "per pass: 32768 while segments average >= 2^18 keys, else 8192"},
+                   "tile": args.tile or "per pass: 8192 once no segment holds over 1/10 of the keys, else 16384 (segments >= 2^18 keys)"},
         "forms": {"learned": learned, "plain": plain,
                   "learned_over_plain": round(plain["ms"] / learned["ms"], 3) if plain else None},
         "roofline": roofline,

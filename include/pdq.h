@@ -105,9 +105,10 @@ typedef struct pdq_options {
   uint32_t struct_size;  /* sizeof(pdq_options); 0 or a smaller value = older layout */
   uint32_t flags;        /* pdq_flags */
   int32_t force_budget;  /* < 0: floor(log2 size) per segment (Section 4.1); >= 0: that budget */
-  uint32_t tile;         /* keys per partition tile: 0 = chosen per pass from the average segment
-                            size (32768, or 8192 below 2^18 keys), else 1024 ... 65536, a power
-                            of two; PDQ_BATCHED uses its shape's tile unless this is set */
+  uint32_t tile;         /* keys per partition tile: 0 = chosen per pass (8192 once no segment
+                            holds more than a tenth of the pass's keys, else 16384 for segments
+                            of 2^18 keys or more), else 1024 ... 65536, a power of two;
+                            PDQ_BATCHED uses its shape's tile unless this is set */
   uint64_t seed;         /* seeds the hashed pivot candidates taken after a bad partition, and
                             the sample, initial weights and minibatches of PDQ_LEARNED */
   float learned_imbalance_limit; /* PDQ_LEARNED: fall back to the plain path when a range bin holds

@@ -36,13 +36,14 @@ struct BatchQ {
 constexpr uint32_t kErrQueue = 16u;  // a queue wait did not end (ring too small or a lost item)
 
 // Shapes of the persistent tail kernel: threads per workgroup and rows per
-// partition tile (a tile is NT * IT keys).
+// partition tile (a tile is NT * IT keys). The tail only finishes the few
+// segments the captured passes leave, so one shape serves.
 struct TailShape {
   uint32_t nt;
   uint32_t it;
 };
-constexpr int kTailShapes = 4;
-constexpr TailShape kTail[kTailShapes] = {{512, 8}, {512, 16}, {1024, 8}, {1024, 16}};
+constexpr int kTailShapes = 1;
+constexpr TailShape kTail[kTailShapes] = {{512, 8}};
 
 // Tunable shape of the batched form: the tile of the captured partition
 // passes, the slots per lane of the two widest LDS classes (16: 512 and 1024

@@ -511,9 +511,6 @@ template <class K, bool PAIRS>
 hipError_t run_shape(const Ctx& c, const BatchArgs& b, int shape, uint32_t grid, hipStream_t s) {
   switch (shape) {
     case 0: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 8>), dim3(grid), dim3(512), 0, s, c, b); break;
-    case 1: hipLaunchKernelGGL((k_batch<K, PAIRS, 512, 16>), dim3(grid), dim3(512), 0, s, c, b); break;
-    case 2: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 8>), dim3(grid), dim3(1024), 0, s, c, b); break;
-    case 3: hipLaunchKernelGGL((k_batch<K, PAIRS, 1024, 16>), dim3(grid), dim3(1024), 0, s, c, b); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -523,9 +520,6 @@ template <class K, bool PAIRS>
 const void* kernel_of(int shape) {
   switch (shape) {
     case 0: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 8>);
-    case 1: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 512, 16>);
-    case 2: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 8>);
-    case 3: return reinterpret_cast<const void*>(&k_batch<K, PAIRS, 1024, 16>);
     default: return nullptr;
   }
 }

@@ -42,6 +42,8 @@ __device__ __forceinline__ void push_seg(const Ctx& c, int parity, bool want, ui
   const uint32_t nt = want ? tiles_of(b, e, c.tile) : 0u;
   const uint64_t r = wave_reserve_packed(reinterpret_cast<unsigned long long*>(&c.ctr->list[parity]), want, nt);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->elems[parity]), want ? (e - b) : 0ull);
+  const uint64_t wmax = wave_max_u64(want ? (e - b) : 0ull);
+  if (lane_id() == 0 && wmax) atomicMax(reinterpret_cast<unsigned long long*>(&c.ctr->maxlen[parity]), wmax);
   if (want && ((r >> 32) >= c.max_active || static_cast<uint64_t>(static_cast<uint32_t>(r)) + nt > c.max_tiles)) {
     atomicOr(&c.ctr->errors, kErrCapacity);
   } else if (want) {
@@ -50,13 +52,11 @@ __device__ __forceinline__ void push_seg(const Ctx& c, int parity, bool want, ui
     s.end = e;
     s.pivot = 0;
     s.pidx = b;
-    s.left = 0;
     s.tile_base = static_cast<uint32_t>(r);
     s.ntiles = nt;
     s.budget = budget;
     s.flags = flags;
     s.mode = kModeRight;
-    s.order_bits = 0;
     c.segs[parity][r >> 32] = s;
   }
 }
@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
     c.ctr->visits += c.ctr->elems[parity];
     c.ctr->list[parity ^ 1] = 0;
     c.ctr->elems[parity ^ 1] = 0;
+    c.ctr->maxlen[parity ^ 1] = 0;
     if (!c.device_counts) {
       for (int k = 0; k < kBaseClasses; ++k) c.ctr->nbase[k] = 0;
       c.ctr->nheap = 0;
@@ -167,16 +168,19 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   }
 }
 
-// Ticket -> segment map for the partition kernel (and, for the look-back
-// partition, a cleared status word per ticket).
+// Ticket -> segment map for the partition kernel, a cleared cursor per
+// segment (and, for the look-back partition, a cleared status word per
+// ticket).
 __global__ __launch_bounds__(kCtlThreads) void k_tilemap(Ctx c, int parity, uint32_t ntiles) {
   const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (t0 == 0) c.ctr->ticket = 0;
+  if (t0 < kTicketQueues) c.tickets[t0 * kTicketStride] = 0;
   if (c.device_counts) ntiles = static_cast<uint32_t>(c.ctr->list[parity]);
   if (ntiles > c.max_tiles) ntiles = c.max_tiles;
   uint32_t nseg = static_cast<uint32_t>(c.ctr->list[parity] >> 32);
   if (nseg > c.max_active) nseg = c.max_active;
   const Seg* segs = c.segs[parity];
+  for (uint32_t t = t0; t < nseg; t += gridDim.x * blockDim.x) c.cur[t] = Cursor{};
   for (uint32_t t = t0; t < ntiles; t += gridDim.x * blockDim.x) {
     uint32_t lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -197,16 +201,20 @@ __device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t 
   const bool live = i < nseg;
   const uint32_t dst = src ^ 1u;
   Seg s = {};
-  if (live) s = c.segs[parity][i];
+  Cursor cu = {};
+  if (live) {
+    s = c.segs[parity][i];
+    cu = c.cur[i];
+  }
   const uint64_t size = s.end - s.begin;
-  const bool no_desc = live && !(s.order_bits & static_cast<uint32_t>(kStDesc >> 32));
-  const bool no_asc = live && !(s.order_bits & static_cast<uint32_t>(kStAsc >> 32));
+  const bool no_desc = live && !(cu.order_bits & static_cast<uint32_t>(kStDesc >> 32));
+  const bool no_asc = live && !(cu.order_bits & static_cast<uint32_t>(kStAsc >> 32));
   const bool asc_sorted = no_desc;           // non-decreasing in the source buffer
   const bool desc_sorted = !no_desc && no_asc; // non-increasing in the source buffer
   bool split = live && !asc_sorted && !desc_sorted;
   // the partition kernel's packed cursor: keys placed left (low half) and
   // right (high half) of the pivot
-  const uint64_t L = static_cast<uint32_t>(s.left);
+  const uint64_t L = static_cast<uint32_t>(cu.left);
   if (split && L >= size) {
     atomicOr(&c.ctr->errors, kErrSplit);
     split = false;

@@ -14,11 +14,12 @@
 //   * per-row wave ballots + mbcnt give each key its rank among the keys of
 //     its class, an LDS scan over (row, wave) counts gives tile offsets;
 //   * the tile reserves its places with one 64-bit atomic on the segment's
-//     packed cursor: left keys upward from the segment start, the others
-//     downward from its end. The order of the tiles' blocks inside each side
-//     is the order their reservations arrived in; the partition does not
-//     need any particular order inside a side (the paper's partition is not
-//     stable either), and no tile ever waits for another. The deterministic
+//     packed cursor (in an array of its own that only atomics touch): left
+//     keys upward from the segment start, the others downward from its end.
+//     The order of the tiles' blocks inside each side is the order their
+//     reservations arrived in; the partition does not need any particular
+//     order inside a side (the paper's partition is not stable either), and
+//     no tile ever waits for another. The deterministic
 //     form (LB) instead publishes each tile's count and runs a decoupled
 //     look-back over the segment's earlier tiles, so the blocks follow tile
 //     order in every run;
@@ -31,7 +32,14 @@
 //   * the tile also records whether its adjacent pairs ever descend or
 //     ascend (including the pair across its end) and ORs these bits into
 //     the segment, which thus learns whether it was already ordered
-//     (Section 5.2).
+//     (Section 5.2); in the reservation form a workgroup sends each bit
+//     once per segment;
+//   * tiles come from ticket counters (one per XCD in the reservation form,
+//     a single one in the look-back form); the reservation form maps
+//     tickets through a permutation of the pass's tiles that puts tiles
+//     running at the same time into different segments (atomics on one
+//     cache line run one after another), the look-back form takes them in
+//     order.
 #pragma once
 
 #include "pdq_internal.h"
@@ -62,6 +70,25 @@ __device__ __forceinline__ TileDesc<T> tile_desc(const Seg* segs, const uint32_t
   d.nts = sg->ntiles;
   d.chunk = (d.b / TILE + d.tis) * static_cast<uint64_t>(TILE);
   return d;
+}
+
+// Stride of a bijection of [0, n): tile number x is taken as tile
+// (x * stride) mod n. The stride lies near 0.618 n and is coprime to n, so
+// tiles that run at the same time lie far apart in the pass's tile order,
+// i.e. in different segments when a pass has many.
+__device__ __forceinline__ uint32_t spread_stride(uint32_t n) {
+  if (n <= 2) return 1u;
+  uint32_t s = static_cast<uint32_t>((static_cast<uint64_t>(n) * 0x9E3779B9ull) >> 32) | 1u;
+  for (; s < n; s += 2) {
+    uint32_t a = n, b = s;
+    while (b) {
+      const uint32_t r = a % b;
+      a = b;
+      b = r;
+    }
+    if (a == 1) return s;
+  }
+  return 1u;
 }
 
 // Buffer descriptor over a whole array (no range limit; gfx9 layout).
@@ -211,20 +238,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   const int lane = tid & 63;
   const int wv = tid >> 6;
 
-  // Tickets come from one counter in the order workgroups ask, so a tile
-  // only ever waits on tiles that running workgroups already hold. A
-  // workgroup asks for its next ticket only when it is about to finish the
-  // current tile: a ticket held long before its tile starts would make
-  // every later tile of the segment wait for it.
+  // Tickets come from counters in the order workgroups ask (tiles carry
+  // uneven work when segments are small, so a fixed share per workgroup
+  // would leave the pass waiting for the unluckiest one). The look-back
+  // form takes every tile from one counter, in order; the reservation form
+  // from its XCD's queue, which covers tickets [q_lo, q_hi). A workgroup
+  // asks for its next ticket only when it is about to finish the current
+  // tile: in the look-back form a ticket held long before its tile starts
+  // would make every later tile of the segment wait for it.
+  const uint32_t nq = LB ? 1u : (gridDim.x < kTicketQueues ? gridDim.x : kTicketQueues);
+  const uint32_t q = blockIdx.x % nq;
+  const uint32_t q_lo = static_cast<uint32_t>(static_cast<uint64_t>(ntiles) * q / nq);
+  const uint32_t q_hi = static_cast<uint32_t>(static_cast<uint64_t>(ntiles) * (q + 1) / nq);
+  uint32_t* const qctr = LB ? &c.ctr->ticket : c.tickets + q * kTicketStride;
   if (tid == 0) {
-    s_next = atomicAdd(&c.ctr->ticket, 1u);
+    s_next = q_lo + atomicAdd(qctr, 1u);
     s_bits = 0;
   }
   lds_barrier();
   uint32_t t = __builtin_amdgcn_readfirstlane(s_next);
-  if (t >= ntiles) return;
-  TileDesc<T> d = tile_desc<T, TILE>(segs, c.tilemap, t);
+  if (t >= q_hi) return;
+  // reservation form: ticket x is tile (x * stride) mod ntiles, which
+  // spreads the tiles of one segment over the pass, so the atomics on one
+  // cursor do not all come at once; the look-back form takes tiles in order
+  const uint32_t stride = LB ? 1u : spread_stride(ntiles);
+  auto tile_of = [&](uint32_t x) -> uint32_t {
+    return LB ? x : static_cast<uint32_t>((static_cast<uint64_t>(x) * stride) % ntiles);
+  };
+  TileDesc<T> d = tile_desc<T, TILE>(segs, c.tilemap, tile_of(t));
   lds_barrier();  // every wave has read s_next
+  // reservation form: the segment whose order bits this workgroup last
+  // ORed, and the bits it ORed there (wave 0, lane 0)
+  uint32_t or_seg = ~0u, or_bits = 0;
+  // the next ticket (thread 0): the reservation form asks for it as soon as
+  // the tile's keys are on their way, so the answer is back by the tile's
+  // end; the look-back form only at the scatter
+  uint32_t nticket = 0;
+  auto early_ticket = [&]() {
+    if constexpr (!LB)
+      if (tid == 0) nticket = q_lo + atomicAdd(qctr, 1u);
+  };
 
   for (;;) {
     const TileGeom g = tile_geom<T, TILE>(d);
@@ -270,6 +323,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 #pragma unroll
         for (int j = 0; j < NSUB; ++j)
           if (j >= j0 && j < j1) load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j * SUB), c.n, src, tid, kr[j]);
+        early_ticket();
 #pragma unroll
         for (int j = 0; j < NSUB; ++j)
           if (j >= j0 && j < j1) count_sub(j, kr[j], lmr[j], vmr[j]);
@@ -284,6 +338,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         // the next sub-tile is loaded while this one is classified
         T k[IT], kn[IT];
         load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+        early_ticket();
 #pragma unroll 1
         for (int j = j0; j < j1; ++j) {
           if (j + 1 < j1) load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>((j + 1) * SUB), c.n, src, tid, kn);
@@ -390,8 +445,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
           s_nl = nl;
           s_bits = 0;  // ready for the next tile (all reads of it are done)
           if (d.tis == d.nts - 1) {
-            segs[d.si].left = ex + nl;
-            segs[d.si].order_bits = static_cast<uint32_t>((exb | own64) >> 32);
+            c.cur[d.si].left = ex + nl;
+            c.cur[d.si].order_bits = static_cast<uint32_t>((exb | own64) >> 32);
           }
         }
       } else {
@@ -401,8 +456,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
           const bool piv_in = g.pl >= g.lo && g.pl < g.hi;
           const uint32_t nvalid = (g.hi - g.lo) - (piv_in ? 1u : 0u);
           const uint64_t add = static_cast<uint64_t>(nl) | (static_cast<uint64_t>(nvalid - nl) << 32);
-          const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&segs[d.si].left), add);
-          if (own_bits) atomicOr(&segs[d.si].order_bits, own_bits);
+          const uint64_t old = atomicAdd(reinterpret_cast<unsigned long long*>(&c.cur[d.si].left), add);
+          // a bit this workgroup already set in this segment is not sent again
+          if (or_seg != d.si) {
+            or_seg = d.si;
+            or_bits = 0;
+          }
+          const uint32_t fresh = own_bits & ~or_bits;
+          if (fresh) atomicOr(&c.cur[d.si].order_bits, fresh);
+          or_bits |= own_bits;
           s_lpre = old;
           s_nl = nl;
           s_bits = 0;  // ready for the next tile (all reads of it are done)
@@ -411,8 +473,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     }
     lds_barrier();  // B2: group prefixes, the tile's places
 
-    uint32_t nticket = 0;
-    if (tid == 0) nticket = atomicAdd(&c.ctr->ticket, 1u);  // returns while the tile is written out
+    if constexpr (LB)
+      if (tid == 0) nticket = q_lo + atomicAdd(qctr, 1u);  // returns while the tile is written out
 
     // ---- scatter pass: write from registers ---------------------------------
     {
@@ -499,8 +561,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     if (tid == 0) s_next = nticket;
     lds_barrier();  // B3: next ticket; LDS is rewritten by the next tile
     t = __builtin_amdgcn_readfirstlane(s_next);
-    if (t >= ntiles) break;
-    d = tile_desc<T, TILE>(segs, c.tilemap, t);
+    if (t >= q_hi) break;
+    d = tile_desc<T, TILE>(segs, c.tilemap, tile_of(t));
   }
 }
 

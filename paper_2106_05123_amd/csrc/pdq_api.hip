@@ -48,7 +48,19 @@ constexpr uint32_t kDefaultTile = 32768;
 // not fix one: large tiles while segments span many of them (fewer
 // reservations on each segment's cursor), 8192 once they hold a few hundred
 // thousand keys or less (less of each tile lies outside its segment).
-uint32_t auto_tile(uint64_t avg) { return avg >= (1ull << 18) ? 32768u : 8192u; }
+// The partition tile of a pass over `elems` keys whose largest segment
+// holds `maxlen`. Each tile makes one atomic on its segment's cursor, and
+// atomics on one cache line run one after another (~12-16 ns apiece), so a
+// segment that holds much of the pass takes larger tiles: 16384 tiles of
+// 16384 keys cost one segment of 2^28 keys ~0.25 ms of atomics against a
+// ~0.5 ms pass. Cursors of different segments work in parallel, so once no
+// segment holds more than 1/kSpread of the keys the 8192-key tile (more
+// workgroups per CU, faster per key) wins at any size.
+constexpr uint64_t kSpread = 10;
+uint32_t auto_tile(uint64_t elems, uint64_t maxlen) {
+  if (maxlen * kSpread <= elems) return 8192u;
+  return maxlen >= (1ull << 18) ? 16384u : 8192u;
+}
 constexpr uint32_t kMaxPasses = 20000;  // far above any reachable pass count; a guard against bugs
 
 constexpr uint64_t kLearnSample = PDQ_LEARN_SAMPLE;
@@ -58,7 +70,7 @@ constexpr uint32_t kMaxLearnSteps = 65536;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, tilemap = 0, status = 0;
+  size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, cur = 0, tickets = 0, tilemap = 0, status = 0;
   size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
@@ -162,6 +174,8 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
   L.scratch_vals = take(vals ? n * 4 : 0);
   L.segs0 = take(sizeof(Seg) * L.max_active);
   L.segs1 = take(sizeof(Seg) * L.max_active);
+  L.cur = take(sizeof(Cursor) * L.max_active);
+  L.tickets = take(4ull * kTicketQueues * kTicketStride);
   L.tilemap = take(4ull * L.max_tiles);
   L.status = take(8ull * L.max_tiles);
   for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
@@ -477,6 +491,8 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.segs[0] = reinterpret_cast<Seg*>(base + L.segs0);
   c.segs[1] = reinterpret_cast<Seg*>(base + L.segs1);
   c.tilemap = reinterpret_cast<uint32_t*>(base + L.tilemap);
+  c.cur = reinterpret_cast<Cursor*>(base + L.cur);
+  c.tickets = reinterpret_cast<uint32_t*>(base + L.tickets);
   c.status = reinterpret_cast<uint64_t*>(base + L.status);
   for (int k = 0; k < kBaseClasses; ++k) c.base[k] = reinterpret_cast<Item*>(base + L.base[k]);
   c.heap = reinterpret_cast<Item*>(base + L.heap);
@@ -681,7 +697,9 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
   // the tile of the first pass, from the average size of its segments
-  if (!o.tile) c.tile = auto_tile(learned ? n / 256 : n / (offsets ? nseg : 1));
+  // (the learned bins hold at most 2n/256 keys each, or the fit is judged
+  // failed; input segments are taken as equal until the first pass has run)
+  if (!o.tile) c.tile = auto_tile(n, learned ? n / 128 : n / (offsets ? nseg : 1));
   LearnedResult lres;
   uint32_t src = 0;
   if (learned) {
@@ -689,7 +707,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     rc = run_learned(c, o, L, base, prof, lres, s);
     if (rc != PDQ_OK) return rc;
     if (lres.state == 1) src = 1;
-    else if (!o.tile) c.tile = auto_tile(n);  // judged and fell back: one segment [0, n)
+    else if (!o.tile) c.tile = auto_tile(n, n);  // judged and fell back: one segment [0, n)
   }
   if (src == 0) HIP_TRY(launch_init(c, s));
   rc = read_counters(c, &snap, s);
@@ -730,7 +748,8 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
       }
       // the children filed now are tiled for the next pass: about two per
       // segment, sharing its keys
-      if (!o.tile) c.tile = auto_tile(snap.elems[parity] / (2ull * nact));
+      // the next pass's largest segment is taken as half this pass's largest
+      if (!o.tile) c.tile = auto_tile(snap.elems[parity], (snap.maxlen[parity] + 1) / 2);
       if ((e = launch_bookkeep(c, parity, nact, src, pass, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
     } while (0);
     if (r2 == PDQ_OK) r2 = read_counters(c, &snap, s);

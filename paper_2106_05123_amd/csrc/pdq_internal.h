@@ -16,8 +16,8 @@ constexpr uint32_t kSegFresh = 2u;      // parent partition was bad: use fresh c
 constexpr uint32_t kModeRight = 0u;
 constexpr uint32_t kModeLeft = 1u;
 
-// Order bits of a segment (positions in a 64-bit word; Seg::order_bits holds
-// them shifted down by 32):
+// Order bits of a segment (positions in a 64-bit word; Cursor::order_bits
+// holds them shifted down by 32):
 //   kStDesc  some adjacent pair descends
 //   kStAsc   some adjacent pair ascends
 // They also sit in the tile status words of the deterministic (look-back)
@@ -32,6 +32,14 @@ constexpr uint64_t kStDesc = 1ull << 61;
 constexpr uint64_t kStAsc = 1ull << 60;
 constexpr uint64_t kStCountMask = (1ull << 60) - 1;
 
+// The reservation partition hands out its tiles from kTicketQueues counters,
+// one per XCD (workgroup b uses queue b mod 8; workgroups are dispatched to
+// the 8 XCDs round-robin), each over its own share of the pass's tiles and
+// on its own cache line: atomics on one line run one after another, and a
+// single counter for all tiles of a pass took longer than the pass itself.
+constexpr uint32_t kTicketQueues = 8;
+constexpr uint32_t kTicketStride = 32;  // 128 bytes
+
 // One live segment of a partition pass. Positions are absolute indices into
 // the key arrays; the segment's keys sit in the pass's source buffer.
 struct Seg {
@@ -39,15 +47,23 @@ struct Seg {
   uint64_t end;
   uint64_t pivot;      // raw key bits of the pivot (pivot kernel)
   uint64_t pidx;       // absolute position of the pivot element in the source buffer
-  uint64_t left;       // partition cursor: keys placed left of the pivot (low 32 bits) and
-                       // right of it (high 32 bits), reserved tile by tile; with the
-                       // look-back, the left count written by the segment's last tile
   uint32_t tile_base;  // first tile ticket of the segment in this pass
   uint32_t ntiles;
   uint32_t budget;     // bad partitions still allowed (Section 4.1)
   uint32_t flags;      // kSegLeftmost | kSegFresh
   uint32_t mode;       // kModeRight / kModeLeft (pivot kernel)
+};
+
+// What the partition kernel accumulates for segment i of the pass, kept
+// apart from the Seg records: every tile reads its Seg, and atomics on a
+// cache line that workgroups also read run several times slower than on a
+// line that only atomics touch. Cleared by the tile-map kernel.
+struct Cursor {
+  uint64_t left;       // keys placed left of the pivot (low 32 bits) and right of it
+                       // (high 32 bits), reserved tile by tile; with the look-back, the
+                       // left count written by the segment's last tile
   uint32_t order_bits; // kStDesc | kStAsc >> 32 of the whole segment (ORed by its tiles)
+  uint32_t pad_;
 };
 
 // A range handed to a finishing kernel: base case, heapsort or a plain
@@ -63,6 +79,7 @@ struct Item {
 struct Counters {
   uint64_t list[2];        // per list parity: (segments << 32) | tiles
   uint64_t elems[2];       // per list parity: keys in the list
+  uint64_t maxlen[2];      // per list parity: keys of its largest segment
   uint32_t nbase[kBaseClasses];
   uint32_t nheap, ncopy, ticket, pad1_;
   // statistics (accumulated over the call)
@@ -91,6 +108,8 @@ struct Ctx {
   uint64_t n;
   Seg* segs[2];         // live-segment lists, indexed by pass parity
   uint32_t* tilemap;    // ticket -> segment index
+  Cursor* cur;          // segment index -> its partition cursor (the pass being run)
+  uint32_t* tickets;    // reservation partition: kTicketQueues counters, kTicketStride words apart
   uint64_t* status;     // ticket -> look-back status word (deterministic partition only)
   Item* base[kBaseClasses];
   Item* heap;
