@@ -56,11 +56,18 @@ struct TileDesc {
   bool left_mode;
 };
 
+// The segment records and the tile map do not change while a pass runs, so
+// they are read through the constant address space: scalar loads, whose
+// wait does not also wait for the vector stores of the previous tile.
+template <class X>
+using ConstPtr = const __attribute__((address_space(4))) X*;
+
 template <class T, int TILE>
 __device__ __forceinline__ TileDesc<T> tile_desc(const Seg* segs, const uint32_t* tilemap, uint32_t t) {
   TileDesc<T> d;
-  d.si = __builtin_amdgcn_readfirstlane(tilemap[t]);
-  const Seg* sg = segs + d.si;
+  const ConstPtr<uint32_t> tm = reinterpret_cast<ConstPtr<uint32_t>>(reinterpret_cast<uintptr_t>(tilemap));
+  d.si = __builtin_amdgcn_readfirstlane(tm[t]);
+  const ConstPtr<Seg> sg = reinterpret_cast<ConstPtr<Seg>>(reinterpret_cast<uintptr_t>(segs)) + d.si;
   d.b = sg->begin;
   d.e = sg->end;
   d.pidx = sg->pidx;
@@ -282,7 +289,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   for (;;) {
     const TileGeom g = tile_geom<T, TILE>(d);
     const auto pv = K::ord(d.piv);
-    if (tid == NT - 1) s_tail = (g.erel > static_cast<uint32_t>(TILE)) ? src[d.chunk + TILE] : T(0);
+    // the first key after the tile (last thread), read with the tile's keys
+    // and handed over in LDS before the first barrier
+    T tail_key = T(0);
+    auto load_tail = [&]() {
+      if (tid == NT - 1 && g.erel > static_cast<uint32_t>(TILE)) tail_key = src[d.chunk + TILE];
+    };
 
     // sub-tiles that hold keys of the segment: [j0, j1)
     const int j0 = static_cast<int>(g.lo / SUB);
@@ -323,6 +335,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 #pragma unroll
         for (int j = 0; j < NSUB; ++j)
           if (j >= j0 && j < j1) load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j * SUB), c.n, src, tid, kr[j]);
+        load_tail();
         early_ticket();
 #pragma unroll
         for (int j = 0; j < NSUB; ++j)
@@ -338,6 +351,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         // the next sub-tile is loaded while this one is classified
         T k[IT], kn[IT];
         load_sub<T, NT, IT>(d.chunk + static_cast<uint32_t>(j0 * SUB), c.n, src, tid, k);
+        load_tail();
         early_ticket();
 #pragma unroll 1
         for (int j = j0; j < j1; ++j) {
@@ -353,7 +367,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         atomicOr(&s_bits, (wd ? static_cast<uint32_t>(kStDesc >> 32) : 0u) |
                               (wa ? static_cast<uint32_t>(kStAsc >> 32) : 0u));
     }
-    lds_barrier();  // B1: group counts, group edge keys, in-group pair bits
+    if (tid == NT - 1) s_tail = tail_key;
+    lds_barrier();  // B1: group counts, group edge keys, in-group pair bits, tail key
 
     // ---- wave 0: edge pairs, scan, reservation ----------------------------------
     if (wv == 0) {
