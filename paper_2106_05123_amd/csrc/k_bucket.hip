@@ -7,9 +7,10 @@
 // i + 1; equality bins hold copies of one key and are final.
 //
 //   hist      per tile of 8192 keys: branchless binary search over the
-//             splitters in LDS, LDS bin counters, one row of 512 counts; and
-//             whether any adjacent pair ascends or descends (an ordered
-//             input is left to the plain path, which retires it in one pass)
+//             splitters in LDS, LDS bin counters, one row of 512 counts
+//             (whether the input is ordered was settled by the order scan
+//             before the fit: an ordered input is left to the plain path,
+//             which retires it in one pass)
 //   scan      chunk sums of 64 rows, one workgroup scanning the chunk sums
 //             (bin totals, bin starts), then each chunk rescans its rows into
 //             absolute per-tile offsets
@@ -85,12 +86,7 @@ __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ 
   using S = typename K::T;
   __shared__ SplitTable<S> s_sp;
   __shared__ uint32_t s_cnt[kBinStride];
-  __shared__ uint32_t s_order;
-  uint32_t u;
-  load_splitters(s_sp, b, u);
-  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) s_cnt[i] = 0;
-  if (threadIdx.x == 0) s_order = 0;
-  __syncthreads();
+  // the tile's keys are on their way while the splitter table is set up
   const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBucketTile;
   typename K::T v[kPer];
 #pragma unroll
@@ -98,26 +94,16 @@ __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ 
     const uint64_t i = base + k * kNT + threadIdx.x;
     v[k] = i < n ? keys[i] : typename K::T(0);
   }
-  // order of adjacent pairs (i, i+1): the neighbour is the next lane's key,
-  // or for the last lane a load of its own
-  bool desc = false, asc = false;
+  uint32_t u;
+  load_splitters(s_sp, b, u);
+  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) s_cnt[i] = 0;
+  lds_barrier();
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint64_t i = base + k * kNT + threadIdx.x;
-    const S o = K::ord(v[k]);
-    if (i < n) atomicAdd(&s_cnt[bin_of(s_sp, u, o)], 1u);
-    typename K::T nx = __shfl_down(v[k], 1, 64);
-    if (lane_id() == 63 && i + 1 < n) nx = keys[i + 1];
-    if (i + 1 < n) {
-      const S on = K::ord(nx);
-      desc |= on < o;
-      asc |= on > o;
-    }
+    if (i < n) atomicAdd(&s_cnt[bin_of(s_sp, u, K::ord(v[k]))], 1u);
   }
-  const uint32_t bits = (__ballot(desc) ? 1u : 0u) | (__ballot(asc) ? 2u : 0u);
-  if (bits && lane_id() == 0) atomicOr(&s_order, bits);
   __syncthreads();
-  if (threadIdx.x == 0 && s_order) atomicOr(b.order, s_order);
   uint32_t* row = b.rows + static_cast<uint64_t>(blockIdx.x) * kBinStride;
   for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) row[i] = s_cnt[i];
 }
@@ -197,17 +183,10 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
   __shared__ T s_key[kBucketTile];
   __shared__ uint16_t s_bin[kBucketTile];
   __shared__ uint32_t s_val[PAIRS ? kBucketTile : 1];
-  uint32_t u;
-  load_splitters(s_sp, b, u);
   const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t* row = b.rows + static_cast<uint64_t>(tile) * kBinStride;
-  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) {
-    s_loc[i] = 0;
-    s_goff[i] = row[i];
-  }
-  __syncthreads();
   const uint64_t base = static_cast<uint64_t>(tile) * kBucketTile;
   const uint32_t cnt = static_cast<uint32_t>(n - base < kBucketTile ? n - base : kBucketTile);
+  // the tile's keys are on their way while the tables are set up
   T v[kPer];
   uint32_t pv[PAIRS ? kPer : 1];
   uint32_t bin[kPer], rank[kPer];
@@ -217,6 +196,14 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
     v[k] = i < cnt ? kin[base + i] : T(0);
     if constexpr (PAIRS) pv[k] = i < cnt ? vin[base + i] : 0u;
   }
+  uint32_t u;
+  load_splitters(s_sp, b, u);
+  const uint32_t* row = b.rows + static_cast<uint64_t>(tile) * kBinStride;
+  for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) {
+    s_loc[i] = 0;
+    s_goff[i] = row[i];
+  }
+  lds_barrier();
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint32_t i = k * kNT + threadIdx.x;
@@ -328,7 +315,6 @@ struct ScatterL {
 __global__ void k_zero_word(uint32_t* p) { *p = 0; }
 
 hipError_t launch_bucket_hist(uint32_t kt, const void* keys, uint64_t n, const BucketBufs& b, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_word, dim3(1), dim3(1), 0, s, b.order);
   switch (kt) {
     case 1: return HistL<KeyU32>::run(keys, n, b, s);
     case 2: return HistL<KeyI32>::run(keys, n, b, s);

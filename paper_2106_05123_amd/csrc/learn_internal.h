@@ -69,7 +69,7 @@ struct BucketBufs {
   uint64_t ntiles;
   uint64_t nchunks;
   uint32_t* errors;        // scatter: bit kErrScatter when a position falls outside [0, n)
-  uint32_t* order;         // histogram: bit 0 some adjacent pair descends, bit 1 some pair ascends
+  uint32_t* order;         // order scan: bit 0 some adjacent pair descends, bit 1 some pair ascends
 };
 
 constexpr uint32_t kErrScatter = 8u;

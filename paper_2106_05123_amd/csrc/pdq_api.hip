@@ -432,7 +432,7 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   if (prof) HIP_TRY(hipEventRecord(e_hist.b, s));
   // judge on the host: bin totals, splitter count, trainer flag, last loss
   uint64_t totals[kBinStride];
-  uint32_t count = 0, sync[2] = {0, 0}, order_bits = 0;
+  uint32_t count = 0, sync[2] = {0, 0};
   uint64_t info[4] = {0, 0, 0, 0};
   float loss = 0.0f;
   HIP_TRY(hipMemcpyAsync(totals, b.totals, sizeof(totals), hipMemcpyDeviceToHost, s));
@@ -440,7 +440,6 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   HIP_TRY(hipMemcpyAsync(sync, f.sync, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&loss, f.losses + (o.steps - 1), 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&order_bits, b.order, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   res.splitters = count;
   res.use_log = static_cast<uint32_t>(info[2]);
@@ -452,11 +451,9 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   }
   res.max_range = max_range;
   res.equal = equal;
-  // an input that is already non-decreasing or non-increasing is retired by
-  // the plain path's first pass; the learned bins would lose that order
-  const bool ordered = (order_bits & 1u) == 0 || (order_bits & 2u) == 0;
-  res.ordered = ordered ? 1u : 0u;
-  const bool ok = !ordered && sync[1] == 0 && isfinite(loss) && o.limit >= 0.0f &&
+  // (an ordered input never gets here: the order scan sent it to the plain
+  // path, whose first pass retires it)
+  const bool ok = sync[1] == 0 && isfinite(loss) && o.limit >= 0.0f &&
                   static_cast<double>(max_range) <= static_cast<double>(o.limit) * static_cast<double>(n) / 256.0;
   if (prof) {
     res.fit_ms = e_fit.ms();
