@@ -409,19 +409,31 @@ __global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
   float b1t = 1.0f, b2t = 1.0f;  // beta1^step, beta2^step
   __syncthreads();
 
+  // this thread's sample of a chunk: the minibatch positions depend only on
+  // the seed and the step, so with one chunk per step the next step's
+  // sample is fetched while the gradients are exchanged
+  auto fetch = [&](uint32_t st, uint32_t c0, uint32_t cs, float& xv, float& tv) {
+    xv = 0.0f;
+    tv = 0.0f;
+    if (tid < static_cast<int>(cs)) {
+      const uint64_t gi = static_cast<uint64_t>(st) * a.batch + static_cast<uint64_t>(wg) * local + c0 + tid;
+      const uint64_t pos = mix64(a.seed ^ (kSaltBatch + gi)) % a.m;
+      xv = a.x[pos];
+      tv = a.t[pos];
+    }
+  };
+  const bool one_chunk = local <= kTrainChunk;
+  float nx = 0.0f, nt = 0.0f;
+  if (one_chunk && tid < static_cast<int>(kTrainChunk)) fetch(1, 0, local, nx, nt);
+
   bool failed = false;
   for (uint32_t step = 1; step <= a.steps; ++step) {
     GradAcc g = {0.0f, 0.0f, 0.0f, 0.0f};
     for (uint32_t c0 = 0; c0 < local; c0 += kTrainChunk) {
       const uint32_t cs = local - c0 < kTrainChunk ? local - c0 : kTrainChunk;
       if (tid < static_cast<int>(kTrainChunk)) {
-        float xv = 0.0f, tv = 0.0f;
-        if (tid < static_cast<int>(cs)) {
-          const uint64_t gi = static_cast<uint64_t>(step) * a.batch + static_cast<uint64_t>(wg) * local + c0 + tid;
-          const uint64_t pos = mix64(a.seed ^ (kSaltBatch + gi)) % a.m;
-          xv = a.x[pos];
-          tv = a.t[pos];
-        }
+        float xv = nx, tv = nt;
+        if (!one_chunk) fetch(step, c0, cs, xv, tv);
         sm.x[tid] = xv;
         sm.t[tid] = tv;
       }
@@ -437,6 +449,7 @@ __global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
     float* rows = a.partials + static_cast<size_t>(step & 1u) * a.grid * kParamStride;
     write_grad_row(sm, rows + static_cast<size_t>(wg) * kParamStride, g, true);
     __syncthreads();
+    if (one_chunk && step < a.steps && tid < static_cast<int>(kTrainChunk)) fetch(step + 1, 0, local, nx, nt);
     if (tid == 0 && !failed) {
       __hip_atomic_fetch_add(&a.sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t target = a.grid * step;
