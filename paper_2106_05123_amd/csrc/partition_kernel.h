@@ -75,7 +75,7 @@ __device__ __forceinline__ TileDesc<T> tile_desc(const Seg* segs, const uint32_t
   d.left_mode = sg->mode == kModeLeft;
   d.tis = t - sg->tile_base;
   d.nts = sg->ntiles;
-  d.chunk = (d.b / TILE + d.tis) * static_cast<uint64_t>(TILE);
+  d.chunk = d.b + static_cast<uint64_t>(d.tis) * TILE;  // tiles start at the segment's first key
   return d;
 }
 

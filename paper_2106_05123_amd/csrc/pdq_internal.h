@@ -193,10 +193,10 @@ __host__ __device__ inline int base_class(uint64_t n) {
   return n <= 64 ? 0 : n <= 256 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 3 : n <= 4096 ? 4 : n <= 8192 ? 5 : 6;
 }
 
-// Number of tile tickets a segment [b, e) takes: tiles are aligned to
-// multiples of `tile` in absolute index space.
+// Number of tile tickets a segment [b, e) takes: its tiles start at b, so
+// only the last one is partial.
 __host__ __device__ inline uint32_t tiles_of(uint64_t b, uint64_t e, uint32_t tile) {
-  return static_cast<uint32_t>((e - 1) / tile - b / tile + 1);
+  return static_cast<uint32_t>((e - b + tile - 1) / tile);
 }
 
 }  // namespace pdq
