@@ -166,6 +166,28 @@ def test_segmented_empty_and_tiny_segments():
     assert np.array_equal(t.cpu().numpy(), oracle.segmented_sort(a, off)[0])
 
 
+@pytest.mark.parametrize("tile", [1024, 8192])
+def test_segmented_tiles_straddling_segments(tile):
+    # segments just below, at and just above multiples of the tile, in a
+    # shuffled order: every segment's tiles start at its first key and only
+    # its last tile is partial; the pass hands tiles out over a permutation
+    # that interleaves segments and over one ticket queue per XCD
+    rng = np.random.default_rng(tile)
+    base = np.array([1, 2, tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile + 1, 5 * tile + 7, 40 * tile + 3])
+    sizes = rng.permutation(np.repeat(base, 37)).astype(np.int64)
+    off = W.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    a = W.uniform_u32(n, seed=tile + 1)
+    vals = np.arange(n, dtype=np.uint32)
+    t, o, v = to_dev(a), to_dev(off), to_dev(vals)
+    pdq.segmented_sort_(t, o, v, tile=tile, validate=True)
+    out, vo = t.cpu().numpy(), v.cpu().numpy()
+    assert np.array_equal(out, oracle.segmented_sort(a, off)[0])
+    check_pairs(a, out, vo)
+    seg_of = np.searchsorted(off, np.arange(n, dtype=np.uint64), side="right") - 1
+    assert np.array_equal(seg_of[vo], seg_of)
+
+
 def test_segmented_validate_rejects_bad_offsets():
     a = W.uniform_u32(1000, seed=1)
     bad = np.array([0, 600, 400, 1000], dtype=np.uint64)  # not monotone
