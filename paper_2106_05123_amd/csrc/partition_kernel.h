@@ -248,11 +248,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   // Tickets come from counters in the order workgroups ask (tiles carry
   // uneven work when segments are small, so a fixed share per workgroup
   // would leave the pass waiting for the unluckiest one). The look-back
-  // form takes every tile from one counter, in order; the reservation form
-  // from its XCD's queue, which covers tickets [q_lo, q_hi). A workgroup
-  // asks for its next ticket only when it is about to finish the current
-  // tile: in the look-back form a ticket held long before its tile starts
-  // would make every later tile of the segment wait for it.
+  // form takes every tile from one counter, in order, and asks for its next
+  // ticket only when it is about to finish the current tile: a ticket held
+  // long before its tile starts would make every later tile of the segment
+  // wait for it. The reservation form takes tickets [q_lo, q_hi) from its
+  // XCD's queue and asks for the next one as soon as a tile's keys load.
   const uint32_t nq = LB ? 1u : (gridDim.x < kTicketQueues ? gridDim.x : kTicketQueues);
   const uint32_t q = blockIdx.x % nq;
   const uint32_t q_lo = static_cast<uint32_t>(static_cast<uint64_t>(ntiles) * q / nq);
