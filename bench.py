@@ -135,6 +135,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--pattern-steps", type=int, default=3)
     ap.add_argument("--no-patterns", action="store_true")
+    ap.add_argument("--paper-log2n", type=int, default=26,
+                    help="size of the uint64 inputs in the paper's remaining distributions (0 = skip)")
     ap.add_argument("--cpu-log2n", type=int, default=26)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
@@ -248,6 +250,24 @@ def main():
             patterns[p] = row
             del pp, wi
 
+    # the paper's remaining distributions (Section 6.1), uint64 keys like the
+    # paper's 64-bit int, in both forms
+    paper = {}
+    if not args.no_patterns and args.paper_log2n > 0:
+        m = 1 << args.paper_log2n
+        for p in W.PAPER_PATTERNS:
+            log(f"paper distribution {p}")
+            hp = W.paper_pattern_u64(p, m, seed=0)
+            pp = torch.from_numpy(hp).to(dev)
+            wu = torch.empty_like(pp)
+            row = {}
+            for name, kw in forms.items():
+                pms, pst = time_sorts(pdq, torch, pp, wu, None, args.pattern_steps, profile=True, **kw)
+                row[name] = {"keys/s": round(m / (np.mean(pms) * 1e-3), 0), "ms": round(float(np.mean(pms)), 3),
+                             "passes": pst[0]["passes"], "learned_state": pst[0]["learned"]}
+            paper[p] = row
+            del pp, wu
+
     segmented = None
     if not args.no_segmented:
         segmented = bench_segmented(pdq, torch, W, dev, args)
@@ -289,6 +309,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "patterns_i32": patterns,
+        "paper_distributions_u64": {"n": 1 << args.paper_log2n, "rows": paper} if paper else None,
         "segmented_f32_pairs": segmented,
     }
     print(json.dumps(line), flush=True)

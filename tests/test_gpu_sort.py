@@ -94,6 +94,19 @@ def test_tile_sizes_same_keys(tile, pattern):
     assert np.array_equal(out, oracle.sort(a)[0])
 
 
+@pytest.mark.parametrize("learned", [False, True])
+@pytest.mark.parametrize("pattern", W.PAPER_PATTERNS)
+def test_paper_distributions_u64(pattern, learned):
+    # the paper's remaining distributions (Section 6.1) on 64-bit keys, a
+    # ragged size above the learned pass's sample: bit-exact in both forms
+    n = (1 << 20) + 4099
+    a = W.paper_pattern_u64(pattern, n, seed=7)
+    out, _, st = gpu_sort(a, learned=learned)
+    assert np.array_equal(out, oracle.sort(a)[0])
+    if pattern == "ones":
+        assert st["passes"] <= 1  # one pass retires the constant input
+
+
 def test_float_edge_bit_patterns():
     bits = np.array([0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x807FFFFF, 0x80000001, 0x80000000,
                      0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x3F800000, 0x7F7FFFFF, 0x7F800000],
