@@ -230,7 +230,8 @@ def gmm_u64(n: int, comps: int = 8, grid_log2: int = 40, seed: int = 0) -> np.nd
 
 
 def key_dtype(key_type: str):
-    return {"u32": np.uint32, "i32": np.int32, "f32": np.float32, "u64": np.uint64}[key_type]
+    return {"u32": np.uint32, "i32": np.int32, "f32": np.float32, "u64": np.uint64, "i64": np.int64,
+            "f64": np.float64}[key_type]
 
 
 def random_keys(key_type: str, n: int, seed: int = 0) -> np.ndarray:
@@ -248,5 +249,13 @@ def random_keys(key_type: str, n: int, seed: int = 0) -> np.ndarray:
         if n >= 8:
             idx = rng.choice(n, size=8, replace=False)
             a[idx] = np.array([0.0, -0.0, np.inf, -np.inf, 0.0, -0.0, 1e-45, -1e-45], dtype=np.float32)
+        return a
+    if key_type == "i64":
+        return rng.integers(-(2**63), 2**63, n, dtype=np.int64, endpoint=False)
+    if key_type == "f64":
+        a = rng.standard_normal(n)
+        if n >= 8:
+            idx = rng.choice(n, size=8, replace=False)
+            a[idx] = np.array([0.0, -0.0, np.inf, -np.inf, 0.0, -0.0, 5e-324, -5e-324])
         return a
     raise ValueError(key_type)

@@ -66,7 +66,9 @@ typedef enum pdq_key_type {
   PDQ_U32 = 1,
   PDQ_I32 = 2,
   PDQ_F32 = 3,
-  PDQ_U64 = 4
+  PDQ_U64 = 4,
+  PDQ_I64 = 5, /* signed 64-bit integers */
+  PDQ_F64 = 6  /* IEEE doubles: -0.0 before +0.0, NaN outside the contract (as for PDQ_F32) */
 } pdq_key_type;
 
 /* The comparison order is supplied by the caller but fixed to ascending

@@ -17,8 +17,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pdq_oracle.cpp")
 _LIB = os.path.join(_HERE, "libpdq_oracle.so")
 
-KEY_TYPES = {"u32": 1, "i32": 2, "f32": 3, "u64": 4}
-_DTYPES = {"u32": np.uint32, "i32": np.int32, "f32": np.float32, "u64": np.uint64}
+KEY_TYPES = {"u32": 1, "i32": 2, "f32": 3, "u64": 4, "i64": 5, "f64": 6}
+_DTYPES = {"u32": np.uint32, "i32": np.int32, "f32": np.float32, "u64": np.uint64, "i64": np.int64,
+           "f64": np.float64}
 
 
 class Counters(ctypes.Structure):

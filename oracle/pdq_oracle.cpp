@@ -45,6 +45,13 @@ constexpr int kBlockSize = 64;               // static block of 64 elements (Sec
 inline uint64_t canon(uint32_t x) { return x; }
 inline uint64_t canon(uint64_t x) { return x; }
 inline uint64_t canon(int32_t x) { return static_cast<uint32_t>(x) ^ 0x80000000u; }
+inline uint64_t canon(int64_t x) { return static_cast<uint64_t>(x) ^ 0x8000000000000000ull; }
+inline uint64_t canon(double f) {
+  uint64_t b;
+  std::memcpy(&b, &f, 8);
+  // the same rule as for float, on 64 bits
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
 inline uint64_t canon(float f) {
   uint32_t b;
   std::memcpy(&b, &f, 4);
@@ -576,6 +583,8 @@ int oracle_sort(int key_type, void* keys, uint32_t* vals, uint64_t n, const orac
     case 2: return sort_typed<int32_t>(keys, vals, n, nullptr, 0, opt, c);
     case 3: return sort_typed<float>(keys, vals, n, nullptr, 0, opt, c);
     case 4: return sort_typed<uint64_t>(keys, vals, n, nullptr, 0, opt, c);
+    case 5: return sort_typed<int64_t>(keys, vals, n, nullptr, 0, opt, c);
+    case 6: return sort_typed<double>(keys, vals, n, nullptr, 0, opt, c);
     default: return -2;
   }
 }
@@ -590,6 +599,8 @@ int oracle_segmented_sort(int key_type, void* keys, uint32_t* vals, uint64_t n,
     case 2: return sort_typed<int32_t>(keys, vals, n, offsets, nseg, opt, c);
     case 3: return sort_typed<float>(keys, vals, n, offsets, nseg, opt, c);
     case 4: return sort_typed<uint64_t>(keys, vals, n, offsets, nseg, opt, c);
+    case 5: return sort_typed<int64_t>(keys, vals, n, offsets, nseg, opt, c);
+    case 6: return sort_typed<double>(keys, vals, n, offsets, nseg, opt, c);
     default: return -2;
   }
 }
@@ -605,6 +616,8 @@ int oracle_routine(int key_type, int which, void* keys, uint64_t n, int arg, ora
     case 2: return routine_typed<int32_t>(which, keys, n, arg, c, out);
     case 3: return routine_typed<float>(which, keys, n, arg, c, out);
     case 4: return routine_typed<uint64_t>(which, keys, n, arg, c, out);
+    case 5: return routine_typed<int64_t>(which, keys, n, arg, c, out);
+    case 6: return routine_typed<double>(which, keys, n, arg, c, out);
     default: return -2;
   }
 }
@@ -616,6 +629,8 @@ uint64_t oracle_key_image(int key_type, const void* key) {
     case 2: return canon(*static_cast<const int32_t*>(key));
     case 3: return canon(*static_cast<const float*>(key));
     case 4: return canon(*static_cast<const uint64_t*>(key));
+    case 5: return canon(*static_cast<const int64_t*>(key));
+    case 6: return canon(*static_cast<const double*>(key));
     default: return 0;
   }
 }

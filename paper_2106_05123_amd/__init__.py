@@ -45,7 +45,7 @@ BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
 MAX_SPLITTERS = 255
 LEARN_SAMPLE = 65536
-KEY_TYPES = {"u32": 1, "i32": 2, "f32": 3, "u64": 4}
+KEY_TYPES = {"u32": 1, "i32": 2, "f32": 3, "u64": 4, "i64": 5, "f64": 6}
 
 
 class Options(ctypes.Structure):
@@ -191,9 +191,9 @@ def _check(status: int):
 
 def _key_type(t) -> int:
     import torch
-    m = {torch.uint32: 1, torch.int32: 2, torch.float32: 3, torch.uint64: 4}
+    m = {torch.uint32: 1, torch.int32: 2, torch.float32: 3, torch.uint64: 4, torch.int64: 5, torch.float64: 6}
     if t.dtype not in m:
-        raise TypeError(f"unsupported key dtype {t.dtype}; use uint32, int32, float32 or uint64")
+        raise TypeError(f"unsupported key dtype {t.dtype}; use uint32, int32, float32, uint64, int64 or float64")
     return m[t.dtype]
 
 

@@ -169,6 +169,8 @@ hipError_t launch_base(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
     case 2: return launch_kp<KeyI32>(c, cls, nitems, s);
     case 3: return launch_kp<KeyF32>(c, cls, nitems, s);
     case 4: return launch_kp<KeyU64>(c, cls, nitems, s);
+    case 5: return launch_kp<KeyI64>(c, cls, nitems, s);
+    case 6: return launch_kp<KeyF64>(c, cls, nitems, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -536,6 +536,8 @@ const void* kernel_for(const Ctx& c, int shape) {
     case 2: return v ? kernel_of<KeyI32, true>(shape) : kernel_of<KeyI32, false>(shape);
     case 3: return v ? kernel_of<KeyF32, true>(shape) : kernel_of<KeyF32, false>(shape);
     case 4: return v ? kernel_of<KeyU64, true>(shape) : kernel_of<KeyU64, false>(shape);
+    case 5: return v ? kernel_of<KeyI64, true>(shape) : kernel_of<KeyI64, false>(shape);
+    case 6: return v ? kernel_of<KeyF64, true>(shape) : kernel_of<KeyF64, false>(shape);
     default: return nullptr;
   }
 }
@@ -568,6 +570,8 @@ hipError_t launch_batch(const Ctx& c, const BatchArgs& b, int shape, uint32_t gr
     case 2: return run_kp<KeyI32>(c, b, shape, grid, s);
     case 3: return run_kp<KeyF32>(c, b, shape, grid, s);
     case 4: return run_kp<KeyU64>(c, b, shape, grid, s);
+    case 5: return run_kp<KeyI64>(c, b, shape, grid, s);
+    case 6: return run_kp<KeyF64>(c, b, shape, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -320,6 +320,8 @@ hipError_t launch_bucket_hist(uint32_t kt, const void* keys, uint64_t n, const B
     case 2: return HistL<KeyI32>::run(keys, n, b, s);
     case 3: return HistL<KeyF32>::run(keys, n, b, s);
     case 4: return HistL<KeyU64>::run(keys, n, b, s);
+    case 5: return HistL<KeyI64>::run(keys, n, b, s);
+    case 6: return HistL<KeyF64>::run(keys, n, b, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -331,6 +333,8 @@ hipError_t launch_order_scan(uint32_t kt, const void* keys, uint64_t n, uint32_t
     case 2: return OrderL<KeyI32>::run(keys, n, flags, s);
     case 3: return OrderL<KeyF32>::run(keys, n, flags, s);
     case 4: return OrderL<KeyU64>::run(keys, n, flags, s);
+    case 5: return OrderL<KeyI64>::run(keys, n, flags, s);
+    case 6: return OrderL<KeyF64>::run(keys, n, flags, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -350,6 +354,8 @@ hipError_t launch_bucket_scatter(uint32_t kt, bool pairs, const void* keys_in, c
     case 2: return ScatterL<KeyI32>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
     case 3: return ScatterL<KeyF32>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
     case 4: return ScatterL<KeyU64>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    case 5: return ScatterL<KeyI64>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
+    case 6: return ScatterL<KeyF64>::run(pairs, keys_in, vals_in, keys_out, vals_out, n, b, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -667,6 +667,8 @@ hipError_t launch_sample(uint32_t kt, const void* keys, uint64_t n, uint64_t m, 
     case 2: return SampleL<KeyI32>::run(keys, n, m, seed, out, s);
     case 3: return SampleL<KeyF32>::run(keys, n, m, seed, out, s);
     case 4: return SampleL<KeyU64>::run(keys, n, m, seed, out, s);
+    case 5: return SampleL<KeyI64>::run(keys, n, m, seed, out, s);
+    case 6: return SampleL<KeyF64>::run(keys, n, m, seed, out, s);
     default: return hipErrorInvalidValue;
   }
 }

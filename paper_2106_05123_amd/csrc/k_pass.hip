@@ -361,6 +361,8 @@ hipError_t dispatch_key(uint32_t kt, Args&&... args) {
     case 2: return F<KeyI32>::run(args...);
     case 3: return F<KeyF32>::run(args...);
     case 4: return F<KeyU64>::run(args...);
+    case 5: return F<KeyI64>::run(args...);
+    case 6: return F<KeyF64>::run(args...);
     default: return hipErrorInvalidValue;
   }
 }

@@ -644,6 +644,8 @@ hipError_t launch_mode(const Ctx& c, int parity, uint32_t ntiles, uint32_t src_b
     case 2: return launch_key<KeyI32, LB>(c, parity, ntiles, src_buf, s);
     case 3: return launch_key<KeyF32, LB>(c, parity, ntiles, src_buf, s);
     case 4: return launch_key<KeyU64, LB>(c, parity, ntiles, src_buf, s);
+    case 5: return launch_key<KeyI64, LB>(c, parity, ntiles, src_buf, s);
+    case 6: return launch_key<KeyF64, LB>(c, parity, ntiles, src_buf, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -148,7 +148,7 @@ BucketLayout bucket_layout(size_t n) {
 
 // Widest LDS class of the batched form: 16384 keys, 8192 for 64-bit keys
 // with a payload (12 LDS bytes a slot).
-uint32_t batch_base_max(uint32_t kt, bool vals) { return kt == PDQ_U64 && vals ? 8192u : kWideBaseMax; }
+uint32_t batch_base_max(uint32_t kt, bool vals) { return key_bytes(kt) == 8 && vals ? 8192u : kWideBaseMax; }
 
 Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) {
   Layout L;
@@ -216,7 +216,7 @@ Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool lear
   return L;
 }
 
-bool valid_key_type(int kt) { return kt >= PDQ_U32 && kt <= PDQ_U64; }
+bool valid_key_type(int kt) { return kt >= PDQ_U32 && kt <= PDQ_F64; }
 
 struct Opts {
   uint32_t flags = 0;

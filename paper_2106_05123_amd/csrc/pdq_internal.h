@@ -162,6 +162,21 @@ struct KeyU64 {
   static __device__ __forceinline__ uint64_t ord(uint64_t x) { return x; }
   static __device__ __forceinline__ uint64_t inv(uint64_t x) { return x; }
 };
+struct KeyI64 {
+  using T = uint64_t;
+  static __device__ __forceinline__ uint64_t ord(uint64_t x) { return x ^ 0x8000000000000000ull; }
+  static __device__ __forceinline__ uint64_t inv(uint64_t x) { return x ^ 0x8000000000000000ull; }
+};
+struct KeyF64 {
+  using T = uint64_t;
+  // negative: flip all bits; non-negative: set the sign bit
+  static __device__ __forceinline__ uint64_t ord(uint64_t x) {
+    return x ^ (static_cast<uint64_t>(static_cast<int64_t>(x) >> 63) | 0x8000000000000000ull);
+  }
+  static __device__ __forceinline__ uint64_t inv(uint64_t y) {
+    return (y & 0x8000000000000000ull) ? (y ^ 0x8000000000000000ull) : ~y;
+  }
+};
 
 // SplitMix64 output function (Steele, Lea and Flood, 2014): the counter-based
 // generator behind every random choice of the library.
@@ -186,7 +201,7 @@ hipError_t launch_base(const Ctx& c, int cls, uint32_t nitems, hipStream_t s);
 hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s);
 hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s);
 
-inline uint32_t key_bytes(uint32_t key_type) { return key_type == 4 ? 8u : 4u; }
+inline uint32_t key_bytes(uint32_t key_type) { return key_type >= 4 ? 8u : 4u; }
 
 // Size class of a base-case segment of n keys (1 <= n <= kWideBaseMax).
 __host__ __device__ inline int base_class(uint64_t n) {

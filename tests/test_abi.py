@@ -77,7 +77,7 @@ def test_argument_errors_without_gpu(pdq):
     Opt = pdq.Options
     assert _call_sort(pdq, 0x1000, 10, order=1) == -2
     assert _call_sort(pdq, 0x1000, 10, kt=0) == -2
-    assert _call_sort(pdq, 0x1000, 10, kt=5) == -2
+    assert _call_sort(pdq, 0x1000, 10, kt=7) == -2  # 1 ... 6 are the key types
     assert _call_sort(pdq, 0, 10) == -1                      # null keys
     assert _call_sort(pdq, 0x1002, 10) == -1                 # misaligned u32 keys
     assert _call_sort(pdq, 0x1004, 10, kt=4) == -1           # misaligned u64 keys

@@ -216,6 +216,17 @@ def test_learned_sort_bit_exact(dist):
         assert st["learned"] == 2  # narrow components: the fit is judged too coarse
 
 
+@pytest.mark.parametrize("kt", ["i64", "f64"])
+def test_learned_sort_wide_signed_and_double(kt):
+    # 64-bit signed and double keys through the learned pass: bit-exact
+    # whether the fit is used or judged and sent to the plain path
+    n = (1 << 21) + 11
+    a = W.random_keys(kt, n, seed=12)
+    out, _, st = gpu_sort(a, learned=True)
+    assert st["learned"] in (1, 2)
+    assert np.array_equal(as_bytes(out), as_bytes(oracle.sort(a)[0]))
+
+
 @pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
 def test_learned_sort_pairs(kt):
     n = (1 << 21) + 11

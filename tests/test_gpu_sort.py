@@ -77,7 +77,7 @@ def test_patterns_i32(pattern):
         assert st["passes"] == 1 and st["sorted_elements"] == a.size
 
 
-@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64", "i64", "f64"])
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 100, 4095, 4096, 4097, 4098, 8191, 8192, 8193, 12289, 65537, 1000003])
 def test_sizes_and_key_types(kt, n):
     a = W.random_keys(kt, n, seed=n + 17)

@@ -132,7 +132,7 @@ def test_paper_patterns_vs_numpy(oracle_lib, pattern):
     assert np.array_equal(k, np.sort(a))
 
 
-@pytest.mark.parametrize("kt", ["u32", "i32", "u64"])
+@pytest.mark.parametrize("kt", ["u32", "i32", "u64", "i64"])
 def test_key_types_vs_numpy(oracle_lib, kt):
     a = W.random_keys(kt, 300_001, seed=5)
     k, _, _, _ = oracle_lib.sort(a)
@@ -384,6 +384,29 @@ def test_slowdown_closed_forms():
 
 F32_ORDER = [0xFF800000, 0xFF7FFFFF, 0xBF800000, 0x80800000, 0x807FFFFF, 0x80000001, 0x80000000,
              0x00000000, 0x00000001, 0x007FFFFF, 0x00800000, 0x3F800000, 0x7F7FFFFF, 0x7F800000]
+
+
+F64_ORDER = [-np.inf, -1.7976931348623157e308, -1.0, -2.2250738585072014e-308, -5e-324, -0.0, 0.0, 5e-324,
+             2.2250738585072014e-308, 1.0, 1.7976931348623157e308, np.inf]
+
+
+def test_double_and_int64_order(oracle_lib):
+    # IEEE order with -0.0 before +0.0 (the float32 rule on 64 bits), and
+    # two's-complement order for int64
+    imgs = [oracle_lib.key_image("f64", x) for x in F64_ORDER]
+    assert all(x < y for x, y in zip(imgs, imgs[1:]))
+    ints = [-(2**63), -(2**62), -1, 0, 1, 2**62, 2**63 - 1]
+    imgs = [oracle_lib.key_image("i64", x) for x in ints]
+    assert all(x < y for x, y in zip(imgs, imgs[1:]))
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(150_001)
+    a[rng.choice(a.size, 2000, replace=False)] = 0.0
+    a[rng.choice(a.size, 2000, replace=False)] = -0.0
+    k, _, _, _ = oracle_lib.sort(a)
+    assert np.array_equal(k, np.sort(a))  # numerically sorted (numpy treats the zeros as equal)
+    z = k[k == 0.0]
+    neg = np.signbit(z)
+    assert neg.sum() > 0 and not np.any(neg[np.argmin(neg):])  # every -0.0 before every +0.0
 
 
 def test_float_bit_order(oracle_lib):
