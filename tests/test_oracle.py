@@ -432,3 +432,80 @@ def test_integer_edge_order(oracle_lib):
         a = np.tile(arr, 30)[rng.permutation(arr.size * 30)]
         k, _, _, _ = oracle_lib.sort(a)
         assert np.array_equal(k, np.repeat(arr, 30))
+
+
+# ---------------------------------------------------------------- Q8 Section 4.2 fresh candidates
+
+def _q8_child(child):
+    """A child of a bad partition after the fresh-candidate rule of Section
+    4.2, written here from the reading of that section: the first and last
+    candidates trade places with the elements a quarter of the child in from
+    either end; children of more than 128 keys also move the ninther's other
+    outer candidates (first+1, first+2, last-1, last-2) by the same distance."""
+    c = list(child)
+    s = len(c)
+    q = s // 4
+    pairs = [(0, q), (s - 1, s - 1 - q)]
+    if s > 128:
+        pairs += [(1, q + 1), (2, q + 2), (s - 2, s - 2 - q), (s - 3, s - 3 - q)]
+    for i, j in pairs:
+        c[i], c[j] = c[j], c[i]
+    return c
+
+
+def _pivot_by_definition(c):
+    """Median of first/middle/last up to 128 keys, Tukey's ninther above."""
+    s = len(c)
+    m = s // 2
+    if s <= 128:
+        return sorted([c[0], c[m], c[s - 1]])[1]
+    return ninther_by_definition(np.array(c))
+
+
+def _planted(n, vals, seed):
+    """A permutation of 0..n-1 whose nine ninther candidates hold `vals`."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    pos = [0, m, n - 1, 1, m - 1, n - 2, 2, m + 1, n - 3]
+    vals = list(rng.permutation(vals))
+    rest = rng.permutation([v for v in range(n) if v not in set(vals)])
+    a = np.empty(n, dtype=np.uint32)
+    mask = np.zeros(n, dtype=bool)
+    mask[pos] = True
+    a[pos] = vals
+    a[~mask] = rest
+    return a
+
+
+@pytest.mark.parametrize("case", ["right_above_128", "left_24_to_128", "left_above_128"])
+def test_fresh_candidates_after_bad_partition(oracle_lib, case):
+    """After a planted bad first partition of 4096 keys, the next pivot is the
+    median-of-3 or ninther over the child whose candidates were refreshed by
+    the Section 4.2 rule (pivot log). The left child is recursed first; when
+    it is below the insertion threshold the next pivot is the right child's.
+    Each case runs on 40 random permutations, so an offset moved by one in
+    the rule changes some expected pivot."""
+    n = 4096
+    planted = {"right_above_128": range(0, 9), "left_24_to_128": range(56, 65),
+               "left_above_128": range(296, 305)}[case]
+    differs = 0
+    for seed in range(40):
+        a = _planted(n, list(planted), seed)
+        part, (r, _), _ = oracle_lib.routine("partition_right", a)
+        assert part[r] == ninther_by_definition(a)
+        assert r < n >> 3  # the first partition is bad
+        _, _, c, (logk, logm) = oracle_lib.sort(a, count=True, pivot_log=4)
+        assert c["first_bad"] == 1 and c["first_left_size"] == r
+        if case == "right_above_128":
+            assert r < 24
+            child = part[r + 1:]
+        else:
+            assert (24 <= r <= 128) == (case == "left_24_to_128")
+            child = part[:r]
+        expect = _pivot_by_definition(_q8_child(child))
+        assert int(logk[1]) == int(expect), (seed, r)
+        assert logm[1] == 0
+        differs += int(_pivot_by_definition(list(child)) != expect)
+    # the rule matters on these inputs: without it most children would have
+    # taken another pivot
+    assert differs >= 20
