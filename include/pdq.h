@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define PDQ_ABI_VERSION 2
+#define PDQ_ABI_VERSION 3
 
 /* Largest segment that goes straight to the LDS base case. */
 #define PDQ_BASE_CASE_MAX 4096
@@ -80,7 +80,9 @@ enum pdq_status {
   PDQ_ERR_INVALID = -1,     /* null pointer with n > 0, misaligned pointer, bad offsets (validate mode) */
   PDQ_ERR_UNSUPPORTED = -2, /* key type, order, n >= 2^32, unknown flag */
   PDQ_ERR_WORKSPACE = -3,   /* d_ws NULL or ws_bytes below pdq_workspace_bytes() */
-  PDQ_ERR_HIP = -4          /* a HIP launch or synchronisation failed (see pdq_last_hip_error) */
+  PDQ_ERR_HIP = -4,         /* a HIP launch or synchronisation failed (see pdq_last_hip_error) */
+  PDQ_ERR_SCRATCH = -5      /* pdq_sort_noalloc: the call needs more scratch than
+                               PDQ_NOALLOC_SCRATCH_BYTES */
 };
 
 enum pdq_flags {
@@ -213,6 +215,33 @@ int pdq_plan_launch(pdq_plan* plan, void* stream);
 int pdq_plan_info(const pdq_plan* plan, uint32_t* shape, double* ms);
 
 void pdq_plan_destroy(pdq_plan* plan);
+
+/* Bytes of the library's own device scratch array used by pdq_sort_noalloc
+ * (one copy per GPU, held until the process ends). */
+#define PDQ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* pdq_sort / pdq_sort_pairs without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). The scratch that pdq_sort keeps in
+ * d_ws (second key and payload buffer, segment lists, counters) lives instead
+ * in a file-scope device array of PDQ_NOALLOC_SCRATCH_BYTES inside the
+ * library; this call allocates nothing (no hipMalloc, no events, no library
+ * allocation). d_vals may be NULL (keys only, as pdq_sort) or a uint32
+ * payload moved with the keys (as pdq_sort_pairs). A call whose
+ * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt) exceeds
+ * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
+ * (without PDQ_LEARNED: about 16.1 million uint32 keys, 8.2 million uint32
+ * keys with payloads or uint64 keys, 5.5 million uint64 keys with payloads).
+ * PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return PDQ_ERR_UNSUPPORTED.
+ * Every call on one GPU shares that GPU's array, which keeps the previous
+ * call's contents (the call clears what must start at zero): calls that
+ * overlap in time on one GPU -- on different streams, or from different
+ * threads -- race and corrupt each other's results; serialise them. The
+ * first call on each device looks up the array's address on that device
+ * (the device must be current). Results, errors and synchronisation are
+ * those of pdq_sort / pdq_sort_pairs. */
+int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type, pdq_order order,
+                     void* stream, const pdq_options* opt, pdq_stats* stats);
 
 /* Human-readable text of a status code (static storage). */
 const char* pdq_status_string(int status);

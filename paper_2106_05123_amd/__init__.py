@@ -27,13 +27,15 @@ __all__ = [
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
     "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
-    "Plan",
+    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpdq.so")
 
 PDQ_OK = 0
+PDQ_ERR_SCRATCH = -5
+NOALLOC_SCRATCH_BYTES = 64 << 20  # PDQ_NOALLOC_SCRATCH_BYTES
 FLAG_VALIDATE = 1
 FLAG_PROFILE = 2
 FLAG_LEARNED = 4
@@ -141,6 +143,9 @@ def lib():
         L.pdq_segmented_sort.argtypes = [vp, u32p, sz, vp, sz, ctypes.c_int, ctypes.c_int, vp, sz, vp,
                                          ctypes.POINTER(Options), ctypes.POINTER(Stats)]
         L.pdq_segmented_sort.restype = ctypes.c_int
+        L.pdq_sort_noalloc.argtypes = [vp, u32p, sz, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(Options),
+                                       ctypes.POINTER(Stats)]
+        L.pdq_sort_noalloc.restype = ctypes.c_int
         L.pdq_status_string.argtypes = [ctypes.c_int]
         L.pdq_status_string.restype = ctypes.c_char_p
         L.pdq_last_hip_error.argtypes = []
@@ -297,6 +302,29 @@ def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: i
                                   keys.numel(), ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), kt, 0,
                                   ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
                                   ctypes.byref(st) if st is not None else None)
+    _check(rc)
+    return _finish(st, st is not None)
+
+
+def sort_noalloc_(keys, vals=None, *, force_budget: int = -1, tile: int = 0, stats: bool = False,
+                  learned: bool = False, seed: int = 0, deterministic: bool = False):
+    """pdq_sort_noalloc: sort keys (and move the uint32 payload vals, if
+    given) in place using the library's own device scratch array instead of
+    a workspace; nothing is allocated. Sizes beyond PDQ_NOALLOC_SCRATCH_BYTES
+    raise PdqError (PDQ_ERR_SCRATCH); calls on one GPU must not overlap."""
+    import torch
+    if not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous device tensor")
+    if vals is not None and (vals.dtype != torch.uint32 or not vals.is_cuda or not vals.is_contiguous()
+                             or vals.numel() != keys.numel()):
+        raise ValueError("vals must be a contiguous uint32 device tensor with as many elements as keys")
+    kt = _key_type(keys)
+    flags = (FLAG_LEARNED if learned else 0) | (FLAG_DETERMINISTIC if deterministic else 0)
+    opt = _options(force_budget, tile, flags, seed=seed)
+    st = Stats(ctypes.sizeof(Stats)) if stats else None
+    stream = ctypes.c_void_p(torch.cuda.current_stream(keys.device).cuda_stream)
+    rc = lib().pdq_sort_noalloc(_ptr(keys), _ptr(vals), keys.numel(), kt, 0, stream, ctypes.byref(opt),
+                                ctypes.byref(st) if st is not None else None)
     _check(rc)
     return _finish(st, st is not None)
 

@@ -829,6 +829,40 @@ int sort_entry(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, si
   return rc;
 }
 
+// ---- scratch of pdq_sort_noalloc ---------------------------------------------
+
+constexpr size_t kNoAllocBytes = PDQ_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+// The workspace of pdq_sort_noalloc: one copy of this array on every GPU the
+// library runs on. Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// that noalloc_scratch looks up once per device.
+static __device__ __align__(256) unsigned char scratch[PDQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current and kept for later calls.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PDQ_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return PDQ_ERR_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PDQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -871,6 +905,8 @@ const char* pdq_status_string(int status) {
     case PDQ_ERR_UNSUPPORTED: return "PDQ_ERR_UNSUPPORTED: unsupported key type, order, size or option";
     case PDQ_ERR_WORKSPACE: return "PDQ_ERR_WORKSPACE: workspace missing or smaller than pdq_workspace_bytes()";
     case PDQ_ERR_HIP: return "PDQ_ERR_HIP: a HIP launch or synchronisation failed";
+    case PDQ_ERR_SCRATCH:
+      return "PDQ_ERR_SCRATCH: pdq_sort_noalloc needs more scratch than PDQ_NOALLOC_SCRATCH_BYTES for this size";
     default: return "unknown pdq status";
   }
 }
@@ -878,6 +914,28 @@ const char* pdq_status_string(int status) {
 int pdq_last_hip_error(void) { return g_last_hip; }
 
 int pdq_abi_version(void) { return PDQ_ABI_VERSION; }
+
+int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type, pdq_order order,
+                     void* stream, const pdq_options* opt, pdq_stats* stats) {
+  g_last_hip = 0;
+  Opts o;
+  const int rc = read_opts(opt, &o);
+  if (rc != PDQ_OK) return rc;
+  if (o.flags & (PDQ_PROFILE | PDQ_BATCHED | PDQ_AUTOTUNE)) return PDQ_ERR_UNSUPPORTED;
+  if (!valid_key_type(key_type) || order != PDQ_ASCENDING || n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (n > 1) {
+    if (!d_keys) return PDQ_ERR_INVALID;
+    // the size check comes before anything touches the GPU
+    const size_t need = pdq_workspace_bytes(n, 1, key_type, d_vals != nullptr, opt);
+    if (need == 0 || need > kNoAllocBytes) return PDQ_ERR_SCRATCH;
+  }
+  void* ws = nullptr;
+  if (n > 1) {
+    const int r2 = noalloc_scratch(&ws);
+    if (r2 != PDQ_OK) return r2;
+  }
+  return sort_entry(d_keys, d_vals, n, nullptr, 1, key_type, order, ws, kNoAllocBytes, stream, opt, stats);
+}
 
 // ---- captured batched sort --------------------------------------------------
 

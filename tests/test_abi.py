@@ -49,7 +49,7 @@ def test_abi_version_matches_header(pdq):
 
 def test_status_strings(pdq):
     for code, name in ((0, "PDQ_OK"), (-1, "PDQ_ERR_INVALID"), (-2, "PDQ_ERR_UNSUPPORTED"),
-                       (-3, "PDQ_ERR_WORKSPACE"), (-4, "PDQ_ERR_HIP")):
+                       (-3, "PDQ_ERR_WORKSPACE"), (-4, "PDQ_ERR_HIP"), (-5, "PDQ_ERR_SCRATCH")):
         assert pdq.status_string(code).startswith(name)
     assert "unknown" in pdq.status_string(12345)
 
@@ -95,6 +95,37 @@ def test_argument_errors_without_gpu(pdq):
                                 1 << 40, None, None, None) == -1
     assert L.pdq_segmented_sort(ctypes.c_void_p(0x1000), None, 10, ctypes.c_void_p(0x1004), 3, 1, 0,
                                 ctypes.c_void_p(0x10000), 1 << 40, None, None, None) == -1  # misaligned offsets
+
+
+def test_noalloc_limits_without_gpu(pdq):
+    """pdq_sort_noalloc rejects what does not fit its scratch array, and the
+    options it does not serve, before anything touches the GPU."""
+    L = pdq.lib()
+    Opt = pdq.Options
+    m = re.search(r"#define PDQ_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", open(HEADER).read())
+    limit = int(m.group(1)) << int(m.group(2))
+    assert limit == pdq.NOALLOC_SCRATCH_BYTES
+    k = ctypes.c_void_p(0x1000)
+    v = ctypes.c_void_p(0x2000)
+    for kt, has_v in ((1, False), (1, True), (4, False), (4, True)):
+        # the largest n whose workspace fits, and the next one
+        lo, hi = 2, 1 << 30
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if pdq.workspace_bytes(mid, 1, kt, has_v) <= limit:
+                lo = mid
+            else:
+                hi = mid - 1
+        assert L.pdq_sort_noalloc(k, v if has_v else None, lo + 1, kt, 0, None, None, None) == -5
+    assert L.pdq_sort_noalloc(k, None, 1 << 31, 1, 0, None, None, None) == -5
+    assert L.pdq_sort_noalloc(k, None, 1 << 32, 1, 0, None, None, None) == -2
+    assert L.pdq_sort_noalloc(None, None, 10, 1, 0, None, None, None) == -1
+    assert L.pdq_sort_noalloc(k, None, 10, 1, 1, None, None, None) == -2   # order
+    assert L.pdq_sort_noalloc(k, None, 10, 9, 0, None, None, None) == -2   # key type
+    assert L.pdq_sort_noalloc(None, None, 1, 1, 0, None, None, None) == 0  # n <= 1 is a no-op
+    for flag in (pdq.FLAG_PROFILE, pdq.FLAG_BATCHED, pdq.FLAG_AUTOTUNE):
+        o = Opt(ctypes.sizeof(Opt), flag, -1, 0, 0)
+        assert L.pdq_sort_noalloc(k, None, 10, 1, 0, None, ctypes.byref(o), None) == -2
 
 
 def test_binding_has_no_fallback(pdq, monkeypatch):
