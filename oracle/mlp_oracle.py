@@ -12,9 +12,11 @@ float32), so that it can be read against this summary:
 
   sample     position j = SplitMix64(seed ^ j) mod n, j < m, with replacement;
              keys are taken as their order-preserving unsigned images
-  feature    of a sorted sample image v: a piecewise-linear log2
-             L(v) = e + (v - 2^e) / 2^e for v >= 1 with e = floor(log2 v),
-             L(0) = -1, scaled by the sample's min and max onto [0, 1]; or a
+  feature    of a sorted sample image v: a smooth pseudo-log2
+             L(v) = e + (4 f - f^2) / 3 with f = (v - 2^e) / 2^e in [0, 1) and
+             e = floor(log2 v) for v >= 1, L(0) = -1 (within 0.0098 of log2,
+             increasing, and with a continuous slope across every power of
+             two), scaled by the sample's min and max onto [0, 1]; or a
              linear scaling (v - lo) / (hi - lo). The scaling whose sample is
              closer to uniform (smaller max |x_j - (j + 1/2) / m|) is used.
              Computed in float64 with correctly rounded operations only, then
@@ -37,6 +39,16 @@ float32), so that it can be read against this summary:
              cannot isolate; it gets an equality bin), else the first sample
              key whose running maximum of the clamped float32 prediction
              reaches k / 256; sorted, duplicates removed
+  leaves     second stage of the model (a two-level learned CDF, as in
+             learned index structures): the running maximum r of the clamped
+             prediction puts sample j in leaf min(63, floor(64 r_j)); every
+             leaf fits t = a + b u by least squares over its samples, with u
+             the feature x (x-leaves) or the clamped prediction (y-leaves);
+             sums run in index order in float64, a leaf of fewer than two
+             samples (or no spread) predicts its mean target
+  choice     the splitters of the prediction, of the x-leaves and of the
+             y-leaves are each judged on the sample (largest count of sample
+             keys in a range bin); the smallest wins, ties in that order
   bins       b = number of splitters <= key; equality bin 2b - 1 when
              key == s[b - 1], range bin 2b otherwise (2u + 1 bins)
 
@@ -120,14 +132,20 @@ def floor_log2_u64(v: np.ndarray) -> np.ndarray:
 
 
 def pseudo_log2(v: np.ndarray) -> np.ndarray:
-    """L(v) = e + (v - 2^e) / 2^e, L(0) = -1; float64 with one rounding in the
-    integer-to-float conversion and one in the final addition."""
+    """L(v) = e + (4 f - f^2) / 3 with f = (v - 2^e) / 2^e, L(0) = -1.
+    On [0, 1) the polynomial p(f) = (4 f - f^2) / 3 has p(0) = 0, p(1) = 1 and
+    p'(1) = p'(0) / 2, so L is increasing with a slope that is continuous
+    across each power of two (a chord per octave, the first version, kinks
+    there, which a small network follows badly). float64, correctly rounded
+    operations in this order: f (exact scaling of the converted difference),
+    f * f, 4 f - f * f, / 3, + e."""
     v = v.astype(np.uint64)
     out = np.full(v.shape, -1.0)
     nz = v > 0
     e = floor_log2_u64(v[nz])
     d = (v[nz] - (np.uint64(1) << e.astype(np.uint64))).astype(np.float64)
-    out[nz] = np.ldexp(d, -e) + e.astype(np.float64)
+    f = np.ldexp(d, -e)
+    out[nz] = (4.0 * f - f * f) / 3.0 + e.astype(np.float64)
     return out
 
 
@@ -301,6 +319,59 @@ def splitters(sorted_images: np.ndarray, pred: np.ndarray, nsplit: int = NSPLIT)
     return np.unique(np.array(out, dtype=np.uint64))
 
 
+LEAVES = 64
+
+
+def leaf_predictions(x: np.ndarray, t: np.ndarray, pred: np.ndarray, leaves: int = LEAVES):
+    """Second stage of the splitter model: returns the float32 predictions
+    of the x-leaves and of the y-leaves (see the module summary)."""
+    p32 = np.clip(np.asarray(pred, dtype=np.float32), np.float32(0), np.float32(1))
+    r = np.maximum.accumulate(p32)
+    leaf = np.minimum((r * np.float32(leaves)).astype(np.int64), leaves - 1)  # exact scaling, then floor
+    t64 = np.asarray(t, dtype=np.float32).astype(np.float64)
+    outs = []
+    for u32 in (np.asarray(x, dtype=np.float32), p32):
+        u = u32.astype(np.float64)
+        out = np.zeros(u.size, dtype=np.float32)
+        for j in range(leaves):
+            idx = np.nonzero(leaf == j)[0]
+            if idx.size == 0:
+                continue
+            uj, tj = u[idx], t64[idx]
+            k = float(idx.size)
+            # float32 * float32 is exact in float64, so only the additions round
+            sx = np.add.accumulate(uj)[-1]
+            st = np.add.accumulate(tj)[-1]
+            sxx = np.add.accumulate(uj * uj)[-1]
+            sxt = np.add.accumulate(uj * tj)[-1]
+            den = k * sxx - sx * sx
+            if idx.size < 2 or not den > 0.0:
+                b = 0.0
+                a = st / k
+            else:
+                b = (k * sxt - sx * st) / den
+                a = (st - b * sx) / k
+            out[idx] = (np.float64(a) + np.float64(b) * uj).astype(np.float32)
+        outs.append(out)
+    return outs[0], outs[1]
+
+
+def sample_judge(sorted_images: np.ndarray, split: np.ndarray) -> int:
+    """Largest number of sample keys in one range bin of these splitters."""
+    return int(histogram(sorted_images, split)[0::2].max())
+
+
+def choose_splitters(sorted_images: np.ndarray, x: np.ndarray, t: np.ndarray, pred: np.ndarray):
+    """Splitters of the prediction, the x-leaves and the y-leaves; the one
+    with the smallest sample judge wins (the first on ties). Returns
+    (splitters, choice, estimates, leaf predictions)."""
+    px, py = leaf_predictions(x, t, pred)
+    cands = [splitters(sorted_images, c) for c in (pred, px, py)]
+    est = [sample_judge(sorted_images, c) for c in cands]
+    best = int(np.argmin(est))
+    return cands[best], best, est, (px, py)
+
+
 def bins_of(images: np.ndarray, split: np.ndarray) -> np.ndarray:
     """Bin of every key image: range bin 2b, equality bin 2b - 1."""
     images = images.astype(np.uint64)
@@ -324,10 +395,11 @@ def judge(hist: np.ndarray, n: int, limit: float = 2.0) -> bool:
 
 # ----------------------------------------------------------------- whole fit
 
-def fit(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, steps: int = 256, batch: int = 1024,
+def fit(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, steps: int = 128, batch: int = 1024,
         residual: bool = True):
-    """Sample, sort, features, targets, Adam, float32 inference, splitters.
-    Returns a dict of every intermediate."""
+    """Sample, sort, features, targets, Adam, float32 inference, leaves,
+    the sample-judged choice of splitters. Returns a dict of every
+    intermediate."""
     img = key_images(keys)
     pos = sample_positions(seed, m, img.size)
     samp = np.sort(img[pos])
@@ -336,5 +408,6 @@ def fit(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, steps: int = 256, bat
     p0 = init_params(seed, x)
     p, losses = adam_train(p0, x, t, seed, steps, batch, residual)
     y = infer_f32(p, x, residual)
-    sp = splitters(samp, y)
-    return dict(sample=samp, x=x, use_log=use_log, t=t, p0=p0, params=p, losses=losses, pred=y, splitters=sp)
+    sp, choice, est, leaves = choose_splitters(samp, x, t, y)
+    return dict(sample=samp, x=x, use_log=use_log, t=t, p0=p0, params=p, losses=losses, pred=y, splitters=sp,
+                choice=choice, estimates=est, leaf_pred=leaves, root_splitters=splitters(samp, y))

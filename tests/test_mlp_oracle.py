@@ -130,11 +130,16 @@ def test_training_reduces_loss_and_beats_untrained_splitters():
 # ----------------------------------------------------------------- features and targets
 
 def test_pseudo_log2_exact_values():
+    # p(f) = (4 f - f^2) / 3 at f = 0, 1/4, 1/2, 3/4: 0, 5/16, 7/12, 13/16
     e = np.arange(64, dtype=np.uint64)
     pw = np.uint64(1) << e
     assert np.array_equal(M.pseudo_log2(pw), np.arange(64, dtype=np.float64))
     three_halves = (np.uint64(3) << (e[1:] - np.uint64(1)))
-    assert np.array_equal(M.pseudo_log2(three_halves), np.arange(1, 64) + 0.5)
+    assert np.array_equal(M.pseudo_log2(three_halves), np.arange(1, 64) + 7.0 / 12.0)
+    five_quarters = (np.uint64(5) << (e[2:] - np.uint64(2)))
+    assert np.array_equal(M.pseudo_log2(five_quarters), np.arange(2, 64) + 5.0 / 16.0)
+    seven_quarters = (np.uint64(7) << (e[2:] - np.uint64(2)))
+    assert np.array_equal(M.pseudo_log2(seven_quarters), np.arange(2, 64) + 13.0 / 16.0)
     assert M.pseudo_log2(np.array([0], dtype=np.uint64))[0] == -1.0
     assert np.array_equal(M.floor_log2_u64(np.array([1, 2, 3, 2**63, 2**64 - 1], dtype=np.uint64)),
                           [0, 1, 1, 63, 63])
@@ -145,8 +150,23 @@ def test_pseudo_log2_monotone_and_close_to_log2():
     L = M.pseudo_log2(v)
     assert np.all(np.diff(L) >= 0)
     nz = v > 0
-    # log2(1 + f) - f peaks at 0.0860713... on [0, 1)
-    assert np.max(np.log2(v[nz].astype(np.float64)) - L[nz]) <= 0.0861
+    # log2(1 + f) - (4 f - f^2) / 3 on [0, 1) lies in [-0.005342, 0.009709]
+    d = np.log2(v[nz].astype(np.float64)) - L[nz]
+    assert d.max() <= 0.00971 and d.min() >= -0.00535
+
+
+def test_pseudo_log2_slope_continuous_across_powers_of_two():
+    """The chord-per-octave form doubled its slope at every power of two;
+    this one keeps it: finite-difference slopes just below and just above
+    2^e agree, and equal (2/3) / 2^(e-1) (p'(1) / 2^(e-1) = p'(0) / 2^e)."""
+    for e in (20, 33, 47):
+        v = np.uint64(1) << np.uint64(e)
+        h = np.uint64(1) << np.uint64(e - 12)
+        L = M.pseudo_log2(np.array([v - h, v, v + h], dtype=np.uint64))
+        left = (L[1] - L[0]) / float(h)
+        right = (L[2] - L[1]) / float(h)
+        want = (2.0 / 3.0) / 2.0 ** (e - 1)
+        assert abs(left / want - 1) < 2e-3 and abs(right / want - 1) < 2e-3
 
 
 def test_features_choose_scaling():
@@ -269,3 +289,71 @@ def test_bins_brute_force_and_histogram():
     assert int(h[1]) == int(np.count_nonzero(keys == 3))
     assert M.judge(np.array([10, 500, 10], dtype=np.uint64), 256 * 5, limit=2.0)
     assert not M.judge(np.array([11, 0, 10], dtype=np.uint64), 256 * 5, limit=2.0)
+
+
+# ----------------------------------------------------------------- leaves, sample judge, choice
+
+def test_leaves_reproduce_a_linear_cdf_exactly():
+    """t = x on dyadic x: every leaf (on x or on the prediction t) fits
+    slope 1 and intercept 0 with exact sums, so both leaf predictions are
+    x itself."""
+    m = 1 << 14
+    x = (np.arange(m, dtype=np.float64) / m).astype(np.float32)
+    px, py = M.leaf_predictions(x, x, x)
+    assert np.array_equal(px, x) and np.array_equal(py, x)
+
+
+def test_leaves_match_least_squares_per_leaf():
+    """Against numpy's polyfit on each leaf's samples (leaves from the
+    running maximum of the clamped prediction)."""
+    rng = np.random.default_rng(12)
+    m = 1 << 13
+    x = np.sort(rng.random(m)).astype(np.float32)
+    t = np.sort(rng.random(m)).astype(np.float32)
+    pred = (t + rng.normal(0, 0.01, m)).astype(np.float32)
+    px, py = M.leaf_predictions(x, t, pred, leaves=16)
+    r = np.maximum.accumulate(np.clip(pred, 0, 1))
+    leaf = np.minimum(np.floor(r.astype(np.float64) * 16).astype(np.int64), 15)
+    for u, got in ((x, px), (np.clip(pred, 0, 1), py)):
+        for j in range(16):
+            sel = leaf == j
+            if sel.sum() < 2:
+                continue
+            b, a = np.polyfit(u[sel].astype(np.float64), t[sel].astype(np.float64), 1)
+            assert np.allclose(got[sel], a + b * u[sel], rtol=0, atol=2e-6)
+
+
+def test_leaf_of_one_sample_predicts_its_target():
+    x = np.array([0.1, 0.2, 0.3, 0.9], dtype=np.float32)
+    t = np.array([0.125, 0.375, 0.625, 0.875], dtype=np.float32)
+    pred = np.array([0.05, 0.06, 0.07, 0.95], dtype=np.float32)  # leaves {0,1,2} and {3} for 2 leaves
+    px, py = M.leaf_predictions(x, t, pred, leaves=2)
+    assert px[3] == t[3] and py[3] == t[3]
+
+
+def test_sample_judge_brute_force():
+    rng = np.random.default_rng(13)
+    s = np.sort(rng.integers(0, 500, 4000)).astype(np.uint64)
+    sp = np.unique(rng.choice(s, 40))
+    counts = {}
+    for k in s:
+        below = int(np.sum(sp <= k))
+        if below and sp[below - 1] == k:
+            continue  # equality bin
+        counts[below] = counts.get(below, 0) + 1
+    assert M.sample_judge(s, sp) == max(counts.values())
+
+
+def test_choice_takes_the_smallest_sample_judge_first_on_ties():
+    m = 1 << 12
+    s = np.arange(m, dtype=np.uint64) * np.uint64(3)
+    x = (np.arange(m) / m).astype(np.float32)
+    t = ((np.arange(m) + 0.5) / m).astype(np.float32)
+    # a root prediction that is far off (a square): the leaves repair it
+    pred = (x.astype(np.float64) ** 2).astype(np.float32)
+    sp, choice, est, _ = M.choose_splitters(s, x, t, pred)
+    assert est[choice] == min(est) and choice != 0 and est[0] > est[choice]
+    assert M.sample_judge(s, sp) == est[choice]
+    # a perfect root: all three candidates tie and the root wins
+    sp2, choice2, est2, _ = M.choose_splitters(s, x, t, t)
+    assert choice2 == 0 and est2[0] == min(est2)
