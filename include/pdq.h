@@ -81,8 +81,13 @@ enum pdq_status {
   PDQ_ERR_UNSUPPORTED = -2, /* key type, order, n >= 2^32, unknown flag */
   PDQ_ERR_WORKSPACE = -3,   /* d_ws NULL or ws_bytes below pdq_workspace_bytes() */
   PDQ_ERR_HIP = -4,         /* a HIP launch or synchronisation failed (see pdq_last_hip_error) */
-  PDQ_ERR_SCRATCH = -5      /* pdq_sort_noalloc: the call needs more scratch than
+  PDQ_ERR_SCRATCH = -5,     /* pdq_sort_noalloc: the call needs more scratch than
                                PDQ_NOALLOC_SCRATCH_BYTES */
+  PDQ_ERR_DEVICE = -6       /* a kernel caught an internal inconsistency (a reservation or split
+                               that does not fit its segment, a lost queue item) or a bounded wait
+                               timed out, and skipped its writes: the output is not sorted.
+                               Reported by the call itself when it synchronises (stats requested,
+                               or a host-driven pass loop), else by pdq_check afterwards */
 };
 
 enum pdq_flags {
@@ -91,18 +96,26 @@ enum pdq_flags {
   PDQ_LEARNED = 1u << 2,  /* learned multiway first pass (pdq_sort / pdq_sort_pairs with
                              n > 65536; other calls ignore it); pass the same options to
                              pdq_workspace_bytes */
-  PDQ_BATCHED = 1u << 3,  /* pdq_segmented_sort: one persistent launch over a device work
-                             queue, no host synchronisation (unless stats or PDQ_VALIDATE);
-                             meant for many segments of up to ~2^20 keys each; pass the same
-                             options to pdq_workspace_bytes */
+  PDQ_BATCHED = 1u << 3,  /* pdq_segmented_sort: device-counted partition passes and one
+                             persistent launch over a device work queue; the host synchronises
+                             once, after the first kernel, to size the passes (pdq_plan_launch
+                             not at all), and once more at the end only when stats are
+                             requested: without stats, device-side errors are reported by
+                             pdq_check. Meant for many segments of up to ~2^20 keys each; pass
+                             the same options to pdq_workspace_bytes */
   PDQ_AUTOTUNE = 1u << 4, /* pdq_plan_create: time every batched shape on the caller's data
                              first and keep the fastest (needs the workspace
                              pdq_workspace_bytes gives with this flag) */
-  PDQ_DETERMINISTIC = 1u << 5 /* partition tiles take their places in tile order by a decoupled
+  PDQ_DETERMINISTIC = 1u << 5, /* partition tiles take their places in tile order by a decoupled
                              look-back instead of one atomic reservation each: every run then
                              arranges the keys (and the payloads of equal keys) identically.
                              Slower. The learned pass's scatter still orders keys inside a bin
                              by LDS atomics, so with PDQ_LEARNED it covers the passes only */
+  PDQ_FRESH_FIXED = 1u << 6 /* after a bad partition take the fresh pivot candidates at the fixed
+                             quarter offsets of Section 4.2's deterministic rule instead of the
+                             default hashed positions (Section 4.2's randomised rule; the hash
+                             is keyed by pdq_options.seed, so a caller facing adversarial
+                             inputs should pass a secret seed) */
 };
 
 typedef struct pdq_options {
@@ -117,7 +130,7 @@ typedef struct pdq_options {
                             the sample, initial weights and minibatches of PDQ_LEARNED */
   float learned_imbalance_limit; /* PDQ_LEARNED: fall back to the plain path when a range bin holds
                                     more than limit * n / 256 keys; 0 = 2.0; < 0 = always fall back */
-  uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps, 0 = 256 (at most 65536) */
+  uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps, 0 = 128 (at most 65536) */
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
@@ -166,6 +179,18 @@ typedef struct pdq_stats {
   uint32_t batch_items;           /* PDQ_BATCHED: segments that went through the device queue */
   uint32_t batch_shape;           /* PDQ_BATCHED: persistent-kernel shape used (0 ... 3) */
   double batch_ms;                /* PDQ_BATCHED + PDQ_PROFILE: duration of the whole launch sequence */
+  uint32_t near_sorted;           /* single-range sorts finished before any partition pass (Section
+                                     5.2): 0 no, 1 one long run with at most 8192 keys in short runs
+                                     (sorted, then merged into it), 2 two long runs merged, 3 already
+                                     non-decreasing */
+  uint32_t pad_;
+  uint64_t near_sorted_runs;      /* maximal non-decreasing runs found (near_sorted != 0) */
+  uint64_t near_sorted_outliers;  /* keys in short runs (near_sorted == 1) */
+  uint32_t learned_choice;        /* PDQ_LEARNED: splitters taken from 0 the network, 1 its x-leaves,
+                                     2 its y-leaves (pdq_learned.h) */
+  uint32_t pad2_;
+  uint64_t learned_sample_judge;  /* PDQ_LEARNED: sample keys in the fullest range bin of the chosen
+                                     splitters (of PDQ_LEARN_SAMPLE) */
 } pdq_stats;
 
 /* Bytes of device workspace needed for a call with these sizes and options
@@ -230,18 +255,24 @@ void pdq_plan_destroy(pdq_plan* plan);
  * payload moved with the keys (as pdq_sort_pairs). A call whose
  * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt) exceeds
  * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
- * (without PDQ_LEARNED: about 16.1 million uint32 keys, 8.2 million uint32
- * keys with payloads or uint64 keys, 5.5 million uint64 keys with payloads).
- * PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return PDQ_ERR_UNSUPPORTED.
- * Every call on one GPU shares that GPU's array, which keeps the previous
- * call's contents (the call clears what must start at zero): calls that
- * overlap in time on one GPU -- on different streams, or from different
- * threads -- race and corrupt each other's results; serialise them. The
- * first call on each device looks up the array's address on that device
- * (the device must be current). Results, errors and synchronisation are
- * those of pdq_sort / pdq_sort_pairs. */
+ * (without PDQ_LEARNED: up to 16,149,632 uint32 keys, 8,227,712 uint32 keys
+ * with payloads or uint64 keys, 5,519,936 uint64 keys with payloads). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return
+ * PDQ_ERR_UNSUPPORTED. Every call on one GPU shares that GPU's array, which
+ * keeps the previous call's contents (the call clears what must start at
+ * zero): calls that overlap in time on one GPU -- on different streams, or
+ * from different threads -- race and corrupt each other's results;
+ * serialise them. The first call on each device looks up the array's
+ * address on that device (the device must be current). Results, errors and
+ * synchronisation are those of pdq_sort / pdq_sort_pairs. */
 int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type, pdq_order order,
                      void* stream, const pdq_options* opt, pdq_stats* stats);
+
+/* Device-side error state of the last call (or plan launch) that used the
+ * workspace d_ws: waits for `stream` and returns PDQ_OK, PDQ_ERR_INVALID
+ * (the segment offsets were found inconsistent) or PDQ_ERR_DEVICE. Calls that
+ * return before their work has finished (PDQ_BATCHED without stats,
+ * pdq_plan_launch) cannot report these themselves. */
+int pdq_check(const void* d_ws, void* stream);
 
 /* Human-readable text of a status code (static storage). */
 const char* pdq_status_string(int status);

@@ -10,10 +10,17 @@
  *      sorted sample key;
  *   3. pdq_mlp_train: Adam on the 1 -> 32 -> 32 -> 1 ReLU MLP
  *      y = x + W3 . relu(W2 relu(W1 x + b1) + b2) + b3;
- *   4. pdq_mlp_infer and pdq_learned_extract: the splitters;
- *   5. pdq_bucket_histogram: keys per bin; a range bin above the imbalance
+ *   4. pdq_mlp_infer, then pdq_learned_leaves: a second stage of 64 linear
+ *      leaves (a two-level learned CDF model, as in learned index
+ *      structures) refines the network's prediction two ways;
+ *   5. pdq_learned_extract on each of the three predictions, and
+ *      pdq_sample_judge: the splitter set whose fullest range bin holds the
+ *      fewest sample keys is kept; if even that one is over the imbalance
+ *      limit (with a 15 % margin), the call goes back to the plain path
+ *      without a histogram;
+ *   6. pdq_bucket_histogram: keys per bin; a range bin above the imbalance
  *      limit sends the call back to the plain path;
- *   6. scatter into the bins, then partition passes inside the range bins.
+ *   7. scatter into the bins, then partition passes inside the range bins.
  *
  * The paper ("Pattern-defeating Quicksort", Peters, arXiv 2106.05123) has
  * no learned component; its Section 2 names multiway partitioning as the
@@ -85,7 +92,10 @@ int pdq_mlp_train(const float* d_x, const float* d_t, size_t m, uint64_t seed, u
                   size_t ws_bytes, void* stream);
 
 /* Features and targets of a sorted sample of key images d_sorted[0..m):
- * L(v) = e + (v - 2^e) / 2^e with e = floor(log2 v) and L(0) = -1;
+ * L(v) = e + (4 f - f^2) / 3 with f = (v - 2^e) / 2^e, e = floor(log2 v)
+ * and L(0) = -1 (a pseudo-log2 within 0.0098 of log2 whose slope is
+ * continuous across powers of two; operations in the order f * f,
+ * 4 f - f * f, / 3, + e);
  * xl = (L(v) - L(lo)) / (L(hi) - L(lo)), xn = (v - lo) / (hi - lo) with lo
  * and hi the first and last sample key, all in double with correctly
  * rounded operations; the scaling with the smaller max_j |x_j - (j+1/2)/m|
@@ -106,6 +116,26 @@ int pdq_learned_features(const uint64_t* d_sorted, size_t m, float* d_x, float* 
 int pdq_learned_extract(const uint64_t* d_sorted, const float* d_pred, size_t m, float* d_runmax,
                         uint64_t* d_splitters, uint32_t* d_count, void* stream);
 
+/* Second stage of the splitter model, over the sorted sample's features
+ * d_x, targets d_t and clamped float32 predictions d_pred (all [m]). The
+ * running maximum r of d_pred (written to d_runmax[m]) assigns sample j to
+ * leaf min(63, floor(64 r_j)); each leaf fits t = a + b u by least squares,
+ * u = x for the x-leaves and u = the prediction for the y-leaves, with the
+ * sums k, sum u, sum t, sum u^2, sum u t taken in index order in double,
+ * b = (k sum u t - sum u sum t) / (k sum u^2 - (sum u)^2) and
+ * a = (sum t - b sum u) / k (b = 0, a = mean t when the leaf has fewer than
+ * two samples or no spread). d_leaf[2][64][2] receives (a, b) of every
+ * leaf (x-leaves first); d_pred_x[j] and d_pred_y[j] the float32 of
+ * a + b u_j of sample j's leaf. */
+int pdq_learned_leaves(const float* d_x, const float* d_t, const float* d_pred, size_t m, float* d_runmax,
+                       double* d_leaf, float* d_pred_x, float* d_pred_y, void* stream);
+
+/* The largest number of keys of the sorted sample d_sorted[0..m) that fall
+ * into one range bin of the d_count[0] sorted, distinct splitters
+ * d_splitters, written to d_max_range[0]. */
+int pdq_sample_judge(const uint64_t* d_sorted, size_t m, const uint64_t* d_splitters, const uint32_t* d_count,
+                     uint64_t* d_max_range, void* stream);
+
 /* Workspace of pdq_bucket_histogram for n keys. */
 size_t pdq_bucket_workspace_bytes(size_t n);
 
@@ -124,15 +154,17 @@ typedef struct pdq_fit_buffers {
   float* d_pred;         /* [PDQ_LEARN_SAMPLE] float32 predictions after training */
   float* d_params;       /* [PDQ_MLP_PARAMS] trained parameters */
   float* d_losses;       /* [learn_steps] minibatch losses */
-  uint64_t* d_splitters; /* [PDQ_MAX_SPLITTERS] */
+  uint64_t* d_splitters; /* [PDQ_MAX_SPLITTERS] the chosen splitters */
   uint32_t* d_count;     /* [1] number of splitters */
-  uint64_t* d_info;      /* [4] as in pdq_learned_features */
+  uint64_t* d_info;      /* [8]: [0..2] as in pdq_learned_features; [3] the chosen candidate (0 the
+                            network, 1 its x-leaves, 2 its y-leaves); [4..6] the sample judge of each
+                            candidate; [7] 1 when the histogram would run (always here) */
 } pdq_fit_buffers;
 
 /* Workspace of pdq_learned_fit with these options (learn_* fields). */
 size_t pdq_learned_fit_workspace_bytes(const pdq_options* opt);
 
-/* Steps 1-4 on d_keys[0..n) (n >= 1) with opt's seed and learn_* fields:
+/* Steps 1-5 on d_keys[0..n) (n >= 1) with opt's seed and learn_* fields:
  * the whole fit that PDQ_LEARNED runs before its histogram, queued on
  * `stream` without a synchronisation. */
 int pdq_learned_fit(const void* d_keys, size_t n, pdq_key_type key_type, void* d_ws, size_t ws_bytes,

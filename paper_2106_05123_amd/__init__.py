@@ -26,8 +26,8 @@ __all__ = [
     "PdqError", "Options", "Stats", "lib", "workspace_bytes", "sort_", "sort_pairs_",
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
-    "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
-    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES",
+    "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "learned_leaves", "sample_judge", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
+    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ LIB_PATH = os.path.join(_HERE, "libpdq.so")
 
 PDQ_OK = 0
 PDQ_ERR_SCRATCH = -5
+PDQ_ERR_DEVICE = -6
 NOALLOC_SCRATCH_BYTES = 64 << 20  # PDQ_NOALLOC_SCRATCH_BYTES
 FLAG_VALIDATE = 1
 FLAG_PROFILE = 2
@@ -42,6 +43,7 @@ FLAG_LEARNED = 4
 FLAG_BATCHED = 8
 FLAG_AUTOTUNE = 16
 FLAG_DETERMINISTIC = 32
+FLAG_FRESH_FIXED = 64
 # batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
 BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
@@ -103,10 +105,17 @@ class Stats(ctypes.Structure):
         ("batch_items", ctypes.c_uint32),
         ("batch_shape", ctypes.c_uint32),
         ("batch_ms", ctypes.c_double),
+        ("near_sorted", ctypes.c_uint32),
+        ("pad_", ctypes.c_uint32),
+        ("near_sorted_runs", ctypes.c_uint64),
+        ("near_sorted_outliers", ctypes.c_uint64),
+        ("learned_choice", ctypes.c_uint32),
+        ("pad2_", ctypes.c_uint32),
+        ("learned_sample_judge", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "struct_size"}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "pad_", "pad2_")}
 
 
 class FitBuffers(ctypes.Structure):
@@ -146,6 +155,8 @@ def lib():
         L.pdq_sort_noalloc.argtypes = [vp, u32p, sz, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(Options),
                                        ctypes.POINTER(Stats)]
         L.pdq_sort_noalloc.restype = ctypes.c_int
+        L.pdq_check.argtypes = [vp, vp]
+        L.pdq_check.restype = ctypes.c_int
         L.pdq_status_string.argtypes = [ctypes.c_int]
         L.pdq_status_string.restype = ctypes.c_char_p
         L.pdq_last_hip_error.argtypes = []
@@ -160,6 +171,10 @@ def lib():
         L.pdq_mlp_train.argtypes = [vp, vp, sz, u64, u32, u32, u32, i, vp, vp, vp, vp, sz, vp]
         L.pdq_learned_features.argtypes = [vp, sz, vp, vp, vp, vp]
         L.pdq_learned_extract.argtypes = [vp, vp, sz, vp, vp, vp, vp]
+        L.pdq_learned_leaves.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, vp]
+        L.pdq_learned_leaves.restype = ctypes.c_int
+        L.pdq_sample_judge.argtypes = [vp, sz, vp, vp, vp, vp]
+        L.pdq_sample_judge.restype = ctypes.c_int
         L.pdq_bucket_workspace_bytes.argtypes = [sz]
         L.pdq_bucket_workspace_bytes.restype = sz
         L.pdq_bucket_histogram.argtypes = [vp, sz, i, vp, vp, vp, vp, sz, vp]
@@ -192,6 +207,14 @@ def abi_version() -> int:
 def _check(status: int):
     if status != PDQ_OK:
         raise PdqError(status, status_string(status), lib().pdq_last_hip_error())
+
+
+def check(workspace):
+    """pdq_check: wait for the current stream and raise if the last call that
+    used this workspace (tensor) found a device-side error."""
+    import torch
+    _check(lib().pdq_check(ctypes.c_void_p(workspace.data_ptr()),
+                           ctypes.c_void_p(torch.cuda.current_stream(workspace.device).cuda_stream)))
 
 
 def _key_type(t) -> int:
@@ -248,14 +271,18 @@ def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_
 
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
           workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
-          learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False):
+          learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False,
+          fresh_fixed: bool = False):
     """Sort a 1-D device tensor in place (ascending canonical order).
     learned=True runs the learned multiway first pass (see pdq_learned.h);
-    deterministic=True selects the look-back partition (PDQ_DETERMINISTIC)."""
+    deterministic=True selects the look-back partition (PDQ_DETERMINISTIC);
+    fresh_fixed=True takes fresh pivot candidates at fixed offsets after a
+    bad partition (PDQ_FRESH_FIXED) instead of hashed positions."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
-                                         (FLAG_DETERMINISTIC if deterministic else 0), workspace, learn)
+                                         (FLAG_DETERMINISTIC if deterministic else 0) |
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
                         need, stream, ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
@@ -266,12 +293,13 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
 def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
                 imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
-                deterministic: bool = False):
+                deterministic: bool = False, fresh_fixed: bool = False):
     """Sort keys in place and move the uint32 payload `vals` with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
-                                         (FLAG_DETERMINISTIC if deterministic else 0), workspace, learn)
+                                         (FLAG_DETERMINISTIC if deterministic else 0) |
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace, learn)
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),
                               kt, 0, ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
@@ -283,7 +311,7 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
 def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: int = 0,
                     validate: bool = False, profile: bool = False, stats: bool = False, workspace=None,
                     batched: bool = False, batch_shape: int = 0, batch_passes: int | None = None,
-                    deterministic: bool = False):
+                    deterministic: bool = False, fresh_fixed: bool = False):
     """Sort each segment [offsets[s], offsets[s+1]) of keys in place.
     offsets: uint64 device tensor of nseg+1 entries. batched=True runs the
     batched form (batch_shape 1..4 forces a shape, batch_passes the number of
@@ -293,7 +321,7 @@ def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: i
         raise ValueError("offsets must be a contiguous uint64 device tensor")
     nseg = offsets.numel() - 1
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0) \
-        | (FLAG_DETERMINISTIC if deterministic else 0)
+        | (FLAG_DETERMINISTIC if deterministic else 0) | (FLAG_FRESH_FIXED if fresh_fixed else 0)
     kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace,
                                          dict(batch_shape=batch_shape, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
@@ -395,6 +423,35 @@ def learned_extract(sorted_images, pred):
     return sp[:u].clone(), r
 
 
+def learned_leaves(x, t, pred):
+    """Second stage of the splitter model: (x-leaf, y-leaf) float32
+    predictions of the sorted sample's features x, targets t and clamped
+    network predictions pred."""
+    import torch
+    m = x.numel()
+    r = torch.empty_like(x)
+    px = torch.empty_like(x)
+    py = torch.empty_like(x)
+    leaf = torch.empty(2 * 64 * 2, dtype=torch.float64, device=x.device)
+    _check(lib().pdq_learned_leaves(_ptr(x), _ptr(t), _ptr(pred), m, _ptr(r), _ptr(leaf), _ptr(px), _ptr(py),
+                                    _stream(x)))
+    return px, py
+
+
+def sample_judge(sorted_images, splitters):
+    """Largest number of sorted sample keys in one range bin of splitters."""
+    import torch
+    dev = sorted_images.device
+    u = splitters.numel()
+    sp = torch.zeros(MAX_SPLITTERS, dtype=torch.uint64, device=dev)
+    sp[:u] = splitters
+    cnt = torch.tensor([u], dtype=torch.uint32, device=dev)
+    out = torch.zeros(1, dtype=torch.uint64, device=dev)
+    _check(lib().pdq_sample_judge(_ptr(sorted_images), sorted_images.numel(), _ptr(sp), _ptr(cnt), _ptr(out),
+                                  _stream(sorted_images)))
+    return int(out.cpu().item())
+
+
 def bucket_histogram(keys, splitters):
     """Keys per bin (2u + 1 bins) for sorted, distinct uint64 splitter images."""
     import torch
@@ -416,7 +473,7 @@ def learned_fit(keys, *, seed: int = 0, learn_steps: int = 0, learn_batch: int =
     import torch
     dev = keys.device
     opt = _options(-1, 0, 0, seed=seed, learn_steps=learn_steps, learn_batch=learn_batch, learn_grid=learn_grid)
-    steps = learn_steps or 256
+    steps = learn_steps or 128
     m = LEARN_SAMPLE
     out = dict(sample=torch.empty(m, dtype=torch.uint64, device=dev),
                x=torch.empty(m, dtype=torch.float32, device=dev),
@@ -426,7 +483,7 @@ def learned_fit(keys, *, seed: int = 0, learn_steps: int = 0, learn_batch: int =
                losses=torch.empty(steps, dtype=torch.float32, device=dev),
                splitters=torch.zeros(MAX_SPLITTERS, dtype=torch.uint64, device=dev),
                count=torch.zeros(1, dtype=torch.uint32, device=dev),
-               info=torch.zeros(4, dtype=torch.uint64, device=dev))
+               info=torch.zeros(8, dtype=torch.uint64, device=dev))
     fb = FitBuffers(*[_ptr(out[k]) for k in ("sample", "x", "t", "pred", "params", "losses", "splitters",
                                              "count", "info")])
     need = int(lib().pdq_learned_fit_workspace_bytes(ctypes.byref(opt)))
@@ -436,6 +493,18 @@ def learned_fit(keys, *, seed: int = 0, learn_steps: int = 0, learn_batch: int =
     u = int(out["count"].cpu().item())
     out["splitters"] = out["splitters"][:u]
     return out
+
+
+_live_plans = None
+
+
+def _destroy_live_plans():
+    """atexit: destroy every plan still alive while the HIP runtime is still
+    up (a graph destroyed from __del__ during interpreter teardown could run
+    after the runtime's own exit handlers)."""
+    if _live_plans is not None:
+        for p in list(_live_plans):
+            p.destroy()
 
 
 class Plan:
@@ -456,10 +525,21 @@ class Plan:
         self._h = ctypes.c_void_p()
         _check(lib().pdq_plan_create(ctypes.byref(self._h), _ptr(keys), _ptr(vals), keys.numel(), _ptr(offsets),
                                      nseg, kt, _ptr(ws), need, stream, ctypes.byref(opt)))
+        global _live_plans
+        if _live_plans is None:
+            import atexit
+            import weakref
+            _live_plans = weakref.WeakSet()
+            atexit.register(_destroy_live_plans)
+        _live_plans.add(self)
 
     def launch(self):
         import torch
         _check(lib().pdq_plan_launch(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def check(self):
+        """Raise if the last launch found a device-side error (waits for the stream)."""
+        check(self._keep[3])
 
     def info(self):
         shape = ctypes.c_uint32()

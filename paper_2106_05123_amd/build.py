@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpdq.so")
-SOURCES = ["pdq_api.hip", "k_pass.hip", "k_partition.hip", "k_partition_lb.hip", "k_base.hip", "k_learn.hip", "k_bucket.hip", "k_batch.hip"]
+SOURCES = ["pdq_api.hip", "k_pass.hip", "k_partition.hip", "k_partition_lb.hip", "k_base.hip", "k_learn.hip", "k_bucket.hip", "k_batch.hip", "k_runs.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

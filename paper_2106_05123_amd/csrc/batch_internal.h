@@ -70,6 +70,8 @@ struct BatchArgs {
 hipError_t launch_batch_zero(const BatchArgs& b, uint32_t cap, hipStream_t s);
 hipError_t launch_batch_from_list(const Ctx& c, const BatchArgs& b, int parity, uint32_t src, hipStream_t s);
 hipError_t launch_batch(const Ctx& c, const BatchArgs& b, int tail, uint32_t grid, hipStream_t s);
+// ORs the queue's error bits into the counter block (after launch_batch).
+hipError_t launch_batch_fold(const Ctx& c, const BatchArgs& b, hipStream_t s);
 // Workgroups of the persistent kernel of this tail shape that fit on the
 // device at once.
 uint32_t batch_grid(const Ctx& c, int tail);

@@ -111,6 +111,16 @@ __global__ void k_batch_zero(BatchArgs b, uint32_t cap) {
   }
 }
 
+// After the persistent launch: the queue's error bits join the counter
+// block's, so that one word tells the caller about every device-side error
+// of the call (pdq_check reads it).
+__global__ void k_batch_fold(Ctx c, BatchArgs b) {
+  if (threadIdx.x == 0) {
+    const uint32_t e = b.q->error;
+    if (e) atomicOr(&c.ctr->errors, e);
+  }
+}
+
 // The segments still live after the captured partition passes (list
 // `parity`, keys in buffer `src`) become the queue's first items, with the
 // budget and flags their bookkeeping gave them.
@@ -431,10 +441,12 @@ __global__ __launch_bounds__(NT) void k_batch(Ctx c, BatchArgs bq) {
       __syncthreads();
     } else {
       if (tid == 0) {
-        // the predecessor (an ancestor's pivot) was published with a coherent store
+        // the candidates (written by the partition that made this segment)
+        // and the predecessor (an ancestor's pivot, published with a coherent
+        // store) may come from another XCD in this launch: coherent loads
         const T* user = static_cast<const T*>(c.keys[0]);
-        const PivotChoice<K> pc = choose_pivot<K>(static_cast<const T*>(c.keys[it.buf]), user, b, e, it.flags,
-                                                  c.seed);
+        const PivotChoice<K> pc = choose_pivot<K, true>(static_cast<const T*>(c.keys[it.buf]), user, b, e,
+                                                        it.flags, c.seed, c.fresh_fixed != 0);
         s_pivot = pc.raw;
         s_pidx = pc.pidx;
         s_mode = pc.mode;
@@ -546,6 +558,11 @@ const void* kernel_for(const Ctx& c, int shape) {
 
 hipError_t launch_batch_zero(const BatchArgs& b, uint32_t cap, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_zero, dim3((cap + 255) / 256), dim3(256), 0, s, b, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_fold(const Ctx& c, const BatchArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_fold, dim3(1), dim3(64), 0, s, c, b);
   return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ __device__ uint32_t block_exclusive_scan_512(uint32_t* s, uint32_t* s_wsum) {
 
 template <class K>
 __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ keys, uint64_t n, BucketBufs b) {
+  if (b.go && *b.go == 0) return;  // the fit's sample judge already failed: nothing to count
   using S = typename K::T;
   __shared__ SplitTable<S> s_sp;
   __shared__ uint32_t s_cnt[kBinStride];
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ 
 
 // Sum of each bin over the rows of one chunk.
 __global__ __launch_bounds__(kBinStride) void k_chunk_sum(BucketBufs b) {
+  if (b.go && *b.go == 0) return;  // the fit's sample judge already failed: nothing to count
   const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
   const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
   uint32_t sum = 0;
@@ -121,6 +123,7 @@ __global__ __launch_bounds__(kBinStride) void k_chunk_sum(BucketBufs b) {
 // One workgroup: chunk sums -> per-chunk exclusive offsets within each bin,
 // bin totals, and the start of every bin (exclusive scan over bins).
 __global__ __launch_bounds__(kBinStride) void k_chunk_scan(BucketBufs b) {
+  if (b.go && *b.go == 0) return;  // the fit's sample judge already failed: nothing to count
   __shared__ uint32_t s_tot[kBinStride];
   __shared__ uint32_t s_wsum[kBinStride / 64];
   const uint32_t tid = threadIdx.x;
@@ -146,6 +149,7 @@ __global__ __launch_bounds__(kBinStride) void k_chunk_scan(BucketBufs b) {
 
 // Rows of one chunk -> absolute start of each (tile, bin) run.
 __global__ __launch_bounds__(kBinStride) void k_tile_rescan(BucketBufs b) {
+  if (b.go && *b.go == 0) return;  // the fit's sample judge already failed: nothing to count
   const uint64_t r0 = static_cast<uint64_t>(blockIdx.x) * kScanRows;
   const uint64_t r1 = r0 + kScanRows < b.ntiles ? r0 + kScanRows : b.ntiles;
   uint32_t run = static_cast<uint32_t>(b.begin[threadIdx.x]) + b.chunk[static_cast<uint64_t>(blockIdx.x) * kBinStride + threadIdx.x];

@@ -92,14 +92,20 @@ __global__ __launch_bounds__(256) void k_rank_merge(const uint64_t* __restrict__
 
 // ---------------------------------------------------------------- features
 
-// L(v) = e + (v - 2^e) / 2^e with e = floor(log2 v); L(0) = -1. One rounding
-// in the integer-to-double conversion, an exact scaling, one rounding in the
-// addition.
+// L(v) = e + (4 f - f^2) / 3 with f = (v - 2^e) / 2^e in [0, 1) and
+// e = floor(log2 v); L(0) = -1. The polynomial has p(0) = 0, p(1) = 1 and
+// p'(1) = p'(0) / 2, so the slope of L is continuous across every power of
+// two. Correctly rounded operations in a fixed order (conversion, exact
+// scaling, f * f, 4 f - f * f, / 3, + e); contraction is off here, so no
+// multiply is fused into an add (the pragma acts on operators written in
+// its scope, not on inlined helpers, so the operators are written out).
 __device__ __forceinline__ double pseudo_log2(uint64_t v) {
+#pragma clang fp contract(off)
   if (v == 0) return -1.0;
   const int e = 63 - __clzll(static_cast<long long>(v));
-  const double d = static_cast<double>(v - (1ull << e));
-  return ldexp(d, -e) + static_cast<double>(e);
+  const double f = ldexp(static_cast<double>(v - (1ull << e)), -e);
+  const double q = 4.0 * f - f * f;
+  return q / 3.0 + static_cast<double>(e);
 }
 
 __global__ void k_zero_u64(uint64_t* p, uint32_t count) {
@@ -441,13 +447,23 @@ __global__ __launch_bounds__(kTrainThreads) void k_train(TrainArgs a) {
       chunk_grad(sm, cs, a.batch, a.residual, g);
     }
     // Gradient exchange. The partial rows are written and read with
-    // agent-scope atomic stores and loads, which are coherent across the
-    // chip without cache maintenance (release/acquire fences would write
-    // back and invalidate whole L2s every step). The workgroup barrier waits
-    // for every wave's stores to complete before lane 0 announces the
-    // workgroup; readers start loading only after seeing every workgroup.
+    // agent-scope atomic stores and loads, which are performed at the
+    // chip-wide coherence point (no copy of them stays in an XCD's L2), so
+    // no cache maintenance is needed (agent-scope release/acquire fences
+    // would write back and invalidate whole L2s every step: ~25 us a step).
+    // What the exchange needs is the order "every wave's row stores have
+    // completed, then lane 0 announces the workgroup". A workgroup barrier
+    // alone does not give it (it orders the waves, not the completion of
+    // their global stores), so every wave first waits until its own stores
+    // are acknowledged (s_waitcnt with all counters at zero: vmcnt counts
+    // outstanding stores too). Lane 0's increment is issued after the
+    // barrier, hence after every row store completed; a reader issues its
+    // row loads only after its spin has seen all `grid` increments of the
+    // step, and those loads read the coherence point, so they return the
+    // completed rows.
     float* rows = a.partials + static_cast<size_t>(step & 1u) * a.grid * kParamStride;
     write_grad_row(sm, rows + static_cast<size_t>(wg) * kParamStride, g, true);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (one_chunk && step < a.steps && tid < static_cast<int>(kTrainChunk)) fetch(step + 1, 0, local, nx, nt);
     if (tid == 0 && !failed) {
@@ -649,6 +665,164 @@ __global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __r
   }
 }
 
+// ---------------------------------------------------------------- leaves
+
+// Running maximum r of y[0..m) (one workgroup: per-lane block maxima, a scan
+// over the lanes, then each lane's block; a maximum is exact in any order).
+__global__ __launch_bounds__(kExtractThreads) void k_running_max(const float* __restrict__ y, uint64_t m,
+                                                                 float* __restrict__ r) {
+  __shared__ float s_max[kExtractThreads];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t per = (m + kExtractThreads - 1) / kExtractThreads;
+  const uint64_t b = tid * per < m ? tid * per : m;
+  const uint64_t e = b + per < m ? b + per : m;
+  float mx = 0.0f;
+  for (uint64_t i = b; i < e; ++i) mx = y[i] > mx ? y[i] : mx;
+  s_max[tid] = mx;
+  __syncthreads();
+  for (uint32_t d = 1; d < kExtractThreads; d <<= 1) {
+    const float o = tid >= d ? s_max[tid - d] : 0.0f;
+    __syncthreads();
+    s_max[tid] = o > s_max[tid] ? o : s_max[tid];
+    __syncthreads();
+  }
+  float run = tid > 0 ? s_max[tid - 1] : 0.0f;
+  for (uint64_t i = b; i < e; ++i) {
+    run = y[i] > run ? y[i] : run;
+    r[i] = run;
+  }
+}
+
+// One lane per (kind, leaf): kind 0 fits t = a + b x, kind 1 t = a + b y
+// (y the clamped prediction) over the samples of leaf j, those whose running
+// maximum r of y satisfies floor(64 r) == j (the last leaf also takes
+// r == 1). Sums run in index order in double: a float times a float is
+// exact in double, so only the additions round, as in the oracle.
+// Contraction is off: k * sum u^2 - (sum u)^2 fused into one rounding would
+// differ from the oracle's two, and this difference of two large sums is
+// where the rounding shows.
+__global__ __launch_bounds__(2 * kLeaves) void k_leaf_fit(const float* __restrict__ x, const float* __restrict__ t,
+                                                          const float* __restrict__ y, const float* __restrict__ r,
+                                                          uint64_t m, double* __restrict__ leaf) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x;
+  const int kind = lane / kLeaves, j = lane % kLeaves;
+  auto first_at_least = [&](float thr) {
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (r[mid] < thr) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  const uint64_t lo = first_at_least(static_cast<float>(j) / static_cast<float>(kLeaves));
+  const uint64_t hi = j == kLeaves - 1 ? m : first_at_least(static_cast<float>(j + 1) / static_cast<float>(kLeaves));
+  const float* u = kind == 0 ? x : y;
+  double sx = 0.0, st = 0.0, sxx = 0.0, sxt = 0.0;
+  for (uint64_t i = lo; i < hi; ++i) {
+    const double ui = static_cast<double>(u[i]), ti = static_cast<double>(t[i]);
+    sx = sx + ui;
+    st = st + ti;
+    sxx = sxx + ui * ui;
+    sxt = sxt + ui * ti;
+  }
+  const uint64_t cnt = hi > lo ? hi - lo : 0;
+  const double k = static_cast<double>(cnt);
+  const double den = k * sxx - sx * sx;
+  double a, b;
+  if (cnt < 2 || !(den > 0.0)) {
+    b = 0.0;
+    a = cnt ? st / k : 0.0;
+  } else {
+    b = (k * sxt - sx * st) / den;
+    a = (st - b * sx) / k;
+  }
+  leaf[(kind * kLeaves + j) * 2] = a;
+  leaf[(kind * kLeaves + j) * 2 + 1] = b;
+}
+
+// Leaf predictions of every sample: (float)(a + b u) of its leaf.
+__global__ __launch_bounds__(256) void k_leaf_eval(const float* __restrict__ x, const float* __restrict__ y,
+                                                   const float* __restrict__ r, uint64_t m,
+                                                   const double* __restrict__ leaf, float* __restrict__ yx,
+                                                   float* __restrict__ yy) {
+#pragma clang fp contract(off)
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x;
+  if (i >= m) return;
+  int j = static_cast<int>(r[i] * static_cast<float>(kLeaves));  // exact scaling, then floor (r >= 0)
+  j = j < kLeaves - 1 ? j : kLeaves - 1;
+  yx[i] = static_cast<float>(leaf[j * 2] + leaf[j * 2 + 1] * static_cast<double>(x[i]));
+  yy[i] = static_cast<float>(leaf[(kLeaves + j) * 2] + leaf[(kLeaves + j) * 2 + 1] * static_cast<double>(y[i]));
+}
+
+// ---------------------------------------------------------------- judge on the sample
+
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* s, uint64_t m, uint64_t v) {
+  uint64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (s[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t* s, uint64_t m, uint64_t v) {
+  uint64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (s[mid] <= v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroup c: the largest number of sorted sample keys in one range bin of
+// candidate c's splitters (range bin b holds the keys strictly between
+// splitters b - 1 and b).
+__global__ __launch_bounds__(256) void k_sample_judge(const uint64_t* __restrict__ s, uint64_t m,
+                                                      const uint64_t* __restrict__ sp, uint32_t stride,
+                                                      const uint32_t* __restrict__ count, uint64_t* est) {
+  __shared__ uint64_t s_max[256];
+  const uint32_t c = blockIdx.x, b = threadIdx.x;
+  const uint64_t* cs = sp + static_cast<uint64_t>(c) * stride;
+  const uint32_t u = count[c];
+  uint64_t v = 0;
+  if (b <= u) {
+    const uint64_t end = b < u ? lower_bound_u64(s, m, cs[b]) : m;
+    const uint64_t begin = b > 0 ? upper_bound_u64(s, m, cs[b - 1]) : 0;
+    v = end > begin ? end - begin : 0;
+  }
+  s_max[b] = v;
+  __syncthreads();
+  for (uint32_t d = 128; d > 0; d >>= 1) {
+    if (b < d) s_max[b] = s_max[b + d] > s_max[b] ? s_max[b + d] : s_max[b];
+    __syncthreads();
+  }
+  if (b == 0) est[c] = s_max[0];
+}
+
+// The candidate with the smallest sample judge (the first on ties) becomes
+// the fit's splitters; info[3] = its index, info[4 + c] = judge of c,
+// info[7] = 1 when the winner's judge is at most `go_limit` (the histogram
+// runs only then).
+__global__ __launch_bounds__(256) void k_pick(const uint64_t* __restrict__ sp, uint32_t stride,
+                                              const uint32_t* __restrict__ count, const uint64_t* __restrict__ est,
+                                              uint32_t ncand, uint64_t go_limit, uint64_t* out, uint32_t* out_count,
+                                              uint64_t* info) {
+  uint32_t best = 0;
+  for (uint32_t c = 1; c < ncand; ++c)
+    if (est[c] < est[best]) best = c;
+  const uint32_t u = count[best];
+  for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) out[i] = sp[static_cast<uint64_t>(best) * stride + i];
+  if (threadIdx.x == 0) {
+    *out_count = u;
+    info[3] = best;
+    for (uint32_t c = 0; c < ncand; ++c) info[4 + c] = est[c];
+    info[7] = est[best] <= go_limit ? 1u : 0u;
+  }
+}
+
 template <class K>
 struct SampleL {
   static hipError_t run(const void* keys, uint64_t n, uint64_t m, uint64_t seed, uint64_t* out, hipStream_t s) {
@@ -713,6 +887,37 @@ hipError_t launch_infer(const float* params, const float* x, uint64_t m, uint32_
 hipError_t launch_extract(const uint64_t* sorted, const float* y, uint64_t m, float* runmax, uint64_t* splitters,
                           uint32_t* count, hipStream_t s) {
   hipLaunchKernelGGL(k_extract, dim3(1), dim3(kExtractThreads), 0, s, sorted, y, m, runmax, splitters, count);
+  return hipGetLastError();
+}
+
+}  // namespace pdq
+
+namespace pdq {
+
+hipError_t launch_running_max(const float* y, uint64_t m, float* runmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_running_max, dim3(1), dim3(kExtractThreads), 0, s, y, m, runmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaves(const float* x, const float* t, const float* y, const float* runmax, uint64_t m,
+                         double* leaf, float* yx, float* yy, hipStream_t s) {
+  hipLaunchKernelGGL(k_leaf_fit, dim3(1), dim3(2 * kLeaves), 0, s, x, t, y, runmax, m, leaf);
+  hipLaunchKernelGGL(k_leaf_eval, dim3(static_cast<uint32_t>((m + 255) / 256)), dim3(256), 0, s, x, y, runmax, m,
+                     leaf, yx, yy);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_judge(const uint64_t* sorted, uint64_t m, const uint64_t* splitters, uint32_t stride,
+                               const uint32_t* count, uint32_t ncand, uint64_t* est, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_judge, dim3(ncand), dim3(256), 0, s, sorted, m, splitters, stride, count, est);
+  return hipGetLastError();
+}
+
+hipError_t launch_pick(const uint64_t* splitters, uint32_t stride, const uint32_t* count, const uint64_t* est,
+                       uint32_t ncand, uint64_t go_limit, uint64_t* out, uint32_t* out_count, uint64_t* info,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pick, dim3(1), dim3(256), 0, s, splitters, stride, count, est, ncand, go_limit, out, out_count,
+                     info);
   return hipGetLastError();
 }
 

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
     Seg* sp = &c.segs[parity][i];
     const PivotChoice<K> pc = choose_pivot<K>(static_cast<const T*>(c.keys[src]), static_cast<const T*>(c.keys[0]),
-                                              sp->begin, sp->end, sp->flags, c.seed);
+                                              sp->begin, sp->end, sp->flags, c.seed, c.fresh_fixed != 0);
     sp->pivot = static_cast<uint64_t>(pc.raw);
     sp->pidx = pc.pidx;
     sp->mode = pc.mode;

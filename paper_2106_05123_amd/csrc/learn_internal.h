@@ -26,6 +26,9 @@ constexpr uint32_t kTrainChunk = 64;             // samples a training workgroup
 constexpr uint32_t kBucketTile = 8192;           // keys per histogram / scatter tile
 constexpr uint32_t kBucketThreads = 512;
 constexpr uint32_t kScanRows = 256;              // tile rows per scan chunk
+constexpr int kLeaves = 64;                      // leaves of the model's second stage
+constexpr int kCandidates = 3;                   // splitter candidates: root, x-leaves, y-leaves
+constexpr int kInfoWords = 8;                    // words of the fit's info array
 
 struct TrainArgs {
   const float* x;         // features of the sorted sample [m]
@@ -54,9 +57,17 @@ struct FitBufs {
   float* losses;      // [steps]
   float* partials;    // [2][grid][kParamStride]
   uint32_t* sync;     // [4]
-  uint64_t* info;     // [4]: dev_log bits, dev_lin bits, use_log, reserved
-  uint64_t* splitters;  // [256]
+  uint64_t* info;     // [kInfoWords]: dev_log bits, dev_lin bits, use_log, chosen candidate,
+                      // sample judge of each candidate (3), histogram go flag
+  uint64_t* splitters;  // [256] the chosen candidate's splitters
   uint32_t* count;    // [1]
+  // second stage and candidates
+  float* yx;          // [m] x-leaf predictions
+  float* yy;          // [m] y-leaf predictions
+  double* leaf;       // [2][kLeaves][2] intercept and slope of every leaf
+  uint64_t* cand;     // [kCandidates][256] splitters of each candidate
+  uint32_t* cand_count;  // [kCandidates]
+  uint64_t* est;      // [kCandidates] sample judge of each candidate
 };
 
 struct BucketBufs {
@@ -70,6 +81,7 @@ struct BucketBufs {
   uint64_t nchunks;
   uint32_t* errors;        // scatter: bit kErrScatter when a position falls outside [0, n)
   uint32_t* order;         // order scan: bit 0 some adjacent pair descends, bit 1 some pair ascends
+  const uint64_t* go;      // null, or a word that is 0 when the histogram is not wanted
 };
 
 constexpr uint32_t kErrScatter = 8u;
@@ -87,6 +99,20 @@ hipError_t launch_gradient(const float* params, const float* x, const float* t, 
                            float* grad, float* loss, hipStream_t s);
 hipError_t launch_extract(const uint64_t* sorted, const float* y, uint64_t m, float* runmax, uint64_t* splitters,
                           uint32_t* count, hipStream_t s);
+
+// Running maximum of y[0..m) (clamped predictions), as the extraction computes it.
+hipError_t launch_running_max(const float* y, uint64_t m, float* runmax, hipStream_t s);
+// Second stage: leaf fits on the running maximum of y, then both leaf
+// predictions of every sample.
+hipError_t launch_leaves(const float* x, const float* t, const float* y, const float* runmax, uint64_t m,
+                         double* leaf, float* yx, float* yy, hipStream_t s);
+// est[c] = largest sample count in a range bin of candidate c (ncand
+// candidates, splitters `stride` apart).
+hipError_t launch_sample_judge(const uint64_t* sorted, uint64_t m, const uint64_t* splitters, uint32_t stride,
+                               const uint32_t* count, uint32_t ncand, uint64_t* est, hipStream_t s);
+hipError_t launch_pick(const uint64_t* splitters, uint32_t stride, const uint32_t* count, const uint64_t* est,
+                       uint32_t ncand, uint64_t go_limit, uint64_t* out, uint32_t* out_count, uint64_t* info,
+                       hipStream_t s);
 
 // k_bucket.hip
 // bit 0 of *flags: some adjacent pair of keys[0..n) descends; bit 1: some pair ascends.

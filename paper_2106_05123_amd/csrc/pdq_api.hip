@@ -33,6 +33,7 @@
 #include "pdq.h"
 #include "pdq_learned.h"
 #include "pdq_internal.h"
+#include "runs_internal.h"
 
 namespace {
 
@@ -75,6 +76,8 @@ struct Layout {
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
   size_t fit_out = 0, fit_scratch = 0, bucket = 0;
+  // near-sorted path of single-range sorts (zero when not used)
+  size_t runs = 0;
   // batched segmented sort: queue words, ring items, ring slot states, and
   // (autotuning only) a copy of the input
   size_t bq = 0, bitems = 0, bstate = 0, backup_keys = 0, backup_vals = 0;
@@ -109,15 +112,15 @@ FitOutLayout fit_out_layout(uint32_t steps) {
   f.losses = b.take(static_cast<size_t>(steps) * 4);
   f.splitters = b.take(256 * 8);
   f.count = b.take(4);
-  f.info = b.take(4 * 8);
+  f.info = b.take(kInfoWords * 8);
   f.total = b.off;
   return f;
 }
 
-// Scratch of the fit: running maximum, gradient partials, barrier words, and
-// the unsorted sample.
+// Scratch of the fit: running maximum, gradient partials, barrier words,
+// the unsorted sample, and the second stage with its candidates.
 struct FitScratchLayout {
-  size_t runmax, partials, sync, raw, total;
+  size_t runmax, partials, sync, raw, yx, yy, leaf, cand, cand_count, est, total;
 };
 FitScratchLayout fit_scratch_layout(uint32_t grid) {
   FitScratchLayout f;
@@ -126,6 +129,12 @@ FitScratchLayout fit_scratch_layout(uint32_t grid) {
   f.partials = b.take(2ull * grid * kParamStride * 4);
   f.sync = b.take(4 * 4);
   f.raw = b.take(kLearnSample * 8);
+  f.yx = b.take(kLearnSample * 4);
+  f.yy = b.take(kLearnSample * 4);
+  f.leaf = b.take(2ull * kLeaves * 2 * 8);
+  f.cand = b.take(static_cast<size_t>(kCandidates) * 256 * 8);
+  f.cand_count = b.take(kCandidates * 4);
+  f.est = b.take(kCandidates * 8);
   f.total = b.off;
   return f;
 }
@@ -145,6 +154,31 @@ BucketLayout bucket_layout(size_t n) {
   L.total = b.off;
   return L;
 }
+
+// Descent log, plan, gather list, outlier buffer and merge splits of the
+// near-sorted path.
+struct RunsLayout {
+  size_t count, pos, plan, shorts, item, okeys, ovals, splits, total;
+};
+RunsLayout runs_layout(size_t n) {
+  RunsLayout r;
+  Bump b;
+  r.count = b.take(4);
+  r.pos = b.take(4ull * kRunMaxDescents);
+  r.plan = b.take(sizeof(RunPlan));
+  r.shorts = b.take(sizeof(RunSpan) * (kRunMaxDescents + 1ull));
+  r.item = b.take(sizeof(Item));
+  r.okeys = b.take(8ull * kRunMaxOutliers);
+  r.ovals = b.take(4ull * kRunMaxOutliers);
+  r.splits = b.take(8ull * (n / kRunMergeTile + 2));
+  r.total = b.off;
+  return r;
+}
+
+// Single-range sorts of at least kRunMinKeys keys try the near-sorted path
+// (a call with one segment reserves its area too, whatever its flags, so
+// that pdq_workspace_bytes and the call agree).
+bool uses_runs(size_t n, size_t nseg) { return nseg == 1 && n >= kRunMinKeys; }
 
 // Widest LDS class of the batched form: 16384 keys, 8192 for 64-bit keys
 // with a payload (12 LDS bytes a slot).
@@ -170,6 +204,8 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
     items = nseg + 2ull * kMaxBatchPasses * (n / (batch_base_max(kt, vals) + 1) + 2);
   }
   L.max_items = static_cast<uint32_t>(items + 64);
+  // the counter block comes first, so pdq_check finds it from d_ws alone
+  L.ctr = take(sizeof(Counters));
   L.scratch_keys = take(n * key_bytes(kt));
   L.scratch_vals = take(vals ? n * 4 : 0);
   L.segs0 = take(sizeof(Seg) * L.max_active);
@@ -181,7 +217,6 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
   for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
   L.heap = take(sizeof(Item) * L.max_items);
   L.copy = take(sizeof(Item) * L.max_items);
-  L.ctr = take(sizeof(Counters));
   L.total = off + kAlign;  // room to align the caller's base pointer
   return L;
 }
@@ -194,9 +229,11 @@ uint32_t batch_capacity(size_t n) { return static_cast<uint32_t>(n / (kBaseMax +
 Layout make_layout_opts(size_t n, size_t nseg, uint32_t kt, bool vals, bool learned, uint32_t steps, uint32_t grid,
                         bool batched = false, bool tune = false) {
   Layout L = make_layout(n, nseg, kt, vals, batched);
-  if (!learned && !batched) return L;
+  const bool runs = uses_runs(n, nseg);
+  if (!learned && !batched && !runs) return L;
   Bump b;
   b.off = L.total - kAlign;
+  if (runs) L.runs = b.take(runs_layout(n).total);
   if (learned) {
     L.fit_out = b.take(fit_out_layout(steps).total);
     L.fit_scratch = b.take(fit_scratch_layout(grid).total);
@@ -224,7 +261,7 @@ struct Opts {
   uint32_t tile = 0;
   uint64_t seed = 0;
   float limit = 2.0f;
-  uint32_t steps = 256;
+  uint32_t steps = 128;
   uint32_t batch = 1024;
   uint32_t grid = 16;
   uint32_t batch_shape = 0;  // 0 = tuned or default, else shape index + 1
@@ -250,7 +287,7 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, batch_passes) + sizeof(uint32_t)) out->batch_passes = o->batch_passes;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
-                             PDQ_DETERMINISTIC))
+                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->batch_passes > kMaxBatchPasses + 1) return PDQ_ERR_UNSUPPORTED;
@@ -280,10 +317,7 @@ int read_counters(const Ctx& c, Counters* snap, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (snap->errors & kErrCapacity) return PDQ_ERR_INVALID;  // only bad offsets can overfill a list
-  if (snap->errors) {
-    g_last_hip = 0;
-    return PDQ_ERR_HIP;
-  }
+  if (snap->errors) return PDQ_ERR_DEVICE;
   const uint32_t nact0 = static_cast<uint32_t>(snap->list[0] >> 32), nact1 = static_cast<uint32_t>(snap->list[1] >> 32);
   if (nact0 > c.max_active || nact1 > c.max_active || static_cast<uint32_t>(snap->list[0]) > c.max_tiles ||
       static_cast<uint32_t>(snap->list[1]) > c.max_tiles || snap->nheap > c.max_items || snap->ncopy > c.max_items)
@@ -325,12 +359,22 @@ FitBufs fit_bufs(char* out, char* scratch, uint32_t steps, uint32_t grid) {
   f.partials = reinterpret_cast<float*>(scratch + fs.partials);
   f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
   f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  f.yx = reinterpret_cast<float*>(scratch + fs.yx);
+  f.yy = reinterpret_cast<float*>(scratch + fs.yy);
+  f.leaf = reinterpret_cast<double*>(scratch + fs.leaf);
+  f.cand = reinterpret_cast<uint64_t*>(scratch + fs.cand);
+  f.cand_count = reinterpret_cast<uint32_t*>(scratch + fs.cand_count);
+  f.est = reinterpret_cast<uint64_t*>(scratch + fs.est);
   return f;
 }
 
-// Sample, sample sort, features, training, inference, splitters, all queued
-// on the stream without a synchronisation.
-int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s) {
+// Sample, sample sort, features, training, inference, the second stage,
+// three candidate splitter sets judged on the sample and the best one kept,
+// all queued on the stream without a synchronisation. info[7] says whether
+// the winner's sample judge is within `go_limit` sample keys (the histogram
+// kernels run only then).
+int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s,
+            uint64_t go_limit = ~0ull) {
   const uint64_t m = kLearnSample;
   HIP_TRY(launch_sample(kt, keys, n, m, o.seed, f.raw, s));
   HIP_TRY(launch_sample_sort(f.raw, m, f.sample, s));
@@ -351,7 +395,13 @@ int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitB
   a.sync = f.sync;
   HIP_TRY(launch_train(a, s));
   HIP_TRY(launch_infer(f.params, f.x, m, 1u, f.y, s));
-  HIP_TRY(launch_extract(f.sample, f.y, m, f.runmax, f.splitters, f.count, s));
+  // candidate 0 (the network) first: its running maximum defines the leaves
+  HIP_TRY(launch_extract(f.sample, f.y, m, f.runmax, f.cand, f.cand_count, s));
+  HIP_TRY(launch_leaves(f.x, f.t, f.y, f.runmax, m, f.leaf, f.yx, f.yy, s));
+  HIP_TRY(launch_extract(f.sample, f.yx, m, f.runmax, f.cand + 256, f.cand_count + 1, s));
+  HIP_TRY(launch_extract(f.sample, f.yy, m, f.runmax, f.cand + 512, f.cand_count + 2, s));
+  HIP_TRY(launch_sample_judge(f.sample, m, f.cand, 256, f.cand_count, kCandidates, f.est, s));
+  HIP_TRY(launch_pick(f.cand, 256, f.cand_count, f.est, kCandidates, go_limit, f.splitters, f.count, f.info, s));
   return PDQ_OK;
 }
 
@@ -368,6 +418,7 @@ BucketBufs bucket_bufs(char* area, uint64_t n, const uint64_t* splitters, const 
   b.nchunks = bucket_chunks(n);
   b.errors = nullptr;
   b.order = reinterpret_cast<uint32_t*>(area + L.order);
+  b.go = nullptr;
   return b;
 }
 
@@ -388,7 +439,8 @@ struct EventPair {
 // What the learned first pass found, for the statistics.
 struct LearnedResult {
   uint32_t state = 0;  // 0 not run, 1 used, 2 fell back
-  uint32_t splitters = 0, use_log = 0, ordered = 0;
+  uint32_t splitters = 0, use_log = 0, ordered = 0, choice = 0;
+  uint64_t sample_judge = 0;
   uint64_t max_range = 0, equal = 0;
   float loss = 0.0f;
   double fit_ms = 0, hist_ms = 0, scatter_ms = 0;
@@ -421,7 +473,14 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
     }
   }
   if (prof) HIP_TRY(hipEventRecord(e_fit.a, s));
-  int rc = run_fit(c.keys[0], n, kt, o, f, s);
+  // the histogram runs only when the chosen splitters' sample judge is
+  // within the limit with a 15 % margin for sampling error (the sample
+  // holds m keys: a range bin at the limit holds limit * m / 256 of them)
+  const double lim = o.limit >= 0.0f ? 1.15 * static_cast<double>(o.limit) * static_cast<double>(kLearnSample) / 256.0
+                                     : -1.0;
+  const uint64_t go_limit = lim >= 0.0 ? static_cast<uint64_t>(lim) : 0ull;
+  b.go = f.info + 7;
+  int rc = run_fit(c.keys[0], n, kt, o, f, s, go_limit);
   if (rc != PDQ_OK) return rc;
   if (prof) {
     HIP_TRY(hipEventRecord(e_fit.b, s));
@@ -433,7 +492,7 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   // judge on the host: bin totals, splitter count, trainer flag, last loss
   uint64_t totals[kBinStride];
   uint32_t count = 0, sync[2] = {0, 0};
-  uint64_t info[4] = {0, 0, 0, 0};
+  uint64_t info[kInfoWords] = {};
   float loss = 0.0f;
   HIP_TRY(hipMemcpyAsync(totals, b.totals, sizeof(totals), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&count, f.count, 4, hipMemcpyDeviceToHost, s));
@@ -444,6 +503,14 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   res.splitters = count;
   res.use_log = static_cast<uint32_t>(info[2]);
   res.loss = loss;
+  res.choice = static_cast<uint32_t>(info[3]);
+  res.sample_judge = info[4 + (info[3] < kCandidates ? info[3] : 0)];
+  if (info[7] == 0) {
+    // the sample judge rejected every candidate: the histogram did not run
+    res.state = 2;
+    if (prof) res.fit_ms = e_fit.ms();
+    return PDQ_OK;
+  }
   uint64_t max_range = 0, equal = 0;
   for (uint32_t i = 0; i <= 2 * count && i < static_cast<uint32_t>(kBinStride); ++i) {
     if (i & 1u) equal += totals[i];
@@ -509,7 +576,55 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.base_max = kBaseMax;
   c.wide_e = 16;
   c.lookback = (o.flags & PDQ_DETERMINISTIC) ? 1u : 0u;
+  c.fresh_fixed = (o.flags & PDQ_FRESH_FIXED) ? 1u : 0u;
   return c;
+}
+
+// ---- near-sorted inputs -------------------------------------------------------
+
+RunBufs run_bufs(const Layout& L, char* base, size_t n) {
+  const RunsLayout r = runs_layout(n);
+  char* a = base + L.runs;
+  RunBufs rb;
+  rb.count = reinterpret_cast<uint32_t*>(a + r.count);
+  rb.pos = reinterpret_cast<uint32_t*>(a + r.pos);
+  rb.plan = reinterpret_cast<RunPlan*>(a + r.plan);
+  rb.shorts = reinterpret_cast<RunSpan*>(a + r.shorts);
+  rb.item = reinterpret_cast<Item*>(a + r.item);
+  rb.okeys = a + r.okeys;
+  rb.ovals = reinterpret_cast<uint32_t*>(a + r.ovals);
+  rb.splits = reinterpret_cast<uint64_t*>(a + r.splits);
+  return rb;
+}
+
+// The GPU form of Section 5.2's partial insertion sort (k_runs.hip): one
+// scan finds the runs; a range that is already sorted, one long run plus a
+// few outliers, or two long runs is finished here by a merge and
+// plan->state says so; otherwise (state kRunUnsorted) the partition passes
+// sort it.
+int run_near_sorted(const Ctx& c, const Layout& L, char* base, RunPlan* plan, hipStream_t s) {
+  const RunBufs rb = run_bufs(L, base, c.n);
+  HIP_TRY(launch_run_scan(c, rb, s));
+  HIP_TRY(hipMemcpyAsync(plan, rb.plan, sizeof(RunPlan), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (plan->state == kRunOutliers) {
+    HIP_TRY(launch_run_gather(c, rb, plan->nshort, s));
+    if (plan->outliers > 1) {
+      // the LDS base case sorts the outlier buffer in place, as one item
+      Ctx o = c;
+      o.keys[0] = o.keys[1] = rb.okeys;
+      o.vals[0] = o.vals[1] = c.has_vals ? rb.ovals : nullptr;
+      const int cls = base_class(plan->outliers);
+      o.base[cls] = rb.item;
+      o.device_counts = 0;
+      o.max_items = 1;
+      HIP_TRY(launch_base(o, cls, 1, s));
+    }
+    HIP_TRY(launch_run_merge(c, rb, *plan, s));
+  } else if (plan->state == kRunTwoRuns) {
+    HIP_TRY(launch_run_merge(c, rb, *plan, s));
+  }
+  return PDQ_OK;
 }
 
 // ---- batched segmented sort --------------------------------------------------
@@ -596,6 +711,7 @@ int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passe
   HIP_TRY(launch_batch_zero(b, L.bcap, s));
   HIP_TRY(launch_batch_from_list(c, b, parity, src, s));
   HIP_TRY(launch_batch(c, b, tail, grid, s));
+  HIP_TRY(launch_batch_fold(c, b, s));
   for (int k = 0; k < kBaseClasses; ++k) {
     if (k == 6 && c.base_max < kWideBaseMax) continue;
     HIP_TRY(launch_base(c, k, c.max_items, s));
@@ -627,10 +743,7 @@ int run_batched(const Ctx& c0, const Opts& o, const Layout& L, char* base, pdq_s
   HIP_TRY(hipMemcpyAsync(&q, batch_args(L, base).q, sizeof(BatchQ), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (snap.errors & kErrCapacity) return PDQ_ERR_INVALID;
-  if (snap.errors || q.error) {
-    g_last_hip = 0;
-    return PDQ_ERR_HIP;
-  }
+  if (snap.errors || q.error) return PDQ_ERR_DEVICE;
   st->passes = passes;
   st->element_visits = snap.visits;
   st->partitions_right = snap.partitions_right;
@@ -693,6 +806,24 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
+  if (!offsets && uses_runs(n, 1)) {
+    RunPlan plan = {};
+    rc = run_near_sorted(c, L, base, &plan, s);
+    if (rc != PDQ_OK) return rc;
+    if (plan.state != kRunUnsorted) {
+      if (st) {
+        if (plan.state == kRunSorted) {
+          st->sorted_segments = 1;
+          st->sorted_elements = n;
+        }
+        st->near_sorted = plan.state;
+        st->near_sorted_runs = plan.runs;
+        st->near_sorted_outliers = plan.state == kRunOutliers ? plan.outliers : 0;
+        HIP_TRY(hipStreamSynchronize(s));
+      }
+      return PDQ_OK;
+    }
+  }
   // the tile of the first pass, from the average size of its segments
   // (the learned bins hold at most 2n/256 keys each, or the fit is judged
   // failed; input segments are taken as equal until the first pass has run)
@@ -787,6 +918,8 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     st->learned_equal_elements = lres.state == 1 ? lres.equal : 0;
     st->learned_final_loss = lres.loss;
     st->learned_use_log = lres.use_log;
+    st->learned_choice = lres.choice;
+    st->learned_sample_judge = lres.sample_judge;
     st->learned_fit_ms = lres.fit_ms;
     st->learned_hist_ms = lres.hist_ms;
     st->learned_scatter_ms = lres.scatter_ms;
@@ -905,6 +1038,9 @@ const char* pdq_status_string(int status) {
     case PDQ_ERR_UNSUPPORTED: return "PDQ_ERR_UNSUPPORTED: unsupported key type, order, size or option";
     case PDQ_ERR_WORKSPACE: return "PDQ_ERR_WORKSPACE: workspace missing or smaller than pdq_workspace_bytes()";
     case PDQ_ERR_HIP: return "PDQ_ERR_HIP: a HIP launch or synchronisation failed";
+    case PDQ_ERR_DEVICE:
+      return "PDQ_ERR_DEVICE: a kernel found an internal inconsistency (or a bounded wait timed out) and skipped "
+             "its writes; the output is not sorted";
     case PDQ_ERR_SCRATCH:
       return "PDQ_ERR_SCRATCH: pdq_sort_noalloc needs more scratch than PDQ_NOALLOC_SCRATCH_BYTES for this size";
     default: return "unknown pdq status";
@@ -914,6 +1050,19 @@ const char* pdq_status_string(int status) {
 int pdq_last_hip_error(void) { return g_last_hip; }
 
 int pdq_abi_version(void) { return PDQ_ABI_VERSION; }
+
+int pdq_check(const void* d_ws, void* stream) {
+  g_last_hip = 0;
+  if (!d_ws) return PDQ_ERR_INVALID;
+  // every layout starts with the counter block (make_layout)
+  const Counters* ctr = reinterpret_cast<const Counters*>(align_ptr(const_cast<void*>(d_ws)));
+  uint32_t words[2] = {0, 0};
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(words, &ctr->bad_offsets, sizeof(words), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (words[0] || (words[1] & kErrCapacity)) return PDQ_ERR_INVALID;
+  return words[1] ? PDQ_ERR_DEVICE : PDQ_OK;
+}
 
 int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_type, pdq_order order,
                      void* stream, const pdq_options* opt, pdq_stats* stats) {
@@ -1149,6 +1298,28 @@ int pdq_learned_extract(const uint64_t* d_sorted, const float* d_pred, size_t m,
   return PDQ_OK;
 }
 
+int pdq_learned_leaves(const float* d_x, const float* d_t, const float* d_pred, size_t m, float* d_runmax,
+                       double* d_leaf, float* d_pred_x, float* d_pred_y, void* stream) {
+  g_last_hip = 0;
+  if (m == 0) return PDQ_OK;
+  if (m >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (!d_x || !d_t || !d_pred || !d_runmax || !d_leaf || !d_pred_x || !d_pred_y) return PDQ_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_running_max(d_pred, m, d_runmax, s));
+  HIP_TRY(launch_leaves(d_x, d_t, d_pred, d_runmax, m, d_leaf, d_pred_x, d_pred_y, s));
+  return PDQ_OK;
+}
+
+int pdq_sample_judge(const uint64_t* d_sorted, size_t m, const uint64_t* d_splitters, const uint32_t* d_count,
+                     uint64_t* d_max_range, void* stream) {
+  g_last_hip = 0;
+  if (m == 0 || m >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  if (!d_sorted || !d_splitters || !d_count || !d_max_range) return PDQ_ERR_INVALID;
+  HIP_TRY(launch_sample_judge(d_sorted, m, d_splitters, 0, d_count, 1, d_max_range,
+                              static_cast<hipStream_t>(stream)));
+  return PDQ_OK;
+}
+
 size_t pdq_bucket_workspace_bytes(size_t n) { return bucket_layout(n).total + kAlign; }
 
 int pdq_bucket_histogram(const void* d_keys, size_t n, pdq_key_type key_type, const uint64_t* d_splitters,
@@ -1201,6 +1372,12 @@ int pdq_learned_fit(const void* d_keys, size_t n, pdq_key_type key_type, void* d
   f.partials = reinterpret_cast<float*>(scratch + fs.partials);
   f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
   f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  f.yx = reinterpret_cast<float*>(scratch + fs.yx);
+  f.yy = reinterpret_cast<float*>(scratch + fs.yy);
+  f.leaf = reinterpret_cast<double*>(scratch + fs.leaf);
+  f.cand = reinterpret_cast<uint64_t*>(scratch + fs.cand);
+  f.cand_count = reinterpret_cast<uint32_t*>(scratch + fs.cand_count);
+  f.est = reinterpret_cast<uint64_t*>(scratch + fs.est);
   return run_fit(d_keys, n, static_cast<uint32_t>(key_type), o, f, static_cast<hipStream_t>(stream));
 }
 

@@ -131,7 +131,7 @@ struct Ctx {
   uint32_t base_max;    // segments of at most this many keys go to the LDS base case
   uint32_t wide_e;      // slots per lane of the 8192 / 16384 classes (16 or 32)
   uint32_t lookback;    // 1: tiles take their places by a decoupled look-back (deterministic order)
-  uint32_t pad1_;
+  uint32_t fresh_fixed; // 1: fresh candidates at the fixed quarter offsets instead of hashed positions
 };
 
 // ---- key traits: canonical unsigned image in registers only ---------------

@@ -49,7 +49,8 @@ def test_abi_version_matches_header(pdq):
 
 def test_status_strings(pdq):
     for code, name in ((0, "PDQ_OK"), (-1, "PDQ_ERR_INVALID"), (-2, "PDQ_ERR_UNSUPPORTED"),
-                       (-3, "PDQ_ERR_WORKSPACE"), (-4, "PDQ_ERR_HIP"), (-5, "PDQ_ERR_SCRATCH")):
+                       (-3, "PDQ_ERR_WORKSPACE"), (-4, "PDQ_ERR_HIP"), (-5, "PDQ_ERR_SCRATCH"),
+                       (-6, "PDQ_ERR_DEVICE")):
         assert pdq.status_string(code).startswith(name)
     assert "unknown" in pdq.status_string(12345)
 
@@ -126,6 +127,10 @@ def test_noalloc_limits_without_gpu(pdq):
     for flag in (pdq.FLAG_PROFILE, pdq.FLAG_BATCHED, pdq.FLAG_AUTOTUNE):
         o = Opt(ctypes.sizeof(Opt), flag, -1, 0, 0)
         assert L.pdq_sort_noalloc(k, None, 10, 1, 0, None, ctypes.byref(o), None) == -2
+
+
+def test_check_argument_error_without_gpu(pdq):
+    assert pdq.lib().pdq_check(None, None) == -1
 
 
 def test_binding_has_no_fallback(pdq, monkeypatch):

@@ -66,7 +66,7 @@ def run_batched(keys, off, vals=None, **kw):
     return host(t), (host(v) if v is not None else None), st
 
 
-@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64", "i64", "f64"])
 @pytest.mark.parametrize("pairs", [False, True])
 def test_batched_mixed_sizes(kt, pairs):
     off = W.offsets_from_sizes(mixed_sizes(7))
@@ -90,6 +90,39 @@ def test_batched_tail(kt, passes):
     check_segmented(keys, off, out, vo)
     assert st["passes"] == passes
     assert st["batch_items"] > 0
+
+
+@pytest.mark.parametrize("kt", ["u64", "f64", "i32"])
+@pytest.mark.parametrize("passes", [0, 1])
+def test_batched_deep_tail(kt, passes):
+    """Segments far above the persistent kernel's LDS size with the passes cut
+    to 0 or 1: the tail partitions each of them over several levels (a child
+    it queued is partitioned again by another workgroup, possibly on another
+    XCD), then sorts the leaves. Bit-exact against the oracle."""
+    sizes = np.array([3_000_001, 1_500_000, 700_003, 64, 4097, 0, 250_000, 9000], dtype=np.int64)
+    off = W.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    keys = W.random_keys(kt, n, seed=21)
+    vals = W.index_payload(n)
+    out, vo, st = run_batched(keys, off, vals, batch_passes=passes)
+    check_segmented(keys, off, out, vo)
+    assert st["passes"] == passes
+    # a 3M-key segment needs at least log2(3M / 16384) > 7 levels of halving
+    assert st["batch_items"] >= 8
+
+
+def test_batched_without_stats_then_check():
+    """Without stats the batched call does not wait for its work; pdq_check
+    on the same workspace reports its device-side state afterwards."""
+    off = W.offsets_from_sizes(mixed_sizes(3, extra=50))
+    n = int(off[-1])
+    keys = W.random_keys("u32", n, seed=1)
+    t, o = dev(keys), dev(off)
+    opt_ws = pdq.workspace_bytes(n, off.size - 1, "u32", options=pdq._options(-1, 0, pdq.FLAG_BATCHED))
+    ws = torch.empty(opt_ws, dtype=torch.uint8, device="cuda:0")
+    pdq.segmented_sort_(t, o, batched=True, workspace=ws)
+    pdq.check(ws)
+    check_segmented(keys, off, host(t))
 
 
 @pytest.mark.parametrize("shape", [1, 2, 3, 4])

@@ -11,8 +11,10 @@ size (the oracle would take too long per case here):
 
 Sizes: 2^28 int32 in each of the paper's patterns (plain and learned
 forms), 2^27 uint64 with k equal values plus payloads, 2^29 uint64 skewed
-mixtures through the learned pass. The 65,536-segment batch and the 2^28
-uint32 headline input have full-size tests of their own."""
+mixtures through the learned pass, and the 2^28 uint32 headline input in
+both forms. Keys are also compared element by element with numpy's sort of
+the same input: the sorted key sequence is unique, so any correct sort pins
+it. The 65,536-segment batch has a full-size test of its own."""
 import numpy as np
 import pytest
 
@@ -65,10 +67,17 @@ def test_full_size_patterns_i32_plain_and_learned(pattern):
     h = multiset_hash(a)
     out, _, st = sort_on_gpu(a)
     check_sorted_permutation(a, out, h)
-    if pattern in ("ascending", "descending"):
+    if pattern == "ascending":
+        assert st["passes"] == 0 and st["near_sorted"] == 3 and st["sorted_elements"] == n
+    if pattern == "descending":
         assert st["passes"] == 1 and st["sorted_elements"] == n
+    if pattern == "ascending_random_tail":
+        # the GPU form of the partial insertion sort (Section 5.2): one scan
+        # finds one long run and 2^10 outliers, sorts them and merges
+        assert st["passes"] == 0 and st["near_sorted"] == 1
     out_l, _, st_l = sort_on_gpu(a, learned=True)
     assert np.array_equal(out_l, out)
+    assert np.array_equal(out, np.sort(a))  # element by element (an independent sort)
     print(pattern, "plain passes", st["passes"], "learned state", st_l["learned"], "passes", st_l["passes"])
 
 
@@ -83,6 +92,7 @@ def test_full_size_equal_keys_u64_pairs(k):
     assert multiset_hash(out) == h
     assert np.array_equal(np.bincount(vo, minlength=n), np.ones(n, dtype=np.int64))
     assert np.array_equal(out, a[vo])
+    assert np.array_equal(out, np.sort(a))  # element by element (an independent sort)
     print("k", k, {x: st[x] for x in ("passes", "element_visits", "partitions_right", "partitions_left",
                                       "equal_elements", "base_segments", "heapsort_segments")})
     if k != "mix" and k <= 16:
@@ -118,6 +128,21 @@ def test_full_size_learned_u64_mixtures(dist):
     h = multiset_hash(a)
     out, _, st = sort_on_gpu(a, learned=True)
     check_sorted_permutation(a, out, h, nranks=3)
+    assert np.array_equal(out, np.sort(a))  # element by element (an independent sort)
     assert st["learned"] in (1, 2)
     print(dist, {x: st[x] for x in ("learned", "learned_splitters", "learned_max_range_bin", "passes",
                                     "element_visits", "equal_elements", "learned_equal_elements")})
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_full_size_headline_u32_element_by_element(learned):
+    """The headline input (2^28 uint32 keys uniform over [0, 2^32), seed 0)
+    in the benchmark's launch configuration, both forms, compared key by key
+    with numpy's sort."""
+    n = 1 << 28
+    a = W.uniform_u32(n, seed=0)
+    out, _, st = sort_on_gpu(a, learned=learned)
+    assert np.array_equal(out, np.sort(a))
+    assert st["heapsort_segments"] == 0
+    if learned:
+        assert st["learned"] == 1

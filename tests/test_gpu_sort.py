@@ -73,8 +73,15 @@ def test_patterns_i32(pattern):
     out, _, st = gpu_sort(a)
     ref, _, c, _ = oracle.sort(a, count=True)
     assert np.array_equal(out, ref)
-    if pattern in ("ascending", "descending"):
+    if pattern == "ascending":
+        # no descent: the run scan finds it sorted, no partition pass runs
+        assert st["passes"] == 0 and st["near_sorted"] == 3 and st["sorted_elements"] == a.size
+    if pattern == "descending":
+        # the first pass finds the one segment ordered and retires it reversed
         assert st["passes"] == 1 and st["sorted_elements"] == a.size
+    if pattern == "ascending_random_tail":
+        # one long run and 2^10 outliers: sorted and merged, no partition pass
+        assert st["passes"] == 0 and st["near_sorted"] == 1 and 0 < st["near_sorted_outliers"] <= 1 << 10
 
 
 @pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64", "i64", "f64"])
@@ -141,19 +148,160 @@ def test_k_distinct_u64_pairs(k):
         assert st["element_visits"] <= n * (2 * k + 2)
 
 
-@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64", "i64", "f64"])
 def test_pairs_key_types(kt):
     n = (1 << 20) + 77
     a = W.random_keys(kt, n, seed=8)
     if kt in ("u32", "u64"):
         a = a % a.dtype.type(5000)
-    elif kt == "i32":
-        a = (a % 5000).astype(np.int32)
+    elif kt in ("i32", "i64"):
+        a = (a % 5000).astype(a.dtype) - a.dtype.type(2500)
+    elif kt == "f64":
+        a = np.round(a, 2)  # many equal keys, both signs, the zeros and infinities kept
     v = np.random.default_rng(1).permutation(n).astype(np.uint32)
     out, vo, _ = gpu_sort(a, v)
     assert np.array_equal(as_bytes(out), as_bytes(oracle.sort(a)[0]))
     assert np.array_equal(as_bytes(out), as_bytes(a[np.argsort(v)][vo]))
     assert np.array_equal(np.sort(vo), np.arange(n, dtype=np.uint32))
+
+
+# ------------------------------------------------------------------ near-sorted inputs (Section 5.2)
+
+def near_sorted_input(kind, n, kt, seed):
+    """Ascending keys of type kt with a disturbance: 'append1' one random key
+    appended, 'tail' a random tail of 2^10 keys, 'insert1' one random key
+    inserted in the middle, 'merge' two ascending runs concatenated,
+    'tail_cap' exactly 8192 keys in short runs, 'tail_over' 8193, 'three'
+    two long runs and a short one, 'sorted' nothing."""
+    rng = np.random.default_rng(seed)
+    # ascending in canonical order (-0.0 before +0.0), which np.sort does not promise
+    base = oracle.sort(W.random_keys(kt, n, seed=seed))[0]
+    if kind == "sorted":
+        return base
+    if kind == "append1":
+        return np.concatenate([base[: n - 1], W.random_keys(kt, 1, seed=seed + 1)])
+    if kind == "tail":
+        t = 1 << 10
+        return np.concatenate([base[: n - t], W.random_keys(kt, t, seed=seed + 1)])
+    if kind in ("tail_cap", "tail_over"):
+        # the t smallest keys, descending, after the t largest: every tail key
+        # is a run of its own (or of two equal keys), all of them short
+        t = 8192 if kind == "tail_cap" else 8193
+        return np.concatenate([base[t:], base[:t][::-1]])
+    if kind == "insert1":
+        m = n // 2
+        return np.concatenate([base[:m], W.random_keys(kt, 1, seed=seed + 1), base[m: n - 1]])
+    if kind == "merge":
+        return np.concatenate([oracle.sort(base[rng.permutation(n)[: n // 3]])[0],
+                               oracle.sort(base[rng.permutation(n)[: n - n // 3]])[0]])
+    if kind == "three":
+        # [run, largest key] [one key above the next run's start] [run]
+        m = n // 2
+        return np.concatenate([base[:m], base[-1:], base[m + 5: m + 6], base[m: n - 2]])
+    raise ValueError(kind)
+
+
+NEAR_EXPECT = {"sorted": 3, "append1": 1, "tail": 1, "insert1": (1, 2), "merge": 2, "tail_cap": 1,
+               "tail_over": 0, "three": 0}
+
+
+@pytest.mark.parametrize("kind", list(NEAR_EXPECT))
+@pytest.mark.parametrize("kt", ["i32", "u64", "f32", "f64"])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_near_sorted_inputs(kind, kt, pairs):
+    n = (1 << 20) + 321
+    a = near_sorted_input(kind, n, kt, seed=31)
+    v = W.index_payload(a.size) if pairs else None
+    out, vo, st = gpu_sort(a, v)
+    ref = oracle.sort(a)[0]
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+    if pairs:
+        check_pairs(a, out, vo)
+    want = NEAR_EXPECT[kind]
+    assert st["near_sorted"] in (want if isinstance(want, tuple) else (want,))
+    if st["near_sorted"]:
+        assert st["passes"] == 0
+    if kind == "append1" and st["near_sorted"] == 1:
+        assert st["near_sorted_outliers"] == 1
+    if kind == "tail_cap":
+        assert st["near_sorted_outliers"] == 8192
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_near_sorted_both_forms_and_sizes(learned):
+    """The run scan is tried before the learned pass too; ranges below
+    16384 keys skip it; a random input falls through to the passes."""
+    for n, kind in ((16384, "append1"), (16383, "append1"), (70001, "tail"), (1 << 21, "merge")):
+        a = near_sorted_input(kind, n, "u32", seed=n)
+        out, _, st = gpu_sort(a, learned=learned)
+        assert np.array_equal(out, np.sort(a))
+        assert (st["near_sorted"] != 0) == (n >= 16384)
+    a = W.uniform_u32(1 << 20, seed=2)
+    out, _, st = gpu_sort(a, learned=learned)
+    assert np.array_equal(out, np.sort(a)) and st["near_sorted"] == 0 and st["passes"] > 0
+
+
+# ------------------------------------------------------------------ fresh candidates (Section 4.2)
+
+def planted_bad_first_pivot(n, seed):
+    """Uniform keys >= 1000 with the nine ninther candidate positions of the
+    whole range (first, mid, last and their neighbours) holding nine keys
+    below 10: the first pivot has rank < 9, so the first partition is bad
+    (L < n/8) and both children take fresh candidates."""
+    rng = np.random.default_rng(seed)
+    a = rng.integers(1000, 2**32, n, dtype=np.uint32)
+    m = n // 2
+    pos = [0, m, n - 1, 1, m - 1, n - 2, 2, m + 1, n - 3]
+    a[pos] = rng.permutation(9).astype(np.uint32)
+    return a
+
+
+@pytest.mark.parametrize("fixed", [False, True])
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_fresh_candidate_rules_after_bad_partition(fixed, deterministic):
+    """Both fresh-candidate rules (hashed positions by default; the paper's
+    fixed quarter offsets with PDQ_FRESH_FIXED) run after a planted bad
+    first partition: the budget is charged, no segment falls to heapsort,
+    and the keys are bit-exact."""
+    n = (1 << 21) + 999
+    a = planted_bad_first_pivot(n, seed=4)
+    v = W.index_payload(n)
+    t = to_dev(a)
+    tv = to_dev(v)
+    st = pdq.sort_pairs_(t, tv, stats=True, fresh_fixed=fixed, deterministic=deterministic)
+    torch.cuda.synchronize()
+    out, vo = t.cpu().numpy(), tv.cpu().numpy()
+    ref, _, c, _ = oracle.sort(a, count=True)
+    assert np.array_equal(out, ref)
+    check_pairs(a, out, vo)
+    assert st["first_left_size"] == c["first_left_size"] < n // 8
+    assert st["bad_partitions"] >= 1
+    assert st["heapsort_segments"] == 0
+
+
+def test_fresh_rules_differ_only_below_the_bad_partition():
+    """With the look-back form every run arranges the keys identically, so
+    each rule repeats its own statistics exactly; the first partition (before
+    any fresh candidate) is the same for both rules."""
+    n = (1 << 21) + 999
+    a = planted_bad_first_pivot(n, seed=5)
+    runs = {}
+    for fixed in (False, True, False, True):
+        out, _, st = gpu_sort(a, deterministic=True, fresh_fixed=fixed)
+        assert np.array_equal(out, np.sort(a))
+        runs.setdefault(fixed, []).append(st)
+    for fixed, (s1, s2) in runs.items():
+        assert {k: s1[k] for k in DET_STATS} == {k: s2[k] for k in DET_STATS}
+    assert runs[False][0]["first_left_size"] == runs[True][0]["first_left_size"]
+
+
+def test_check_after_sort_reports_no_device_error():
+    a = W.uniform_u32((1 << 20) + 3, seed=3)
+    t = to_dev(a)
+    ws = torch.empty(pdq.workspace_bytes(a.size, 1, "u32"), dtype=torch.uint8, device="cuda:0")
+    pdq.sort_(t, workspace=ws)
+    pdq.check(ws)
+    assert np.array_equal(t.cpu().numpy(), np.sort(a))
 
 
 # ------------------------------------------------------------------ segmented
