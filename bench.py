@@ -19,8 +19,14 @@ Also reported:
     partition kernel and first pass, beside it;
   * patterns: keys/s of both forms on 2^28 int32 keys in the seven input
     patterns;
-  * cpu_baseline: the oracle (single-threaded CPU pdqsort) on a bounded
-    sample of the same input, timed on this host.
+  * equal_keys_u64_pairs: 2^27 uint64 keys with k in {2, 16, 1024, 65536}
+    distinct values and a 90%-one-value mix, with payloads: passes and keys
+    partitioned per key against Theorem 1's 2k + 2;
+  * learned_mixtures_u64: learned against plain on 2^29 uint64 lognormal,
+    Zipf and Gaussian-mixture keys, with the learned judge's decision;
+  * cpu_baseline: the oracle (single-threaded CPU pdqsort) on the whole
+    headline input, median of three runs pinned to one core, plus the
+    segmented batch over every usable core.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--log2n 28]
 """
@@ -137,7 +143,10 @@ def main():
     ap.add_argument("--no-patterns", action="store_true")
     ap.add_argument("--paper-log2n", type=int, default=26,
                     help="size of the uint64 inputs in the paper's remaining distributions (0 = skip)")
-    ap.add_argument("--cpu-log2n", type=int, default=26)
+    ap.add_argument("--equal-log2n", type=int, default=27,
+                    help="size of the uint64 equal-key inputs with payloads (0 = skip)")
+    ap.add_argument("--mix-log2n", type=int, default=29,
+                    help="size of the uint64 skewed mixtures of the learned form (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-segmented", action="store_true")
@@ -272,19 +281,17 @@ def main():
     if not args.no_segmented:
         segmented = bench_segmented(pdq, torch, W, dev, args)
 
+    equal_keys = None
+    if not args.no_patterns and args.equal_log2n > 0:
+        equal_keys = bench_equal_keys(pdq, torch, W, dev, args)
+
+    learned_mix = None
+    if not args.no_patterns and args.mix_log2n > 0:
+        learned_mix = bench_learned_mixtures(pdq, torch, W, dev, args)
+
     cpu = None
     if not args.no_cpu:
-        import oracle
-        m = 1 << min(args.cpu_log2n, args.log2n)
-        sample = host[:m].copy()
-        log(f"cpu oracle on {m} keys")
-        t1 = time.perf_counter()
-        oracle.sort(sample)
-        dt = time.perf_counter() - t1
-        cpu = {"value": round(m / dt, 0), "unit": "keys/s", "cores": 1, "kind": "oracle",
-               "sample": f"first 2^{int(np.log2(m))} keys of the same uint32 input, one single-threaded "
-                         f"oracle sort ({dt:.2f} s)",
-               "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+        cpu = cpu_baseline(host, keys_seg=None if args.no_segmented else args.seg_count, W=W)
 
     line = {
         "metric": METRIC,
@@ -311,6 +318,8 @@ def main():
         "patterns_i32": patterns,
         "paper_distributions_u64": {"n": 1 << args.paper_log2n, "rows": paper} if paper else None,
         "segmented_f32_pairs": segmented,
+        "equal_keys_u64_pairs": equal_keys,
+        "learned_mixtures_u64": learned_mix,
     }
     print(json.dumps(line), flush=True)
 
@@ -395,6 +404,154 @@ def bench_segmented(pdq, torch, W, dev, args):
                               "shape": {"tile": pdq.BATCH_SHAPES[shape][0], "wide_class_slots": pdq.BATCH_SHAPES[shape][1]},
                               "autotune_ms_per_shape": [round(x, 3) for x in tune_ms]},
             "batched_over_plain": round(mp / mg, 3)}
+
+
+def bench_equal_keys(pdq, torch, W, dev, args):
+    """The equal-key stress of the Dutch-flag scheme (Section 3, Theorem 1):
+    2^27 uint64 keys taking k distinct values (and a 90%-one-value mix) with
+    a uint32 index payload; passes and keys partitioned per key against the
+    2k + 2 bound, and the oracle's comparisons per key on a 2^22-key input of
+    the same generator (comparisons / n depends on k, not on n)."""
+    import oracle
+    n = 1 << args.equal_log2n
+    rows = {}
+    wk = torch.empty(n, dtype=torch.uint64, device=dev)
+    wv = torch.empty(n, dtype=torch.uint32, device=dev)
+    pv = torch.from_numpy(W.index_payload(n)).to(dev)
+    for k in (2, 16, 1024, 65536, "mix"):
+        log(f"equal keys k={k}")
+        h = W.one_value_mix_u64(n, seed=0) if k == "mix" else W.k_distinct_u64(n, k, seed=0)
+        pk = torch.from_numpy(h).to(dev)
+        ms, sts = [], []
+        for _ in range(args.pattern_steps + 1):
+            wk.copy_(pk)
+            wv.copy_(pv)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            st = pdq.sort_pairs_(wk, wv, stats=True)
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+            sts.append(st)
+        ms = ms[1:]
+        st = sts[-1]
+        m = 1 << 22
+        small = W.one_value_mix_u64(m, seed=0) if k == "mix" else W.k_distinct_u64(m, k, seed=0)
+        _, _, c, _ = oracle.sort(small, count=True)
+        rows[str(k)] = {"keys/s": round(n / (np.mean(ms) * 1e-3), 0), "ms": round(float(np.mean(ms)), 3),
+                        "passes": st["passes"], "element_visits_per_key": round(st["element_visits"] / n, 3),
+                        "pass_bound_2k_plus_2": (2 * k + 2) if k != "mix" else None,
+                        "partitions_right": st["partitions_right"], "partitions_left": st["partitions_left"],
+                        "equal_elements": st["equal_elements"], "heapsort_segments": st["heapsort_segments"],
+                        "oracle_comparisons_per_key_2p22": round(c["comparisons"] / m, 3)}
+        del pk
+    del wk, wv, pv
+    torch.cuda.empty_cache()
+    return {"workload": f"2^{args.equal_log2n} uint64 keys with k distinct values (uniform over them) or 90% one "
+                        f"value + 10% uniform, uint32 index payload (seed 0)", "n": n, "rows": rows}
+
+
+def bench_learned_mixtures(pdq, torch, W, dev, args):
+    """The learned form against the plain one on 2^29 uint64 keys from three
+    skewed mixtures; reports whether the learned pass ran or its judge sent
+    the call back to the plain path, and the largest range bin over the fair
+    share n/256."""
+    n = 1 << args.mix_log2n
+    rows = {}
+    wk = torch.empty(n, dtype=torch.uint64, device=dev)
+    lopt = pdq.Options(ctypes.sizeof(pdq.Options), pdq.FLAG_LEARNED, -1, 0, 0, 0.0, 0, 0, 0)
+    ws = torch.empty(pdq.workspace_bytes(n, 1, "u64", options=lopt), dtype=torch.uint8, device=dev)
+    for dist in ("lognormal", "zipf", "gmm"):
+        log(f"learned mixture {dist}: generating 2^{args.mix_log2n} keys")
+        if dist == "zipf":
+            # inverse-CDF lookup of the same uniforms on the device (same keys as zipf_u64)
+            cdf = torch.from_numpy(W.zipf_cdf()).to(dev)
+            u = torch.from_numpy(W.zipf_uniforms(n, 0)).to(dev)
+            pk = torch.clamp(torch.searchsorted(cdf, u, right=True) + 1, max=cdf.numel()).to(torch.int64)
+            pk = pk.view(torch.uint64)
+            del cdf, u
+        else:
+            h = W.lognormal_u64(n, seed=0) if dist == "lognormal" else W.gmm_u64(n, seed=0)
+            pk = torch.from_numpy(h).to(dev)
+            del h
+        row = {}
+        for name, kw in (("plain", {}), ("learned", {"learned": True})):
+            ms, st = time_sorts(pdq, torch, pk, wk, ws, args.pattern_steps + 1, profile=True, **kw)
+            ms = ms[1:]
+            s0 = st[-1]
+            row[name] = {"keys/s": round(n / (np.mean(ms) * 1e-3), 0), "ms": round(float(np.mean(ms)), 3),
+                         "passes": s0["passes"], "element_visits_per_key": round(s0["element_visits"] / n, 3)}
+            if kw:
+                row[name].update({"learned_state": s0["learned"], "splitters": s0["learned_splitters"],
+                                  "max_range_bin_over_fair": round(s0["learned_max_range_bin"] / (n / 256), 3),
+                                  "fit_ms": round(float(np.mean([x["learned_fit_ms"] for x in st[1:]])), 3),
+                                  "equal_bin_keys": s0["learned_equal_elements"]})
+        row["learned_over_plain"] = round(row["plain"]["ms"] / row["learned"]["ms"], 3)
+        rows[dist] = row
+        del pk
+        torch.cuda.empty_cache()
+    del wk, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"2^{args.mix_log2n} uint64 keys: lognormal(20, 3) rounded, Zipf(1.1) over 2^24 ranks, "
+                        f"8-component Gaussian mixture on a 2^40 grid (seed 0); learned state 1 = learned pass "
+                        f"used, 2 = judged and sent back to the plain path", "n": n, "rows": rows}
+
+
+def cpu_baseline(host, keys_seg, W):
+    """The oracle (single-threaded CPU pdqsort, generic -O2 build, counters
+    compiled out) timed on this host: the full 2^28 headline input, three
+    runs pinned to one core, median; plus the 65,536-segment batch sorted
+    with the segments spread over every core this process may use."""
+    import concurrent.futures as cf
+    import oracle
+    n = host.size
+    cpus = sorted(os.sched_getaffinity(0))
+    old = set(cpus)
+    runs = []
+    try:
+        os.sched_setaffinity(0, {cpus[0]})
+        for r in range(3):
+            log(f"cpu oracle on {n} keys, run {r + 1} of 3 (one core)")
+            t1 = time.perf_counter()
+            oracle.sort(host)
+            runs.append(time.perf_counter() - t1)
+    finally:
+        os.sched_setaffinity(0, old)
+    dt = float(np.median(runs))
+    out = {"value": round(n / dt, 0), "unit": "keys/s", "cores": 1, "kind": "oracle",
+           "sample": f"the whole 2^{int(np.log2(n))}-key uint32 headline input, median of 3 single-threaded oracle "
+                     f"sorts pinned to one core ({', '.join(f'{x:.2f}' for x in runs)} s)",
+           "ns_per_n_log2_n": round(float(dt * 1e9 / (n * np.log2(n))), 4),
+           "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(), "usable_cores": len(cpus)}
+    if keys_seg:
+        keys, off, vals = W.segmented_f32(keys_seg, max_log2=16, seed=0)
+        nseg = off.size - 1
+        threads = len(cpus)
+        # contiguous groups of segments with about equal key counts
+        cuts = np.searchsorted(off, np.linspace(0, off[-1], threads + 1).astype(np.uint64))
+        cuts[0], cuts[-1] = 0, nseg
+        groups = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+
+        def one(g):
+            a, b = g
+            lo, hi = int(off[a]), int(off[b])
+            oracle.segmented_sort(keys[lo:hi], (off[a:b + 1] - off[a]).astype(np.uint64), vals[lo:hi])
+
+        truns = []
+        with cf.ThreadPoolExecutor(threads) as ex:
+            for r in range(3):
+                log(f"cpu oracle, segmented batch on {threads} threads, run {r + 1} of 3")
+                t1 = time.perf_counter()
+                list(ex.map(one, groups))
+                truns.append(time.perf_counter() - t1)
+        ts = float(np.median(truns))
+        out["segmented_all_cores"] = {
+            "value": round(keys.size / ts, 0), "unit": "keys/s", "cores": threads, "kind": "oracle",
+            "sample": f"the {nseg}-segment float32 + uint32 batch ({keys.size} keys), segments split into "
+                      f"{len(groups)} contiguous groups of about equal key counts, one oracle segmented sort per "
+                      f"thread, median of 3 ({', '.join(f'{x:.2f}' for x in truns)} s)"}
+    return out
 
 
 def _cpu_model() -> str:
