@@ -29,9 +29,10 @@
  * int32 as two's complement, float32 by the total order on its bit
  * patterns: -inf < ... < -0.0 < +0.0 < ... < +inf. NaN inputs are outside
  * the contract (they are placed by bit pattern, nothing more is promised).
- * Sorted keys are unique bit for bit. Payloads (uint32) travel with their
- * keys; the sort is unstable, so the order of payloads of equal keys is not
- * specified (any permutation consistent with the keys is valid).
+ * Sorted keys are unique bit for bit. Payloads (uint32, or uint64 with
+ * PDQ_VALS64) travel with their keys; the sort is unstable, so the order of
+ * payloads of equal keys is not specified (any permutation consistent with
+ * the keys is valid).
  *
  * Memory and ownership: every pointer argument named d_* is a device
  * pointer owned by the caller. The library never allocates device memory:
@@ -111,6 +112,10 @@ enum pdq_flags {
                              arranges the keys (and the payloads of equal keys) identically.
                              Slower. The learned pass's scatter still orders keys inside a bin
                              by LDS atomics, so with PDQ_LEARNED it covers the passes only */
+  PDQ_VALS64 = 1u << 7,   /* the payload pointer d_vals of pdq_sort_pairs, pdq_segmented_sort,
+                             pdq_plan_create and pdq_sort_noalloc points to uint64_t payloads
+                             (8-byte aligned) instead of uint32_t; pass the same options to
+                             pdq_workspace_bytes (12 more bytes per key) */
   PDQ_FRESH_FIXED = 1u << 6 /* after a bad partition take the fresh pivot candidates at the fixed
                              quarter offsets of Section 4.2's deterministic rule instead of the
                              default hashed positions (Section 4.2's randomised rule; the hash
@@ -252,7 +257,8 @@ void pdq_plan_destroy(pdq_plan* plan);
  * in a file-scope device array of PDQ_NOALLOC_SCRATCH_BYTES inside the
  * library; this call allocates nothing (no hipMalloc, no events, no library
  * allocation). d_vals may be NULL (keys only, as pdq_sort) or a uint32
- * payload moved with the keys (as pdq_sort_pairs). A call whose
+ * (uint64 with PDQ_VALS64) payload moved with the keys (as pdq_sort_pairs).
+ * A call whose
  * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt) exceeds
  * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
  * (without PDQ_LEARNED: up to 16,149,632 uint32 keys, 8,227,712 uint32 keys

@@ -27,7 +27,7 @@ __all__ = [
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
     "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "learned_leaves", "sample_judge", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
-    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED",
+    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED", "FLAG_VALS64",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,6 +44,7 @@ FLAG_BATCHED = 8
 FLAG_AUTOTUNE = 16
 FLAG_DETERMINISTIC = 32
 FLAG_FRESH_FIXED = 64
+FLAG_VALS64 = 128
 # batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
 BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
@@ -246,10 +247,12 @@ def _prepare(keys, vals, nseg, force_budget, tile, flags, workspace, learn=None)
     if not keys.is_contiguous():
         raise ValueError("keys must be contiguous")
     if vals is not None:
-        if vals.dtype != torch.uint32 or not vals.is_cuda or not vals.is_contiguous():
-            raise ValueError("vals must be a contiguous uint32 device tensor")
+        if vals.dtype not in (torch.uint32, torch.uint64) or not vals.is_cuda or not vals.is_contiguous():
+            raise ValueError("vals must be a contiguous uint32 or uint64 device tensor")
         if vals.numel() != keys.numel():
             raise ValueError("vals must have as many elements as keys")
+        if vals.dtype == torch.uint64:
+            flags |= FLAG_VALS64
     kt = _key_type(keys)
     opt = _options(force_budget, tile, flags, **(learn or {}))
     need = workspace_bytes(keys.numel(), nseg, kt, vals is not None, opt)
@@ -294,7 +297,8 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
                 imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
                 deterministic: bool = False, fresh_fixed: bool = False):
-    """Sort keys in place and move the uint32 payload `vals` with them."""
+    """Sort keys in place and move the payload `vals` (uint32, or uint64:
+    PDQ_VALS64) with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
@@ -343,11 +347,13 @@ def sort_noalloc_(keys, vals=None, *, force_budget: int = -1, tile: int = 0, sta
     import torch
     if not keys.is_cuda or not keys.is_contiguous():
         raise ValueError("keys must be a contiguous device tensor")
-    if vals is not None and (vals.dtype != torch.uint32 or not vals.is_cuda or not vals.is_contiguous()
-                             or vals.numel() != keys.numel()):
-        raise ValueError("vals must be a contiguous uint32 device tensor with as many elements as keys")
+    if vals is not None and (vals.dtype not in (torch.uint32, torch.uint64) or not vals.is_cuda
+                             or not vals.is_contiguous() or vals.numel() != keys.numel()):
+        raise ValueError("vals must be a contiguous uint32 or uint64 device tensor with as many elements as keys")
     kt = _key_type(keys)
     flags = (FLAG_LEARNED if learned else 0) | (FLAG_DETERMINISTIC if deterministic else 0)
+    if vals is not None and vals.dtype == torch.uint64:
+        flags |= FLAG_VALS64
     opt = _options(force_budget, tile, flags, seed=seed)
     st = Stats(ctypes.sizeof(Stats)) if stats else None
     stream = ctypes.c_void_p(torch.cuda.current_stream(keys.device).cuda_stream)

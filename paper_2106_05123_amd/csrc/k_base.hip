@@ -4,9 +4,12 @@
 //
 // The paper sorts small subsequences with insertion sort (Section 5.1) and
 // notes that sorting networks lost on its CPU through code size (Section 2);
-// on a GPU a bitonic network (bitonic.h) is the natural small sort. A
-// segment of P = E * NT slots (padded to a power of two) is held E slots per
-// lane in registers; payloads are gathered by index at the end.
+// on a GPU a bitonic network (bitonic.h) is the natural small sort below
+// 1024 slots. From 1024 slots a segment whose 32-bit key images span at most
+// 18 bits (the usual case: it lies between two pivots) is sorted by an LDS
+// radix sort of (image - minimum), else by a merge sort. A segment of
+// P = E * NT slots (padded to a power of two) is held E slots per lane in
+// registers; payloads are gathered by index at the end.
 #include "bitonic.h"
 #include "pdq_internal.h"
 #include "wave_ops.h"
@@ -29,7 +32,11 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   using V = typename S::V;
   constexpr int P = E * NT;
   constexpr int PL = lds_plane<P, E>();
+  // the radix sort serves 32-bit images in workgroups of up to 256 lanes
+  // (its counter matrix grows with the lanes)
+  constexpr bool kRadix = P >= 1024 && NT <= 256 && sizeof(typename S::I) == 4;
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
+  __shared__ __align__(16) uint16_t cnt[kRadix ? net::radix_counters<NT>() : 1];
   // a list longer than its capacity (only invalid offsets make one; it is
   // flagged) is read no further than its capacity
   uint32_t count = c.device_counts ? c.ctr->nbase[cls] : nitems;
@@ -55,8 +62,13 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
     for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
     __syncthreads();
 
-    if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
-    else net::bitonic<S, E, NT>(x, sh, tid);
+    if constexpr (E * NT >= 1024) {
+      bool done = false;
+      if constexpr (kRadix) done = net::radix_sort<S, E, NT>(x, sh, cnt, tid, len);
+      if (!done) net::merge_sort<S, E, NT>(x, sh, tid);
+    } else {
+      net::bitonic<S, E, NT>(x, sh, tid);
+    }
 
     // back through LDS so that the final writes are coalesced
 #pragma unroll

@@ -454,4 +454,42 @@ hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s) {
   return dispatch_key<HeapL>(c.key_type, c, nitems, s);
 }
 
+// 64-bit payloads travel through the sort as 32-bit indices: before it,
+// idx[i] = i and a copy of the payloads; after it, each output slot fetches
+// its payload through its index.
+__global__ __launch_bounds__(256) void k_vals64_prepare(const uint64_t* __restrict__ vals, uint64_t n,
+                                                        uint32_t* __restrict__ idx, uint64_t* __restrict__ copy) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * 256u) {
+    idx[i] = static_cast<uint32_t>(i);
+    copy[i] = vals[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_vals64_gather(uint64_t* __restrict__ vals, uint64_t n,
+                                                       const uint32_t* __restrict__ idx,
+                                                       const uint64_t* __restrict__ copy) {
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * 256u) {
+    const uint32_t j = idx[i];
+    vals[i] = j < n ? copy[j] : 0ull;  // j < n always; the test keeps a corrupted index in bounds
+  }
+}
+
+static uint32_t stream_grid(uint64_t n) {
+  const uint64_t g = (n + 255) / 256;
+  return static_cast<uint32_t>(g < 16384 ? (g ? g : 1) : 16384);
+}
+
+hipError_t launch_vals64_prepare(const uint64_t* vals, uint64_t n, uint32_t* idx, uint64_t* copy, hipStream_t s) {
+  hipLaunchKernelGGL(k_vals64_prepare, dim3(stream_grid(n)), dim3(256), 0, s, vals, n, idx, copy);
+  return hipGetLastError();
+}
+
+hipError_t launch_vals64_gather(uint64_t* vals, uint64_t n, const uint32_t* idx, const uint64_t* copy,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_vals64_gather, dim3(stream_grid(n)), dim3(256), 0, s, vals, n, idx, copy);
+  return hipGetLastError();
+}
+
 }  // namespace pdq

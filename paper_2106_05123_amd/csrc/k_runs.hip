@@ -62,8 +62,16 @@ __global__ __launch_bounds__(kScanNT) void k_run_scan(const typename K::T* __res
     for (int r = 0; r < kScanRows; ++r) {
       const uint64_t i = ch * kScanChunk + static_cast<uint64_t>(r) * kScanNT + tid;
       k[r] = i < n ? keys[i] : T(0);
-      d[r] = false;
-      if (i + 1 < n) d[r] = K::ord(keys[i + 1]) < K::ord(k[r]);
+    }
+    // the successor of a key is the next lane's key; the last lane of a wave
+    // loads it (it belongs to the next wave or the next row)
+    const bool last_lane = lane_id() == 63;
+#pragma unroll
+    for (int r = 0; r < kScanRows; ++r) {
+      const uint64_t i = ch * kScanChunk + static_cast<uint64_t>(r) * kScanNT + tid;
+      T nxt = __shfl_down(k[r], 1, 64);
+      if (last_lane) nxt = i + 1 < n ? keys[i + 1] : T(0);
+      d[r] = i + 1 < n && K::ord(nxt) < K::ord(k[r]);
       mine += d[r] ? 1u : 0u;
     }
     const uint64_t wsum = wave_sum_u64(mine);

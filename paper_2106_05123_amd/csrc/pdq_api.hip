@@ -287,7 +287,7 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, batch_passes) + sizeof(uint32_t)) out->batch_passes = o->batch_passes;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
-                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED))
+                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->batch_passes > kMaxBatchPasses + 1) return PDQ_ERR_UNSUPPORTED;
@@ -949,7 +949,19 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
 // Runs a sort with statistics gathered in a current-layout struct and copied
 // out up to the caller's struct_size (older, smaller layouts stay valid).
-int sort_entry(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
+// Workspace of 64-bit payloads (PDQ_VALS64), after the call's layout: the
+// 32-bit index payload the sort moves, and a copy of the payloads.
+size_t vals64_bytes(size_t n) { return align_up(n * 4) + align_up(n * 8); }
+
+// The layout a call uses (the same decisions as run_sort).
+Layout call_layout(size_t n, const uint64_t* offsets, size_t nseg, int kt, bool vals, const Opts& o) {
+  const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
+  const bool batched = (o.flags & PDQ_BATCHED) && offsets;
+  return make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals, learned, o.steps, o.grid, batched,
+                          false);
+}
+
+int sort_stats(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
                void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
   if (!st) return run_sort(keys, vals, n, offsets, nseg, kt, order, ws, ws_bytes, stream, opt, nullptr);
   pdq_stats local;
@@ -960,6 +972,36 @@ int sort_entry(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, si
   local.struct_size = user_size;
   memcpy(st, &local, copy);
   return rc;
+}
+
+// Runs a sort with statistics gathered in a current-layout struct and copied
+// out up to the caller's struct_size (older, smaller layouts stay valid).
+// With PDQ_VALS64 the 64-bit payloads travel as 32-bit indices: the sort
+// moves an index array in the workspace, and one gather places the payloads
+// at the end (traffic: 12 bytes per key once, instead of 8 more bytes per
+// key in every partition pass).
+int sort_entry(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
+               void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
+  Opts o;
+  const int orc = read_opts(opt, &o);
+  if (orc != PDQ_OK || !vals || !(o.flags & PDQ_VALS64) || n <= 1 || !valid_key_type(kt))
+    return sort_stats(keys, vals, n, offsets, nseg, kt, order, ws, ws_bytes, stream, opt, st);
+  g_last_hip = 0;
+  if (reinterpret_cast<uintptr_t>(vals) % 8) return PDQ_ERR_INVALID;
+  if (n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
+  const Layout L = call_layout(n, offsets, nseg, kt, true, o);
+  if (!ws || ws_bytes < L.total + vals64_bytes(n)) return PDQ_ERR_WORKSPACE;
+  char* extra = align_ptr(ws) + (L.total - kAlign);
+  uint32_t* idx = reinterpret_cast<uint32_t*>(extra);
+  uint64_t* vcopy = reinterpret_cast<uint64_t*>(extra + align_up(n * 4));
+  uint64_t* v64 = reinterpret_cast<uint64_t*>(vals);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_vals64_prepare(v64, n, idx, vcopy, s));
+  const int rc = sort_stats(keys, idx, n, offsets, nseg, kt, order, ws, ws_bytes, stream, opt, st);
+  if (rc != PDQ_OK) return rc;
+  HIP_TRY(launch_vals64_gather(v64, n, idx, vcopy, s));
+  if (st) HIP_TRY(hipStreamSynchronize(s));
+  return PDQ_OK;
 }
 
 // ---- scratch of pdq_sort_noalloc ---------------------------------------------
@@ -1007,9 +1049,10 @@ size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has
   if (nseg == 0) nseg = 1;
   const bool learned = (o.flags & PDQ_LEARNED) && nseg == 1 && n > kLearnSample;
   const bool batched = (o.flags & (PDQ_BATCHED | PDQ_AUTOTUNE)) != 0;
-  return make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps, o.grid, batched,
-                          (o.flags & PDQ_AUTOTUNE) != 0)
-      .total;
+  const size_t total = make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps,
+                                        o.grid, batched, (o.flags & PDQ_AUTOTUNE) != 0)
+                           .total;
+  return total + (has_vals && (o.flags & PDQ_VALS64) ? vals64_bytes(n) : 0);
 }
 
 int pdq_sort(void* d_keys, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws, size_t ws_bytes,
@@ -1108,16 +1151,23 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
   if (rc != PDQ_OK) return rc;
   if (n == 0 || n >= (1ull << 32) || nseg == 0 || nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
   const uint32_t kb = key_bytes(static_cast<uint32_t>(key_type));
+  const bool v64 = d_vals && (o.flags & PDQ_VALS64);
   if (!d_keys || !d_offsets || reinterpret_cast<uintptr_t>(d_keys) % kb ||
-      reinterpret_cast<uintptr_t>(d_offsets) % 8 || (d_vals && reinterpret_cast<uintptr_t>(d_vals) % 4))
+      reinterpret_cast<uintptr_t>(d_offsets) % 8 || (d_vals && reinterpret_cast<uintptr_t>(d_vals) % (v64 ? 8 : 4)))
     return PDQ_ERR_INVALID;
   const bool tune = (o.flags & PDQ_AUTOTUNE) != 0;
   const Layout L = make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), d_vals != nullptr, false, o.steps,
                                     o.grid, true, tune);
-  if (!d_ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
+  if (!d_ws || ws_bytes < L.total + (v64 ? vals64_bytes(n) : 0)) return PDQ_ERR_WORKSPACE;
   char* base = align_ptr(d_ws);
+  // 64-bit payloads: the plan sorts 32-bit indices and gathers at the end
+  uint64_t* const vals64 = v64 ? reinterpret_cast<uint64_t*>(d_vals) : nullptr;
+  uint32_t* const idx = v64 ? reinterpret_cast<uint32_t*>(base + (L.total - kAlign)) : nullptr;
+  uint64_t* const vcopy = v64 ? reinterpret_cast<uint64_t*>(base + (L.total - kAlign) + align_up(n * 4)) : nullptr;
+  if (v64) d_vals = idx;
   const Ctx c = make_ctx(d_keys, d_vals, n, d_offsets, nseg, key_type, o, L, base);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (v64 && launch_vals64_prepare(vals64, n, idx, vcopy, s) != hipSuccess) return PDQ_ERR_HIP;
   pdq_plan* p = new pdq_plan();
   auto fail = [&](int code) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -1177,8 +1227,11 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     const Ctx cc = batch_ctx(c, o, shape);
-    rc = enqueue_batch_init(cc, cs);
+    rc = PDQ_OK;
+    if (v64 && launch_vals64_prepare(vals64, n, idx, vcopy, cs) != hipSuccess) rc = PDQ_ERR_HIP;
+    if (rc == PDQ_OK) rc = enqueue_batch_init(cc, cs);
     if (rc == PDQ_OK) rc = enqueue_batch_rest(cc, L, base, passes, kShapes[shape].tail, cs);
+    if (rc == PDQ_OK && v64 && launch_vals64_gather(vals64, n, idx, vcopy, cs) != hipSuccess) rc = PDQ_ERR_HIP;
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(cs, &g);
     p->graph = g;

@@ -200,6 +200,11 @@ hipError_t launch_bookkeep(const Ctx& c, int parity, uint32_t nseg, uint32_t src
 hipError_t launch_base(const Ctx& c, int cls, uint32_t nitems, hipStream_t s);
 hipError_t launch_heap(const Ctx& c, uint32_t nitems, hipStream_t s);
 hipError_t launch_copy(const Ctx& c, uint32_t nitems, hipStream_t s);
+// 64-bit payloads (PDQ_VALS64): idx[i] = i and copy = vals before the sort,
+// vals[i] = copy[idx[i]] after it.
+hipError_t launch_vals64_prepare(const uint64_t* vals, uint64_t n, uint32_t* idx, uint64_t* copy, hipStream_t s);
+hipError_t launch_vals64_gather(uint64_t* vals, uint64_t n, const uint32_t* idx, const uint64_t* copy,
+                                hipStream_t s);
 
 inline uint32_t key_bytes(uint32_t key_type) { return key_type >= 4 ? 8u : 4u; }
 

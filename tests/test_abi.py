@@ -87,7 +87,7 @@ def test_argument_errors_without_gpu(pdq):
     assert _call_sort(pdq, 0x1000, 1 << 20, ws_bytes=100) == -3
     assert _call_sort(pdq, 0, 0) == 0                        # n <= 1 is a no-op
     assert _call_sort(pdq, 0, 1) == 0
-    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0x80, -1, 0, 0)) == -2  # unknown flag
+    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0x100, -1, 0, 0)) == -2  # unknown flag
     assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0, -1, 3000, 0)) == -2  # bad tile
     # pairs without payload, segmented without offsets
     assert L.pdq_sort_pairs(ctypes.c_void_p(0x1000), None, 10, 1, 0, ctypes.c_void_p(0x10000), 1 << 40, None,
@@ -127,6 +127,26 @@ def test_noalloc_limits_without_gpu(pdq):
     for flag in (pdq.FLAG_PROFILE, pdq.FLAG_BATCHED, pdq.FLAG_AUTOTUNE):
         o = Opt(ctypes.sizeof(Opt), flag, -1, 0, 0)
         assert L.pdq_sort_noalloc(k, None, 10, 1, 0, None, ctypes.byref(o), None) == -2
+
+
+def test_vals64_workspace_and_alignment_without_gpu(pdq):
+    """PDQ_VALS64: 12 more workspace bytes per key (the 32-bit index payload
+    the sort moves and a copy of the 64-bit payloads), and 8-byte alignment
+    of the payload pointer."""
+    Opt = pdq.Options
+    o64 = Opt(ctypes.sizeof(Opt), pdq.FLAG_VALS64, -1, 0, 0)
+    for kt in ("u32", "u64"):
+        for n in (1000, 1 << 20):
+            base = pdq.workspace_bytes(n, 1, kt, has_vals=True)
+            assert pdq.workspace_bytes(n, 1, kt, has_vals=True, options=o64) >= base + 12 * n
+            assert pdq.workspace_bytes(n, 1, kt, has_vals=False, options=o64) == pdq.workspace_bytes(n, 1, kt)
+    L = pdq.lib()
+    rc = L.pdq_sort_pairs(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2004), 10, 1, 0, ctypes.c_void_p(0x100000),
+                          1 << 40, None, ctypes.byref(o64), None)
+    assert rc == -1
+    rc = L.pdq_sort_pairs(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 1 << 20, 1, 0, ctypes.c_void_p(0x100000),
+                          pdq.workspace_bytes(1 << 20, 1, "u32", has_vals=True), None, ctypes.byref(o64), None)
+    assert rc == -3  # the workspace of 32-bit payloads is too small for 64-bit ones
 
 
 def test_check_argument_error_without_gpu(pdq):

@@ -451,3 +451,121 @@ def test_default_form_agrees_with_deterministic_on_keys_and_first_pass():
     assert np.array_equal(o1, o2)
     assert s1["first_pivot_image"] == s2["first_pivot_image"]
     assert s1["first_left_size"] == s2["first_left_size"]
+
+
+# ------------------------------------------------------------------ 64-bit payloads (PDQ_VALS64)
+
+def check_pairs64(keys_in, vals_in, keys_out, vals_out):
+    """Keys bit-exact against the oracle; every output (key, payload) pair is
+    an input pair, each used once (payloads of equal keys in any order)."""
+    assert np.array_equal(as_bytes(keys_out), as_bytes(oracle.sort(keys_in)[0]))
+    kb_in, kb_out = bits_u64(keys_in), bits_u64(keys_out)
+    a = np.lexsort((vals_in, kb_in))
+    b = np.lexsort((vals_out, kb_out))
+    assert np.array_equal(kb_in[a], kb_out[b]) and np.array_equal(vals_in[a], vals_out[b])
+
+
+def bits_u64(a):
+    return a.view(np.uint32).astype(np.uint64) if a.dtype.itemsize == 4 else a.view(np.uint64)
+
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64", "i64", "f64"])
+@pytest.mark.parametrize("learned", [False, True])
+def test_pairs_u64_payloads(kt, learned):
+    n = (1 << 20) + 4097
+    a = W.random_keys(kt, n, seed=40)
+    if kt in ("u32", "i32", "u64", "i64"):
+        a = (a % a.dtype.type(70000)).astype(a.dtype)  # equal keys with different payloads
+    v = np.random.default_rng(41).integers(0, 2**64, n, dtype=np.uint64)
+    t, tv = to_dev(a), to_dev(v)
+    st = pdq.sort_pairs_(t, tv, stats=True, learned=learned)
+    torch.cuda.synchronize()
+    check_pairs64(a, v, t.cpu().numpy(), tv.cpu().numpy())
+    if learned:
+        assert st["learned"] in (1, 2)
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_segmented_u64_payloads(batched):
+    sizes = np.array([0, 1, 5, 4096, 4097, 20000, 70001, 300000, 1000, 9000], dtype=np.int64)
+    off = W.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    a = W.random_keys("f64", n, seed=42)
+    v = np.random.default_rng(43).integers(0, 2**64, n, dtype=np.uint64)
+    t, tv, to = to_dev(a), to_dev(v), to_dev(off)
+    pdq.segmented_sort_(t, to, tv, batched=batched)
+    torch.cuda.synchronize()
+    ko, vo = t.cpu().numpy(), tv.cpu().numpy()
+    ref = oracle.segmented_sort(a, off)[0]
+    assert np.array_equal(as_bytes(ko), as_bytes(ref))
+    for s in range(sizes.size):
+        lo, hi = int(off[s]), int(off[s + 1])
+        if hi > lo:
+            x = np.lexsort((v[lo:hi], bits_u64(a[lo:hi])))
+            y = np.lexsort((vo[lo:hi], bits_u64(ko[lo:hi])))
+            assert np.array_equal(v[lo:hi][x], vo[lo:hi][y])
+
+
+def test_plan_and_noalloc_u64_payloads():
+    keys, off, _ = W.segmented_f32(300, max_log2=16, seed=12)
+    n = keys.size
+    v = np.random.default_rng(44).integers(0, 2**64, n, dtype=np.uint64)
+    t, tv, to = to_dev(keys), to_dev(v), to_dev(off)
+    plan = pdq.Plan(t, to, tv, autotune=True)
+    for rep in range(2):
+        t.copy_(to_dev(keys))
+        tv.copy_(to_dev(v))
+        plan.launch()
+        plan.check()
+        ko, vo = t.cpu().numpy(), tv.cpu().numpy()
+        assert np.array_equal(as_bytes(ko), as_bytes(oracle.segmented_sort(keys, off)[0]))
+        assert np.array_equal(np.sort(vo), np.sort(v))
+    plan.destroy()
+    a = W.random_keys("u64", 200003, seed=45)
+    v2 = np.random.default_rng(46).integers(0, 2**64, a.size, dtype=np.uint64)
+    t2, tv2 = to_dev(a), to_dev(v2)
+    pdq.sort_noalloc_(t2, tv2)
+    torch.cuda.synchronize()
+    check_pairs64(a, v2, t2.cpu().numpy(), tv2.cpu().numpy())
+
+
+# ------------------------------------------------------------------ LDS base case: radix and merge forms
+
+@pytest.mark.parametrize("kt", ["u32", "i32", "f32", "u64"])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_base_case_key_spans(kt, pairs):
+    """Segments of 1000 ... 4096 keys whose images span 0, 1, 5, 6, 7, 12,
+    13, 18, 19 and all bits: the radix form takes 0, 1, 1, 1, 2, 2, 3, 3
+    passes, the merge form the rest; both bit-exact against the oracle."""
+    rng = np.random.default_rng(47)
+    spans = [0, 1, 5, 6, 7, 12, 13, 18, 19, 64]
+    sizes, parts = [], []
+    for sp in spans:
+        for size in (1000, 1024, 2048, 2049, 3000, 4095, 4096):
+            lo = int(rng.integers(0, 2**20))
+            width = min(sp, 31)
+            r = rng.integers(0, 2 ** width, size, dtype=np.uint64) if width else np.zeros(size, np.uint64)
+            img = (np.uint64(lo) + r) if sp < 64 else rng.integers(0, 2**63, size, dtype=np.uint64)
+            parts.append(img)
+            sizes.append(size)
+    img = np.concatenate(parts)
+    off = W.offsets_from_sizes(np.array(sizes, dtype=np.int64))
+    dt = W.key_dtype(kt)
+    if dt().itemsize == 4:
+        a = (img & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        if kt == "f32":
+            a = np.where(a >> np.uint32(23) >= np.uint32(0xFF), a & np.uint32(0x3FFFFFFF), a)  # no NaN
+        a = a.view(dt)
+    else:
+        a = img.view(dt)
+    v = W.index_payload(a.size) if pairs else None
+    t, to = to_dev(a), to_dev(off)
+    tv = to_dev(v) if pairs else None
+    pdq.segmented_sort_(t, to, tv)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    assert np.array_equal(as_bytes(out), as_bytes(oracle.segmented_sort(a, off)[0]))
+    if pairs:
+        vo = tv.cpu().numpy()
+        assert np.array_equal(as_bytes(out), as_bytes(a[vo]))
+        assert np.array_equal(np.sort(vo), v)
