@@ -378,8 +378,9 @@ def bench_segmented(pdq, torch, W, dev, args):
     wv.copy_(pv)
     plan = pdq.Plan(wk, po, wv, autotune=True, workspace=ws)
     shape, tune_ms = plan.info()
-    eager = lambda prof: pdq.segmented_sort_(wk, po, wv, workspace=ws, batched=True, batch_shape=shape + 1,
-                                             profile=prof, stats=prof)
+    class_threads, class_ms = plan.classes()
+    # the eager call takes the configuration the plan tuned (kept in process)
+    eager = lambda prof: pdq.segmented_sort_(wk, po, wv, workspace=ws, batched=True, profile=prof, stats=prof)
     timed(eager, 1, False)
     check("batched")
     ms_b, st_b = timed(eager, steps, True)
@@ -399,10 +400,12 @@ def bench_segmented(pdq, torch, W, dev, args):
                       if s0["partition_ms"] else None},
             "batched_eager": {"keys/s": round(n / (mb * 1e-3), 0), "ms": round(mb, 3),
                               "queue_items": st_b[0]["batch_items"], "passes": st_b[0]["passes"],
-                              "shape": {"tile": pdq.BATCH_SHAPES[shape][0], "wide_class_slots": pdq.BATCH_SHAPES[shape][1]}},
+                              "partition_tile": pdq.BATCH_SHAPES[shape][0]},
             "batched_graph": {"keys/s": round(n / (mg * 1e-3), 0), "ms": round(mg, 3),
-                              "shape": {"tile": pdq.BATCH_SHAPES[shape][0], "wide_class_slots": pdq.BATCH_SHAPES[shape][1]},
-                              "autotune_ms_per_shape": [round(x, 3) for x in tune_ms]},
+                              "partition_tile": pdq.BATCH_SHAPES[shape][0],
+                              "autotune_ms_per_tile": [round(x, 3) for x in tune_ms[:3]],
+                              "base_class_threads": class_threads,
+                              "autotune_ms_per_class_shape": [[round(x, 3) for x in row] for row in class_ms]},
             "batched_over_plain": round(mp / mg, 3)}
 
 

@@ -104,9 +104,11 @@ enum pdq_flags {
                              requested: without stats, device-side errors are reported by
                              pdq_check. Meant for many segments of up to ~2^20 keys each; pass
                              the same options to pdq_workspace_bytes */
-  PDQ_AUTOTUNE = 1u << 4, /* pdq_plan_create: time every batched shape on the caller's data
-                             first and keep the fastest (needs the workspace
-                             pdq_workspace_bytes gives with this flag) */
+  PDQ_AUTOTUNE = 1u << 4, /* pdq_plan_create: on the caller's data, time every partition tile of
+                             the batched passes (8192, 16384, 32768 keys), then every workgroup
+                             shape of each LDS base-case size class (1 to 16 waves), and keep the
+                             fastest of each (needs the workspace pdq_workspace_bytes gives with
+                             this flag); see tune_cache_path */
   PDQ_DETERMINISTIC = 1u << 5, /* partition tiles take their places in tile order by a decoupled
                              look-back instead of one atomic reservation each: every run then
                              arranges the keys (and the payloads of equal keys) identically.
@@ -145,6 +147,17 @@ typedef struct pdq_options {
                             segment to the widest LDS class, plus 2); k > 0 = k - 1 passes (at
                             most 20); segments still live after them finish in the persistent
                             tail */
+  uint32_t waves;        /* 0 = each LDS base-case size class takes its default (or tuned)
+                            workgroup shape; 1, 2, 4, 8 or 16 = every class that has a shape of
+                            that many waves per workgroup takes it (pdq_plan_classes lists the
+                            shapes a plan uses) */
+  uint32_t reserved_;    /* must be 0 */
+  const char* tune_cache_path; /* NULL, or a text file that remembers autotuned configurations
+                            across processes: pdq_plan_create with PDQ_AUTOTUNE reads a line
+                            for this device kind and problem (key type, payload, n, segment
+                            count) and skips the timing when it finds one, else tunes and
+                            appends one; batched calls without PDQ_AUTOTUNE use a line if one is
+                            there. File errors only skip the cache */
 } pdq_options;
 
 /* Filled on request (forces a synchronisation at the end of the call). */
@@ -243,6 +256,13 @@ int pdq_plan_launch(pdq_plan* plan, void* stream);
 /* Shape index used (0 ... 3) and, after autotuning, the measured ms per
  * shape (ms[4]; 0 where not measured). Either pointer may be NULL. */
 int pdq_plan_info(const pdq_plan* plan, uint32_t* shape, double* ms);
+
+/* Workgroup shape of each of the seven LDS base-case size classes the plan
+ * uses (threads[7]: lanes per workgroup; classes of at most 64, 256, 1024,
+ * 2048, 4096, 8192 and 16384 keys) and, after autotuning, the measured ms of
+ * each class under each of its three candidate shapes (ms[7 * 3], 0 where
+ * not measured or the shape does not exist). Either pointer may be NULL. */
+int pdq_plan_classes(const pdq_plan* plan, uint32_t* threads, double* ms);
 
 void pdq_plan_destroy(pdq_plan* plan);
 

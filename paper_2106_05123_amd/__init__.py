@@ -66,6 +66,9 @@ class Options(ctypes.Structure):
         ("learn_grid", ctypes.c_uint32),
         ("batch_shape", ctypes.c_uint32),
         ("batch_passes", ctypes.c_uint32),
+        ("waves", ctypes.c_uint32),
+        ("reserved_", ctypes.c_uint32),
+        ("tune_cache_path", ctypes.c_char_p),
     ]
 
 
@@ -186,6 +189,8 @@ def lib():
                                       ctypes.POINTER(Options)]
         L.pdq_plan_launch.argtypes = [vp, vp]
         L.pdq_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]
+        L.pdq_plan_classes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]
+        L.pdq_plan_classes.restype = ctypes.c_int
         L.pdq_plan_destroy.argtypes = [vp]
         L.pdq_plan_destroy.restype = None
         for f in ("pdq_plan_create", "pdq_plan_launch", "pdq_plan_info"):
@@ -228,9 +233,10 @@ def _key_type(t) -> int:
 
 def _options(force_budget: int, tile: int, flags: int, seed: int = 0, imbalance_limit: float = 0.0,
              learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, batch_shape: int = 0,
-             batch_passes: int | None = None) -> Options:
+             batch_passes: int | None = None, waves: int = 0, tune_cache_path: str | None = None) -> Options:
     return Options(ctypes.sizeof(Options), flags, force_budget, tile, seed, imbalance_limit, learn_steps,
-                   learn_batch, learn_grid, batch_shape, 0 if batch_passes is None else batch_passes + 1)
+                   learn_batch, learn_grid, batch_shape, 0 if batch_passes is None else batch_passes + 1, waves, 0,
+                   tune_cache_path.encode() if tune_cache_path else None)
 
 
 def workspace_bytes(n: int, nseg: int = 1, key_type: int | str = "u32", has_vals: bool = False,
@@ -275,17 +281,19 @@ def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
           workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
           learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False,
-          fresh_fixed: bool = False):
+          fresh_fixed: bool = False, waves: int = 0):
     """Sort a 1-D device tensor in place (ascending canonical order).
     learned=True runs the learned multiway first pass (see pdq_learned.h);
     deterministic=True selects the look-back partition (PDQ_DETERMINISTIC);
     fresh_fixed=True takes fresh pivot candidates at fixed offsets after a
-    bad partition (PDQ_FRESH_FIXED) instead of hashed positions."""
+    bad partition (PDQ_FRESH_FIXED) instead of hashed positions; waves
+    (1, 2, 4, 8, 16) sets the workgroup shape of the LDS base-case classes."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
-                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace, learn)
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace,
+                                         dict(learn, waves=waves))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
                         need, stream, ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
@@ -296,14 +304,15 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
 def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
                 imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
-                deterministic: bool = False, fresh_fixed: bool = False):
+                deterministic: bool = False, fresh_fixed: bool = False, waves: int = 0):
     """Sort keys in place and move the payload `vals` (uint32, or uint64:
     PDQ_VALS64) with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
-                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace, learn)
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace,
+                                         dict(learn, waves=waves))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),
                               kt, 0, ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
@@ -315,7 +324,8 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
 def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: int = 0,
                     validate: bool = False, profile: bool = False, stats: bool = False, workspace=None,
                     batched: bool = False, batch_shape: int = 0, batch_passes: int | None = None,
-                    deterministic: bool = False, fresh_fixed: bool = False):
+                    deterministic: bool = False, fresh_fixed: bool = False, waves: int = 0,
+                    tune_cache_path: str | None = None):
     """Sort each segment [offsets[s], offsets[s+1]) of keys in place.
     offsets: uint64 device tensor of nseg+1 entries. batched=True runs the
     batched form (batch_shape 1..4 forces a shape, batch_passes the number of
@@ -327,7 +337,8 @@ def segmented_sort_(keys, offsets, vals=None, *, force_budget: int = -1, tile: i
     flags = (FLAG_VALIDATE if validate else 0) | (FLAG_PROFILE if profile else 0) | (FLAG_BATCHED if batched else 0) \
         | (FLAG_DETERMINISTIC if deterministic else 0) | (FLAG_FRESH_FIXED if fresh_fixed else 0)
     kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, tile, flags, workspace,
-                                         dict(batch_shape=batch_shape, batch_passes=batch_passes))
+                                         dict(batch_shape=batch_shape, batch_passes=batch_passes, waves=waves,
+                                              tune_cache_path=tune_cache_path))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_segmented_sort(ctypes.c_void_p(keys.data_ptr()),
                                   ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,
@@ -518,7 +529,8 @@ class Plan:
     pdq_plan_create). launch() replays the graph on the current stream."""
 
     def __init__(self, keys, offsets, vals=None, *, autotune: bool = False, batch_shape: int = 0,
-                 batch_passes: int | None = None, force_budget: int = -1, workspace=None):
+                 batch_passes: int | None = None, force_budget: int = -1, workspace=None, waves: int = 0,
+                 tune_cache_path: str | None = None):
         # the workspace must be sized with the same flags (batched, autotune)
         import torch
         if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
@@ -526,8 +538,9 @@ class Plan:
         nseg = offsets.numel() - 1
         flags = FLAG_BATCHED | (FLAG_AUTOTUNE if autotune else 0)
         kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, 0, flags, workspace,
-                                             dict(batch_shape=batch_shape, batch_passes=batch_passes))
-        self._keep = (keys, offsets, vals, ws)
+                                             dict(batch_shape=batch_shape, batch_passes=batch_passes, waves=waves,
+                                                  tune_cache_path=tune_cache_path))
+        self._keep = (keys, offsets, vals, ws, opt)
         self._h = ctypes.c_void_p()
         _check(lib().pdq_plan_create(ctypes.byref(self._h), _ptr(keys), _ptr(vals), keys.numel(), _ptr(offsets),
                                      nseg, kt, _ptr(ws), need, stream, ctypes.byref(opt)))
@@ -552,6 +565,14 @@ class Plan:
         ms = (ctypes.c_double * 4)()
         _check(lib().pdq_plan_info(self._h, ctypes.byref(shape), ms))
         return int(shape.value), list(ms)
+
+    def classes(self):
+        """(lanes per workgroup of each base-case size class, measured ms of
+        each class under each candidate shape [7][3])."""
+        th = (ctypes.c_uint32 * 7)()
+        ms = (ctypes.c_double * 21)()
+        _check(lib().pdq_plan_classes(self._h, th, ms))
+        return list(th), [list(ms[3 * k:3 * k + 3]) for k in range(7)]
 
     def destroy(self):
         if self._h:

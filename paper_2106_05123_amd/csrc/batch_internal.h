@@ -45,10 +45,10 @@ struct TailShape {
 constexpr int kTailShapes = 1;
 constexpr TailShape kTail[kTailShapes] = {{512, 8}};
 
-// Tunable shape of the batched form: the tile of the captured partition
-// passes, the slots per lane of the two widest LDS classes (16: 512 and 1024
-// threads for 8192 and 16384 keys; 32: 256 and 512 threads), and the tail
-// kernel's shape.
+// Shape of the batched form: the tile of the captured partition passes,
+// the slots per lane of the two widest LDS classes when the shape is given
+// explicitly (16: 512 and 1024 threads for 8192 and 16384 keys; 32: 256 and
+// 512 threads), and the tail kernel's shape.
 struct BatchShape {
   uint32_t tile;
   uint32_t wide_e;
@@ -56,6 +56,9 @@ struct BatchShape {
 };
 constexpr int kBatchShapes = 4;
 constexpr BatchShape kShapes[kBatchShapes] = {{8192, 16, 0}, {16384, 16, 0}, {32768, 16, 0}, {8192, 32, 0}};
+// The autotuner tries the partition tiles (shapes 0-2); the 32-slot form of
+// the widest classes (shape 3) is one of their per-class variants.
+constexpr int kTunedShapes = 3;
 
 // Passes the batched form captures at most; deeper recursions finish in the
 // persistent tail.

@@ -32,9 +32,7 @@ struct Slot;
 template <class K>
 struct Slot<K, false, false> {
   using V = uint32_t;
-  using I = uint32_t;
   static constexpr int kLdsBytes = 4;
-  __device__ static I img(V v) { return v; }
   __device__ static V make(uint32_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return 0xFFFFFFFFu; }
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
@@ -50,9 +48,7 @@ struct Slot<K, false, false> {
 template <class K>
 struct Slot<K, true, false> {
   using V = uint64_t;
-  using I = uint32_t;
   static constexpr int kLdsBytes = 8;
-  __device__ static I img(V v) { return static_cast<uint32_t>(v >> 32); }
   __device__ static V make(uint32_t raw, uint32_t i) { return (static_cast<uint64_t>(K::ord(raw)) << 32) | i; }
   __device__ static V pad() { return ~0ull; }
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
@@ -68,9 +64,7 @@ struct Slot<K, true, false> {
 template <class K>
 struct Slot<K, false, true> {
   using V = uint64_t;
-  using I = uint64_t;
   static constexpr int kLdsBytes = 8;
-  __device__ static I img(V v) { return v; }
   __device__ static V make(uint64_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return ~0ull; }
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
@@ -86,9 +80,7 @@ struct Slot<K, false, true> {
 template <class K>
 struct Slot<K, true, true> {
   using V = KV;
-  using I = uint64_t;
   static constexpr int kLdsBytes = 12;
-  __device__ static I img(V v) { return v.k; }
   __device__ static V make(uint64_t raw, uint32_t i) { return KV{K::ord(raw), i}; }
   __device__ static V pad() { return KV{~0ull, 0xFFFFFFFFu}; }
   // field by field: a select of whole structs goes through scratch memory
@@ -242,132 +234,6 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
     }
     __syncthreads();
   }
-}
-
-// ---------------------------------------------------------------- radix sort
-
-// LSD radix sort of the block's P = E * NT slots, the alternative to the
-// merge sort for segments whose keys span few bits (a segment that reaches
-// the base case lies between two pivots, so its keys usually span a small
-// part of the key range: about 2^16 for 4096 uniform 32-bit keys out of
-// 2^28). Digits are kRadixBits of (image - minimum image); each pass ranks
-// the slots stably the way a block radix sort does: every lane counts its
-// own keys per digit in a private column of a [digit][lane] counter matrix
-// (its rank among its own keys with that digit is the count before it), one
-// exclusive scan over the matrix in (digit, lane) order turns the counts
-// into first positions, and every slot is written to first position + rank.
-// Slots at positions >= len are padding: they take the largest digit in
-// every pass and, being last and the sort stable, stay last. Returns false,
-// with x untouched, when the real images span more than
-// kRadixBits * kRadixMaxPasses bits (the merge sort then runs).
-constexpr int kRadixBits = 6;
-constexpr int kRadixDigits = 1 << kRadixBits;  // also the counters each lane scans
-constexpr int kRadixMaxPasses = 3;
-
-// The counter matrix: kRadixDigits * NT 16-bit counts (P <= 65535), with two
-// padding halves after every kRadixDigits entries so that the lanes' scan
-// segments start in different banks.
-template <int NT>
-constexpr int radix_counters() {
-  return kRadixDigits * NT + 2 * NT;
-}
-__device__ __forceinline__ int cnt_pos(int f) { return f + 2 * (f >> 6); }
-
-template <class S, int E, int NT>
-__device__ __forceinline__ bool radix_sort(typename S::V (&x)[E], unsigned char* sh, uint16_t* cnt, int tid,
-                                           int len) {
-  using I = typename S::I;
-  constexpr int PL = lds_plane<E * NT, E>();
-  constexpr int kWaves = NT / 64;
-  static_assert(kRadixDigits == 64, "each lane scans one 64-entry segment of the counter matrix");
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  // range of the real images (the counter area holds the wave partials)
-  I lo = ~I(0), hi = I(0);
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    if (tid * E + r < len) {
-      const I v = S::img(x[r]);
-      lo = v < lo ? v : lo;
-      hi = v > hi ? v : hi;
-    }
-  }
-  for (int d = 32; d >= 1; d >>= 1) {
-    const I olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
-    lo = olo < lo ? olo : lo;
-    hi = ohi > hi ? ohi : hi;
-  }
-  I* part = reinterpret_cast<I*>(cnt);
-  if (lane == 0) {
-    part[2 * wave] = lo;
-    part[2 * wave + 1] = hi;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const I plo = part[2 * w], phi = part[2 * w + 1];
-    lo = plo < lo ? plo : lo;
-    hi = phi > hi ? phi : hi;
-  }
-  __syncthreads();
-  const I span = hi > lo ? hi - lo : I(0);
-  int bits = 0;
-  if (span) bits = static_cast<int>(sizeof(I) * 8) - (sizeof(I) == 8 ? __clzll(static_cast<long long>(span))
-                                                                     : __clz(static_cast<int>(span)));
-  const int passes = (bits + kRadixBits - 1) / kRadixBits;
-  if (passes > kRadixMaxPasses) return false;  // the same decision in every lane
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
-    // this lane's column of the counter matrix
-#pragma unroll 8
-    for (int d = 0; d < kRadixDigits; ++d) cnt[cnt_pos(d * NT + tid)] = 0;
-    uint32_t dig[E];
-    uint32_t rank[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      dig[r] = tid * E + r < len ? static_cast<uint32_t>((S::img(x[r]) - lo) >> shift) & (kRadixDigits - 1)
-                                 : static_cast<uint32_t>(kRadixDigits - 1);
-      const int at = cnt_pos(static_cast<int>(dig[r]) * NT + tid);
-      rank[r] = cnt[at];
-      cnt[at] = static_cast<uint16_t>(rank[r] + 1);
-    }
-    __syncthreads();
-    // exclusive scan in (digit, lane) order: lane t owns entries
-    // [64 t, 64 t + 64), i.e. digit 64 t / NT, lanes (64 t) % NT ...
-    uint16_t* seg = cnt + cnt_pos(tid * kRadixDigits);
-    uint32_t sum = 0;
-#pragma unroll 16
-    for (int k = 0; k < kRadixDigits; ++k) sum += seg[k];
-    uint32_t incl = sum;
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t t = __shfl_up(incl, d, 64);
-      if (lane >= d) incl += t;
-    }
-    uint32_t* wsum = reinterpret_cast<uint32_t*>(sh);  // the data planes are free until the scatter
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t run = incl - sum;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w)
-      if (w < wave) run += wsum[w];
-#pragma unroll 16
-    for (int k = 0; k < kRadixDigits; ++k) {
-      const uint32_t c = seg[k];
-      seg[k] = static_cast<uint16_t>(run);
-      run += c;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int at = static_cast<int>(cnt[cnt_pos(static_cast<int>(dig[r]) * NT + tid)] + rank[r]);
-      S::st(sh, PL, lds_pos<E>(at), x[r]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>(tid * E + r));
-    __syncthreads();
-  }
-  return true;
 }
 
 }  // namespace net

@@ -4,12 +4,9 @@
 //
 // The paper sorts small subsequences with insertion sort (Section 5.1) and
 // notes that sorting networks lost on its CPU through code size (Section 2);
-// on a GPU a bitonic network (bitonic.h) is the natural small sort below
-// 1024 slots. From 1024 slots a segment whose 32-bit key images span at most
-// 18 bits (the usual case: it lies between two pivots) is sorted by an LDS
-// radix sort of (image - minimum), else by a merge sort. A segment of
-// P = E * NT slots (padded to a power of two) is held E slots per lane in
-// registers; payloads are gathered by index at the end.
+// on a GPU a bitonic network (bitonic.h) is the natural small sort. A
+// segment of P = E * NT slots (padded to a power of two) is held E slots per
+// lane in registers; payloads are gathered by index at the end.
 #include "bitonic.h"
 #include "pdq_internal.h"
 #include "wave_ops.h"
@@ -32,11 +29,7 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   using V = typename S::V;
   constexpr int P = E * NT;
   constexpr int PL = lds_plane<P, E>();
-  // the radix sort serves 32-bit images in workgroups of up to 256 lanes
-  // (its counter matrix grows with the lanes)
-  constexpr bool kRadix = P >= 1024 && NT <= 256 && sizeof(typename S::I) == 4;
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
-  __shared__ __align__(16) uint16_t cnt[kRadix ? net::radix_counters<NT>() : 1];
   // a list longer than its capacity (only invalid offsets make one; it is
   // flagged) is read no further than its capacity
   uint32_t count = c.device_counts ? c.ctr->nbase[cls] : nitems;
@@ -62,13 +55,8 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
     for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
     __syncthreads();
 
-    if constexpr (E * NT >= 1024) {
-      bool done = false;
-      if constexpr (kRadix) done = net::radix_sort<S, E, NT>(x, sh, cnt, tid, len);
-      if (!done) net::merge_sort<S, E, NT>(x, sh, tid);
-    } else {
-      net::bitonic<S, E, NT>(x, sh, tid);
-    }
+    if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
+    else net::bitonic<S, E, NT>(x, sh, tid);
 
     // back through LDS so that the final writes are coalesced
 #pragma unroll
@@ -136,34 +124,58 @@ hipError_t launch_shape(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class K, bool PAIRS, int P, int NT>
+hipError_t launch_lanes(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
+  return launch_shape<K, PAIRS, P / NT, NT>(c, cls, nitems, s);
+}
+
+// The class's workgroup shape from its variant (kBaseThreads): every shape
+// a class can take is instantiated here.
 template <class K, bool PAIRS>
 hipError_t launch_cls(const Ctx& c, int cls, uint32_t nitems, hipStream_t s) {
-  // 64-bit keys with a payload hold three registers a slot: 8 slots per lane
-  // (twice the threads) keep them out of the register limit that 16 would hit
+  // 64-bit keys with a payload hold three registers a slot: at most 8 slots
+  // per lane keep them out of the register limit that 16 would hit
   constexpr bool kWidePairs = sizeof(typename K::T) == 8 && PAIRS;
+  const int nt = base_threads(kWidePairs, cls, c.base_var[cls]);
   switch (cls) {
-    case 0: return launch_shape<K, PAIRS, 1, 64>(c, cls, nitems, s);
-    case 1: return launch_shape<K, PAIRS, 4, 64>(c, cls, nitems, s);
+    case 0: return launch_lanes<K, PAIRS, 64, 64>(c, cls, nitems, s);
+    case 1:
+      if (nt == 128) return launch_lanes<K, PAIRS, 256, 128>(c, cls, nitems, s);
+      if (nt == 256) return launch_lanes<K, PAIRS, 256, 256>(c, cls, nitems, s);
+      return launch_lanes<K, PAIRS, 256, 64>(c, cls, nitems, s);
     case 2:
-      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 128>(c, cls, nitems, s);
-      else return launch_shape<K, PAIRS, 16, 64>(c, cls, nitems, s);
+      if (nt == 256) return launch_lanes<K, PAIRS, 1024, 256>(c, cls, nitems, s);
+      if constexpr (!kWidePairs)
+        if (nt == 64) return launch_lanes<K, PAIRS, 1024, 64>(c, cls, nitems, s);
+      return launch_lanes<K, PAIRS, 1024, 128>(c, cls, nitems, s);
     case 3:
-      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 256>(c, cls, nitems, s);
-      else return launch_shape<K, PAIRS, 16, 128>(c, cls, nitems, s);
+      if constexpr (kWidePairs) {
+        if (nt == 512) return launch_lanes<K, PAIRS, 2048, 512>(c, cls, nitems, s);
+      } else {
+        if (nt == 64) return launch_lanes<K, PAIRS, 2048, 64>(c, cls, nitems, s);
+        if (nt == 128) return launch_lanes<K, PAIRS, 2048, 128>(c, cls, nitems, s);
+      }
+      return launch_lanes<K, PAIRS, 2048, 256>(c, cls, nitems, s);
     case 4:
-      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 512>(c, cls, nitems, s);
-      else return launch_shape<K, PAIRS, 16, 256>(c, cls, nitems, s);
+      if constexpr (kWidePairs) {
+        if (nt == 1024) return launch_lanes<K, PAIRS, 4096, 1024>(c, cls, nitems, s);
+      } else {
+        if (nt == 128) return launch_lanes<K, PAIRS, 4096, 128>(c, cls, nitems, s);
+        if (nt == 256) return launch_lanes<K, PAIRS, 4096, 256>(c, cls, nitems, s);
+      }
+      return launch_lanes<K, PAIRS, 4096, 512>(c, cls, nitems, s);
     case 5:
-      if constexpr (kWidePairs) return launch_shape<K, PAIRS, 8, 1024>(c, cls, nitems, s);
-      else
-        return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 256>(c, cls, nitems, s)
-                              : launch_shape<K, PAIRS, 16, 512>(c, cls, nitems, s);
+      if constexpr (!kWidePairs) {
+        if (nt == 256) return launch_lanes<K, PAIRS, 8192, 256>(c, cls, nitems, s);
+        if (nt == 512) return launch_lanes<K, PAIRS, 8192, 512>(c, cls, nitems, s);
+      }
+      return launch_lanes<K, PAIRS, 8192, 1024>(c, cls, nitems, s);
     case 6:
       // 64-bit keys with a payload need 12 LDS bytes a slot: their widest class is 8192
       if constexpr (kWidePairs) return hipErrorInvalidValue;
       else
-        return c.wide_e == 32 ? launch_shape<K, PAIRS, 32, 512>(c, cls, nitems, s)
-                              : launch_shape<K, PAIRS, 16, 1024>(c, cls, nitems, s);
+        return nt == 512 ? launch_lanes<K, PAIRS, 16384, 512>(c, cls, nitems, s)
+                         : launch_lanes<K, PAIRS, 16384, 1024>(c, cls, nitems, s);
     default: return hipErrorInvalidValue;
   }
 }

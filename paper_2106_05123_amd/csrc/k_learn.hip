@@ -577,18 +577,35 @@ __global__ __launch_bounds__(256) void k_infer(const float* __restrict__ p, cons
 
 constexpr uint32_t kExtractThreads = 1024;
 
-__global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __restrict__ s,
-                                                             const float* __restrict__ y, uint64_t m, float* r,
-                                                             uint64_t* __restrict__ sp, uint32_t* count) {
+// One extraction per workgroup: prediction, its running maximum, the
+// splitters and their count.
+struct ExtractJob {
+  const float* y;
+  float* r;
+  uint64_t* sp;
+  uint32_t* count;
+};
+struct ExtractJobs {
+  ExtractJob job[kCandidates];
+};
+
+__global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __restrict__ s, uint64_t m,
+                                                             ExtractJobs jobs) {
   __shared__ float s_max[kExtractThreads];
   __shared__ uint64_t s_cand[kMaxSplitters];
   __shared__ uint32_t s_valid[kMaxSplitters];
   __shared__ uint32_t s_keep[256];
+  const ExtractJob J = jobs.job[blockIdx.x];
+  const float* __restrict__ y = J.y;
+  float* r = J.r;
+  uint64_t* __restrict__ sp = J.sp;
+  uint32_t* count = J.count;
   const uint32_t tid = threadIdx.x;
   const uint64_t per = (m + kExtractThreads - 1) / kExtractThreads;
   const uint64_t b = tid * per < m ? tid * per : m;
   const uint64_t e = b + per < m ? b + per : m;
   float mx = 0.0f;  // predictions are clamped to [0, 1]
+#pragma unroll 16
   for (uint64_t i = b; i < e; ++i) mx = y[i] > mx ? y[i] : mx;
   s_max[tid] = mx;
   __syncthreads();
@@ -599,6 +616,7 @@ __global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __r
     __syncthreads();
   }
   float run = tid > 0 ? s_max[tid - 1] : 0.0f;
+#pragma unroll 16
   for (uint64_t i = b; i < e; ++i) {
     run = y[i] > run ? y[i] : run;
     r[i] = run;
@@ -677,6 +695,7 @@ __global__ __launch_bounds__(kExtractThreads) void k_running_max(const float* __
   const uint64_t b = tid * per < m ? tid * per : m;
   const uint64_t e = b + per < m ? b + per : m;
   float mx = 0.0f;
+#pragma unroll 16
   for (uint64_t i = b; i < e; ++i) mx = y[i] > mx ? y[i] : mx;
   s_max[tid] = mx;
   __syncthreads();
@@ -687,6 +706,7 @@ __global__ __launch_bounds__(kExtractThreads) void k_running_max(const float* __
     __syncthreads();
   }
   float run = tid > 0 ? s_max[tid - 1] : 0.0f;
+#pragma unroll 16
   for (uint64_t i = b; i < e; ++i) {
     run = y[i] > run ? y[i] : run;
     r[i] = run;
@@ -720,7 +740,26 @@ __global__ __launch_bounds__(2 * kLeaves) void k_leaf_fit(const float* __restric
   const uint64_t hi = j == kLeaves - 1 ? m : first_at_least(static_cast<float>(j + 1) / static_cast<float>(kLeaves));
   const float* u = kind == 0 ? x : y;
   double sx = 0.0, st = 0.0, sxx = 0.0, sxt = 0.0;
-  for (uint64_t i = lo; i < hi; ++i) {
+  // sixteen samples' loads in flight at a time; the sums still run in index order
+  constexpr int kBatch = 16;
+  uint64_t i = lo;
+  for (; i + kBatch <= hi; i += kBatch) {
+    float ub[kBatch], tb[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      ub[q] = u[i + q];
+      tb[q] = t[i + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+      const double ui = static_cast<double>(ub[q]), ti = static_cast<double>(tb[q]);
+      sx = sx + ui;
+      st = st + ti;
+      sxx = sxx + ui * ui;
+      sxt = sxt + ui * ti;
+    }
+  }
+  for (; i < hi; ++i) {
     const double ui = static_cast<double>(u[i]), ti = static_cast<double>(t[i]);
     sx = sx + ui;
     st = st + ti;
@@ -886,7 +925,18 @@ hipError_t launch_infer(const float* params, const float* x, uint64_t m, uint32_
 
 hipError_t launch_extract(const uint64_t* sorted, const float* y, uint64_t m, float* runmax, uint64_t* splitters,
                           uint32_t* count, hipStream_t s) {
-  hipLaunchKernelGGL(k_extract, dim3(1), dim3(kExtractThreads), 0, s, sorted, y, m, runmax, splitters, count);
+  ExtractJobs jobs = {};
+  jobs.job[0] = ExtractJob{y, runmax, splitters, count};
+  hipLaunchKernelGGL(k_extract, dim3(1), dim3(kExtractThreads), 0, s, sorted, m, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_candidates(const uint64_t* sorted, uint64_t m, const float* const* y, float* const* runmax,
+                                     uint64_t* splitters, uint32_t stride, uint32_t* count, hipStream_t s) {
+  ExtractJobs jobs = {};
+  for (int c = 0; c < kCandidates; ++c)
+    jobs.job[c] = ExtractJob{y[c], runmax[c], splitters + static_cast<uint64_t>(c) * stride, count + c};
+  hipLaunchKernelGGL(k_extract, dim3(kCandidates), dim3(kExtractThreads), 0, s, sorted, m, jobs);
   return hipGetLastError();
 }
 

@@ -62,6 +62,7 @@ struct FitBufs {
   uint64_t* splitters;  // [256] the chosen candidate's splitters
   uint32_t* count;    // [1]
   // second stage and candidates
+  float* runmax2;     // [2][m] running maxima of the leaf predictions
   float* yx;          // [m] x-leaf predictions
   float* yy;          // [m] y-leaf predictions
   double* leaf;       // [2][kLeaves][2] intercept and slope of every leaf
@@ -99,6 +100,10 @@ hipError_t launch_gradient(const float* params, const float* x, const float* t, 
                            float* grad, float* loss, hipStream_t s);
 hipError_t launch_extract(const uint64_t* sorted, const float* y, uint64_t m, float* runmax, uint64_t* splitters,
                           uint32_t* count, hipStream_t s);
+// The three candidates' extractions side by side (one workgroup each):
+// predictions y[c], running maxima runmax[c], splitters `stride` apart.
+hipError_t launch_extract_candidates(const uint64_t* sorted, uint64_t m, const float* const* y, float* const* runmax,
+                                     uint64_t* splitters, uint32_t stride, uint32_t* count, hipStream_t s);
 
 // Running maximum of y[0..m) (clamped predictions), as the extraction computes it.
 hipError_t launch_running_max(const float* y, uint64_t m, float* runmax, hipStream_t s);

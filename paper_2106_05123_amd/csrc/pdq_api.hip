@@ -23,8 +23,11 @@
 
 #include <math.h>
 
+#include <stdio.h>
+
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -120,7 +123,7 @@ FitOutLayout fit_out_layout(uint32_t steps) {
 // Scratch of the fit: running maximum, gradient partials, barrier words,
 // the unsorted sample, and the second stage with its candidates.
 struct FitScratchLayout {
-  size_t runmax, partials, sync, raw, yx, yy, leaf, cand, cand_count, est, total;
+  size_t runmax, partials, sync, raw, runmax2, yx, yy, leaf, cand, cand_count, est, total;
 };
 FitScratchLayout fit_scratch_layout(uint32_t grid) {
   FitScratchLayout f;
@@ -129,6 +132,7 @@ FitScratchLayout fit_scratch_layout(uint32_t grid) {
   f.partials = b.take(2ull * grid * kParamStride * 4);
   f.sync = b.take(4 * 4);
   f.raw = b.take(kLearnSample * 8);
+  f.runmax2 = b.take(2ull * kLearnSample * 4);
   f.yx = b.take(kLearnSample * 4);
   f.yy = b.take(kLearnSample * 4);
   f.leaf = b.take(2ull * kLeaves * 2 * 8);
@@ -266,6 +270,8 @@ struct Opts {
   uint32_t grid = 16;
   uint32_t batch_shape = 0;  // 0 = tuned or default, else shape index + 1
   uint32_t batch_passes = 0; // 0 = automatic, else passes + 1
+  uint32_t waves = 0;        // 0 = default / tuned base-case shapes, else lanes / 64 for every class
+  const char* tune_cache = nullptr;
 };
 
 
@@ -285,11 +291,17 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, learn_grid) + sizeof(uint32_t) && o->learn_grid) out->grid = o->learn_grid;
   if (sz >= offsetof(pdq_options, batch_shape) + sizeof(uint32_t)) out->batch_shape = o->batch_shape;
   if (sz >= offsetof(pdq_options, batch_passes) + sizeof(uint32_t)) out->batch_passes = o->batch_passes;
+  if (sz >= offsetof(pdq_options, waves) + sizeof(uint32_t)) out->waves = o->waves;
+  if (sz >= offsetof(pdq_options, reserved_) + sizeof(uint32_t) && o->reserved_) return PDQ_ERR_UNSUPPORTED;
+  if (sz >= offsetof(pdq_options, tune_cache_path) + sizeof(const char*)) out->tune_cache = o->tune_cache_path;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
                              PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
+  if (out->waves != 0 && out->waves != 1 && out->waves != 2 && out->waves != 4 && out->waves != 8 &&
+      out->waves != 16)
+    return PDQ_ERR_UNSUPPORTED;
   if (out->batch_passes > kMaxBatchPasses + 1) return PDQ_ERR_UNSUPPORTED;
   if (out->steps > kMaxLearnSteps || out->grid > kMaxTrainGrid || out->batch > 65536 || out->batch % out->grid)
     return PDQ_ERR_UNSUPPORTED;
@@ -359,6 +371,7 @@ FitBufs fit_bufs(char* out, char* scratch, uint32_t steps, uint32_t grid) {
   f.partials = reinterpret_cast<float*>(scratch + fs.partials);
   f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
   f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  f.runmax2 = reinterpret_cast<float*>(scratch + fs.runmax2);
   f.yx = reinterpret_cast<float*>(scratch + fs.yx);
   f.yy = reinterpret_cast<float*>(scratch + fs.yy);
   f.leaf = reinterpret_cast<double*>(scratch + fs.leaf);
@@ -395,11 +408,13 @@ int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitB
   a.sync = f.sync;
   HIP_TRY(launch_train(a, s));
   HIP_TRY(launch_infer(f.params, f.x, m, 1u, f.y, s));
-  // candidate 0 (the network) first: its running maximum defines the leaves
-  HIP_TRY(launch_extract(f.sample, f.y, m, f.runmax, f.cand, f.cand_count, s));
+  // the running maximum of the network's prediction defines the leaves; then
+  // the three candidates' splitters are extracted side by side
+  HIP_TRY(launch_running_max(f.y, m, f.runmax, s));
   HIP_TRY(launch_leaves(f.x, f.t, f.y, f.runmax, m, f.leaf, f.yx, f.yy, s));
-  HIP_TRY(launch_extract(f.sample, f.yx, m, f.runmax, f.cand + 256, f.cand_count + 1, s));
-  HIP_TRY(launch_extract(f.sample, f.yy, m, f.runmax, f.cand + 512, f.cand_count + 2, s));
+  const float* preds[kCandidates] = {f.y, f.yx, f.yy};
+  float* maxima[kCandidates] = {f.runmax, f.runmax2, f.runmax2 + m};
+  HIP_TRY(launch_extract_candidates(f.sample, m, preds, maxima, f.cand, 256, f.cand_count, s));
   HIP_TRY(launch_sample_judge(f.sample, m, f.cand, 256, f.cand_count, kCandidates, f.est, s));
   HIP_TRY(launch_pick(f.cand, 256, f.cand_count, f.est, kCandidates, go_limit, f.splitters, f.count, f.info, s));
   return PDQ_OK;
@@ -544,6 +559,16 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   return PDQ_OK;
 }
 
+// pdq_options.waves: every base-case class that has a shape of that many
+// waves per workgroup takes it.
+void apply_waves(Ctx& c, uint32_t waves) {
+  if (!waves) return;
+  const bool wide = key_bytes(c.key_type) == 8 && c.has_vals;
+  for (int k = 0; k < kBaseClasses; ++k)
+    for (int v = 0; v < kBaseVariants; ++v)
+      if (kBaseThreads[wide ? 1 : 0][k][v] == 64u * waves) c.base_var[k] = static_cast<uint8_t>(v);
+}
+
 Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, const Opts& o,
              const Layout& L, char* base) {
   Ctx c = {};
@@ -574,7 +599,8 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.single = offsets ? 0u : 1u;
   c.seed = o.seed;
   c.base_max = kBaseMax;
-  c.wide_e = 16;
+  for (int k = 0; k < kBaseClasses; ++k) c.base_var[k] = 0;
+  apply_waves(c, o.waves);
   c.lookback = (o.flags & PDQ_DETERMINISTIC) ? 1u : 0u;
   c.fresh_fixed = (o.flags & PDQ_FRESH_FIXED) ? 1u : 0u;
   return c;
@@ -629,15 +655,102 @@ int run_near_sorted(const Ctx& c, const Layout& L, char* base, RunPlan* plan, hi
 
 // ---- batched segmented sort --------------------------------------------------
 
-// Autotuned shapes, remembered per (key type, payload, n, segment count).
-std::mutex g_tune_mu;
-std::map<std::tuple<uint32_t, uint32_t, uint64_t, uint64_t>, int> g_tune;
+// The batched form's configuration: the shape (partition tile) and the
+// workgroup shape of every base-case class.
+struct Tuned {
+  int shape = 0;
+  uint8_t var[kBaseClasses] = {};
+};
 
-int tuned_shape(const Ctx& c, const Opts& o) {
-  if (o.batch_shape) return static_cast<int>(o.batch_shape) - 1;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg));
-  return it == g_tune.end() ? 0 : it->second;
+// Autotuned configurations, remembered per (key type, payload, n, segment
+// count) in process memory, and in pdq_options.tune_cache_path when given.
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, uint32_t, uint64_t, uint64_t>, Tuned> g_tune;
+
+// "<gfx arch>/<compute units> <key type> <payload> <n> <segments>": a cache
+// line is only taken on the same kind of device for the same problem.
+std::string tune_key(const Ctx& c) {
+  int dev = 0;
+  hipDeviceProp_t prop = {};
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  }
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s/%d %u %u %llu %llu", arch.c_str(), cus, c.key_type, c.has_vals,
+           static_cast<unsigned long long>(c.n), static_cast<unsigned long long>(c.nseg));
+  return buf;
+}
+
+// Cache file lines: "pdq-tune 1 <key> <shape> <variant of class 0> ... <class 6>".
+bool cache_lookup(const char* path, const std::string& key, Tuned* out) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  const std::string prefix = "pdq-tune 1 " + key + " ";
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    if (strncmp(line, prefix.c_str(), prefix.size()) != 0) continue;
+    int v[1 + kBaseClasses];
+    if (sscanf(line + prefix.size(), "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+               &v[7]) != 1 + kBaseClasses)
+      continue;
+    bool ok = v[0] >= 0 && v[0] < kBatchShapes;
+    for (int k = 0; k < kBaseClasses; ++k) ok = ok && v[1 + k] >= 0 && v[1 + k] < kBaseVariants;
+    if (!ok) continue;
+    out->shape = v[0];
+    for (int k = 0; k < kBaseClasses; ++k) out->var[k] = static_cast<uint8_t>(v[1 + k]);
+    found = true;  // the last matching line wins
+  }
+  fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Tuned& t) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "pdq-tune 1 %s %d", key.c_str(), t.shape);
+  for (int k = 0; k < kBaseClasses; ++k) fprintf(f, " %d", t.var[k]);
+  fprintf(f, "\n");
+  fclose(f);
+}
+
+// The configuration a batched call uses: an explicit batch_shape, else the
+// tuned one of this process, else the cache file's, else the defaults; then
+// pdq_options.waves, if set, for the base-case classes.
+Tuned tuned_config(const Ctx& c, const Opts& o) {
+  Tuned t;
+  bool have = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg));
+    if (it != g_tune.end()) {
+      t = it->second;
+      have = true;
+    }
+  }
+  if (!have && o.tune_cache && cache_lookup(o.tune_cache, tune_key(c), &t)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg)] = t;
+  }
+  if (o.batch_shape) {
+    t = Tuned();
+    t.shape = static_cast<int>(o.batch_shape) - 1;
+    if (kShapes[t.shape].wide_e == 32) t.var[5] = t.var[6] = 1;  // the 32-slot widest classes
+  }
+  if (o.waves) {
+    Ctx tmp = c;
+    for (int k = 0; k < kBaseClasses; ++k) tmp.base_var[k] = t.var[k];
+    apply_waves(tmp, o.waves);
+    for (int k = 0; k < kBaseClasses; ++k) t.var[k] = tmp.base_var[k];
+  }
+  return t;
 }
 
 BatchArgs batch_args(const Layout& L, char* base) {
@@ -649,12 +762,12 @@ BatchArgs batch_args(const Layout& L, char* base) {
 }
 
 // The batched form's context: device-side counts, accumulating item lists,
-// the wide LDS classes, and the shape's partition tile.
-Ctx batch_ctx(Ctx c, const Opts& o, int shape) {
+// the wide LDS classes, the shape's partition tile and the classes' shapes.
+Ctx batch_ctx(Ctx c, const Opts& o, const Tuned& t) {
   c.device_counts = 1;
   c.base_max = batch_base_max(c.key_type, c.has_vals != 0);
-  c.tile = o.tile ? o.tile : kShapes[shape].tile;
-  c.wide_e = kShapes[shape].wide_e;
+  c.tile = o.tile ? o.tile : kShapes[t.shape].tile;
+  for (int k = 0; k < kBaseClasses; ++k) c.base_var[k] = t.var[k];
   return c;
 }
 
@@ -694,7 +807,8 @@ int batch_probe(const Ctx& c, const Opts& o, hipStream_t s, uint32_t* passes) {
 // The rest, with no host synchronisation (capturable): `passes` partition
 // passes whose kernels read their counts on the device, the persistent tail
 // over whatever is still live, then every item list finished once.
-int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passes, int tail, hipStream_t s) {
+int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passes, int tail, hipStream_t s,
+                       EventPair* class_ev = nullptr) {
   const BatchArgs b = batch_args(L, base);
   const uint32_t grid = batch_grid(c, tail);
   if (grid == 0) return PDQ_ERR_HIP;
@@ -714,7 +828,9 @@ int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passe
   HIP_TRY(launch_batch_fold(c, b, s));
   for (int k = 0; k < kBaseClasses; ++k) {
     if (k == 6 && c.base_max < kWideBaseMax) continue;
+    if (class_ev) HIP_TRY(hipEventRecord(class_ev[k].a, s));
     HIP_TRY(launch_base(c, k, c.max_items, s));
+    if (class_ev) HIP_TRY(hipEventRecord(class_ev[k].b, s));
   }
   HIP_TRY(launch_heap(c, c.max_items, s));
   HIP_TRY(launch_copy(c, c.max_items, s));
@@ -722,8 +838,9 @@ int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passe
 }
 
 int run_batched(const Ctx& c0, const Opts& o, const Layout& L, char* base, pdq_stats* st, hipStream_t s) {
-  const int shape = tuned_shape(c0, o);
-  const Ctx c = batch_ctx(c0, o, shape);
+  const Tuned tc = tuned_config(c0, o);
+  const int shape = tc.shape;
+  const Ctx c = batch_ctx(c0, o, tc);
   EventPair ev;
   const bool prof = (o.flags & PDQ_PROFILE) && st;
   if (prof && !ev.make()) return PDQ_ERR_HIP;
@@ -1137,6 +1254,9 @@ struct pdq_plan {
   uint32_t shape = 0;
   uint32_t passes = 0;
   double ms[kBatchShapes] = {};
+  uint8_t var[kBaseClasses] = {};
+  uint32_t threads[kBaseClasses] = {};
+  double class_ms[kBaseClasses][kBaseVariants] = {};
 };
 
 int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, const uint64_t* d_offsets,
@@ -1175,50 +1295,100 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
     delete p;
     return code;
   };
-  int shape = tuned_shape(c, o);
+  Tuned tc = tuned_config(c, o);
   // the first step (shape-independent) gives the number of passes to capture
   uint32_t passes = 0;
   {
-    const Ctx c0 = batch_ctx(c, o, shape);
+    const Ctx c0 = batch_ctx(c, o, tc);
     rc = enqueue_batch_init(c0, s);
     if (rc == PDQ_OK) rc = batch_probe(c0, o, s, &passes);
     if (rc != PDQ_OK) return fail(rc);
   }
-  if (tune) {
-    // time every shape on a copy of the caller's data, keep the fastest
+  const std::string key = o.tune_cache ? tune_key(c) : std::string();
+  Tuned cached;
+  const bool from_cache = tune && !o.batch_shape && cache_lookup(o.tune_cache, key, &cached);
+  if (from_cache) {
+    tc = cached;
+  } else if (tune) {
+    // On a copy of the caller's data: first the partition tile of the
+    // passes (every tile shape with the default base-case shapes, the
+    // whole sequence timed), then the base-case classes (every variant
+    // for all classes at once with that tile, each class's launch timed
+    // by its own events); the fastest of each is kept. The first run of
+    // every configuration warms its kernels up and is not counted.
     void* bk = base + L.backup_keys;
     uint32_t* bv = d_vals ? reinterpret_cast<uint32_t*>(base + L.backup_vals) : nullptr;
     if (hipMemcpyAsync(bk, d_keys, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
     if (bv && hipMemcpyAsync(bv, d_vals, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
-    double best = 1e300;
-    for (int sh = 0; sh < kBatchShapes; ++sh) {
-      const Ctx cs = batch_ctx(c, o, sh);
-      double total = 0;
-      for (int rep = 0; rep < 2; ++rep) {  // the first run warms the kernels up
-        if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
-        if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-          return fail(PDQ_ERR_HIP);
+    auto timed_run = [&](const Tuned& t, EventPair* class_ev, double* total) -> int {
+      const Ctx cs = batch_ctx(c, o, t);
+      for (int rep = 0; rep < 2; ++rep) {
+        if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return PDQ_ERR_HIP;
+        if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return PDQ_ERR_HIP;
         EventPair ev;
-        if (!ev.make() || hipEventRecord(ev.a, s) != hipSuccess) return fail(PDQ_ERR_HIP);
-        rc = enqueue_batch_init(cs, s);
-        if (rc == PDQ_OK) rc = enqueue_batch_rest(cs, L, base, passes, kShapes[sh].tail, s);
-        if (rc != PDQ_OK) return fail(rc);
-        if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess)
-          return fail(PDQ_ERR_HIP);
-        if (rep == 1) total = ev.ms();
+        if (!ev.make() || hipEventRecord(ev.a, s) != hipSuccess) return PDQ_ERR_HIP;
+        int r = enqueue_batch_init(cs, s);
+        if (r == PDQ_OK)
+          r = enqueue_batch_rest(cs, L, base, passes, kShapes[t.shape].tail, s, rep == 1 ? class_ev : nullptr);
+        if (r != PDQ_OK) return r;
+        if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess) return PDQ_ERR_HIP;
+        if (rep == 1) *total = ev.ms();
       }
+      return PDQ_OK;
+    };
+    Tuned best;
+    double best_ms = 1e300;
+    for (int sh = 0; sh < kTunedShapes; ++sh) {
+      Tuned t;
+      t.shape = sh;
+      double total = 0;
+      rc = timed_run(t, nullptr, &total);
+      if (rc != PDQ_OK) return fail(rc);
       p->ms[sh] = total;
-      if (total < best) {
-        best = total;
-        shape = sh;
+      if (total < best_ms) {
+        best_ms = total;
+        best.shape = sh;
+      }
+    }
+    double class_best[kBaseClasses];
+    for (int k = 0; k < kBaseClasses; ++k) class_best[k] = 1e300;
+    const bool wide = kb == 8 && d_vals;
+    for (int v = 0; v < kBaseVariants; ++v) {
+      Tuned t = best;
+      for (int k = 0; k < kBaseClasses; ++k) t.var[k] = kBaseThreads[wide ? 1 : 0][k][v] ? v : 0;
+      EventPair class_ev[kBaseClasses];
+      for (auto& e2 : class_ev)
+        if (!e2.make()) return fail(PDQ_ERR_HIP);
+      double total = 0;
+      rc = timed_run(t, class_ev, &total);
+      if (rc != PDQ_OK) return fail(rc);
+      for (int k = 0; k < kBaseClasses; ++k) {
+        if (!kBaseThreads[wide ? 1 : 0][k][v] || (k == 6 && batch_base_max(c.key_type, d_vals != nullptr) < kWideBaseMax))
+          continue;
+        const double ms = class_ev[k].ms();
+        p->class_ms[k][v] = ms > 0 ? ms : 1e-6;  // nonzero marks a measured shape
+        if (ms < class_best[k]) {
+          class_best[k] = ms;
+          best.var[k] = static_cast<uint8_t>(v);
+        }
       }
     }
     if (hipMemcpyAsync(d_keys, bk, n * kb, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
     if (bv && hipMemcpyAsync(d_vals, bv, n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PDQ_ERR_HIP);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(PDQ_ERR_HIP);
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg)] = shape;
+    tc = best;
+    cache_store(o.tune_cache, key, tc);
   }
+  if (tune || from_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(c.key_type, c.has_vals, c.n, c.nseg)] = tc;
+  }
+  const bool wide = kb == 8 && d_vals;
+  for (int k = 0; k < kBaseClasses; ++k) {
+    p->var[k] = tc.var[k];
+    p->threads[k] = static_cast<uint32_t>(base_threads(wide, k, tc.var[k]));
+  }
+  const int shape = tc.shape;
   p->shape = static_cast<uint32_t>(shape);
   p->passes = passes;
   // capture the launch sequence on a private stream
@@ -1226,7 +1396,7 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PDQ_ERR_HIP);
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    const Ctx cc = batch_ctx(c, o, shape);
+    const Ctx cc = batch_ctx(c, o, tc);
     rc = PDQ_OK;
     if (v64 && launch_vals64_prepare(vals64, n, idx, vcopy, cs) != hipSuccess) rc = PDQ_ERR_HIP;
     if (rc == PDQ_OK) rc = enqueue_batch_init(cc, cs);
@@ -1265,6 +1435,16 @@ int pdq_plan_info(const pdq_plan* plan, uint32_t* shape, double* ms) {
   if (shape) *shape = plan->shape;
   if (ms)
     for (int i = 0; i < kBatchShapes; ++i) ms[i] = plan->ms[i];
+  return PDQ_OK;
+}
+
+int pdq_plan_classes(const pdq_plan* plan, uint32_t* threads, double* ms) {
+  if (!plan) return PDQ_ERR_INVALID;
+  for (int k = 0; k < kBaseClasses; ++k) {
+    if (threads) threads[k] = plan->threads[k];
+    if (ms)
+      for (int v = 0; v < kBaseVariants; ++v) ms[k * kBaseVariants + v] = plan->class_ms[k][v];
+  }
   return PDQ_OK;
 }
 
@@ -1425,6 +1605,7 @@ int pdq_learned_fit(const void* d_keys, size_t n, pdq_key_type key_type, void* d
   f.partials = reinterpret_cast<float*>(scratch + fs.partials);
   f.sync = reinterpret_cast<uint32_t*>(scratch + fs.sync);
   f.raw = reinterpret_cast<uint64_t*>(scratch + fs.raw);
+  f.runmax2 = reinterpret_cast<float*>(scratch + fs.runmax2);
   f.yx = reinterpret_cast<float*>(scratch + fs.yx);
   f.yy = reinterpret_cast<float*>(scratch + fs.yy);
   f.leaf = reinterpret_cast<double*>(scratch + fs.leaf);

@@ -129,7 +129,8 @@ struct Ctx {
                            // accumulate over the passes and are finished once at the end
   uint64_t seed;        // seeds the candidate positions taken after a bad partition
   uint32_t base_max;    // segments of at most this many keys go to the LDS base case
-  uint32_t wide_e;      // slots per lane of the 8192 / 16384 classes (16 or 32)
+  uint8_t base_var[kBaseClasses];  // workgroup shape of each base-case class (kBaseThreads)
+  uint8_t pad2_;
   uint32_t lookback;    // 1: tiles take their places by a decoupled look-back (deterministic order)
   uint32_t fresh_fixed; // 1: fresh candidates at the fixed quarter offsets instead of hashed positions
 };
@@ -207,6 +208,21 @@ hipError_t launch_vals64_gather(uint64_t* vals, uint64_t n, const uint32_t* idx,
                                 hipStream_t s);
 
 inline uint32_t key_bytes(uint32_t key_type) { return key_type >= 4 ? 8u : 4u; }
+
+// Workgroup shapes of the LDS base case: lanes per workgroup for size class
+// k (64, 256, 1024, ..., 16384 slots) and variant v, for 32-bit slots and
+// 64-bit keys without payload [0] and for 64-bit keys with a payload [1];
+// 0 where the variant does not exist (the launcher then takes variant 0).
+// Variant 0 is the default; the batched form's autotuner picks per class.
+constexpr int kBaseVariants = 3;
+constexpr uint16_t kBaseThreads[2][kBaseClasses][kBaseVariants] = {
+    {{64, 0, 0}, {64, 128, 256}, {64, 128, 256}, {128, 256, 64}, {256, 512, 128}, {512, 256, 1024}, {1024, 512, 0}},
+    {{64, 0, 0}, {64, 128, 256}, {128, 256, 0}, {256, 512, 0}, {512, 1024, 0}, {1024, 0, 0}, {0, 0, 0}}};
+
+__host__ __device__ inline int base_threads(bool wide_pairs, int cls, int var) {
+  const int t = kBaseThreads[wide_pairs ? 1 : 0][cls][var < kBaseVariants ? var : 0];
+  return t ? t : kBaseThreads[wide_pairs ? 1 : 0][cls][0];
+}
 
 // Size class of a base-case segment of n keys (1 <= n <= kWideBaseMax).
 __host__ __device__ inline int base_class(uint64_t n) {

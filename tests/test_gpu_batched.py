@@ -252,3 +252,108 @@ def test_batched_deterministic_repeat_exactly():
     check_segmented(keys, off, o1, v1)
     assert np.array_equal(v1, v2)
     assert s1["element_visits"] == s2["element_visits"]
+
+
+# lanes per workgroup of each base-case size class under each of its three
+# launcher variants (0 = the variant does not exist), for 32-bit slots and
+# 64-bit keys alone, and for 64-bit keys with a payload
+CLASS_SHAPES = {
+    False: [(64, 0, 0), (64, 128, 256), (64, 128, 256), (128, 256, 64), (256, 512, 128), (512, 256, 1024),
+            (1024, 512, 0)],
+    True: [(64, 0, 0), (64, 128, 256), (128, 256, 0), (256, 512, 0), (512, 1024, 0), (1024, 0, 0), (0, 0, 0)],
+}
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("kt,pairs", [("u32", True), ("f64", False), ("u64", True)])
+def test_batched_waves_option(kt, pairs, waves):
+    """pdq_options.waves forces every base-case class that has a shape of that
+    many waves to take it; results match the oracle whatever the shapes."""
+    off = W.offsets_from_sizes(mixed_sizes(40 + waves, extra=120, max_log2=15))
+    n = int(off[-1])
+    keys = W.random_keys(kt, n, seed=waves)
+    vals = W.index_payload(n) if pairs else None
+    out, vo, _ = run_batched(keys, off, vals, waves=waves)
+    check_segmented(keys, off, out, vo)
+
+
+@pytest.mark.parametrize("waves", [1, 4, 16])
+@pytest.mark.parametrize("kt", ["u32", "i64"])
+def test_sort_waves_option(kt, waves):
+    """The single-array sort takes the same option for its base case."""
+    n = 300007
+    keys = W.random_keys(kt, n, seed=7 + waves)
+    t = dev(keys)
+    pdq.sort_(t, waves=waves)
+    assert np.array_equal(as_bytes(host(t)), as_bytes(oracle.sort(keys)[0]))
+    v = dev(W.index_payload(n))
+    t = dev(keys)
+    pdq.sort_pairs_(t, v, waves=waves)
+    out, vo = host(t), host(v)
+    assert np.array_equal(as_bytes(out), as_bytes(oracle.sort(keys)[0]))
+    assert np.array_equal(as_bytes(keys[vo]), as_bytes(out))
+
+
+def test_waves_option_rejects_other_values():
+    t = dev(W.random_keys("u32", 1000, seed=1))
+    o = dev(np.array([0, 1000], dtype=np.uint64))
+    for w in (3, 5, 32):
+        with pytest.raises(pdq.PdqError) as ei:
+            pdq.segmented_sort_(t, o, batched=True, waves=w)
+        assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("kt,pairs", [("f32", True), ("u64", True)])
+def test_plan_autotune_per_class_and_cache_file(tmp_path, kt, pairs):
+    """PDQ_AUTOTUNE times every shape of every base-case class and keeps the
+    fastest of each; with a cache file it appends one line, and a second plan
+    for the same problem takes that line without timing anything (no new
+    line, no class timings). A later invalid line for the same problem is
+    ignored. Every replay matches the oracle."""
+    off = W.offsets_from_sizes(mixed_sizes(77, extra=400, max_log2=15))
+    n = int(off[-1])
+    keys = W.random_keys(kt, n, seed=3)
+    vals = W.index_payload(n) if pairs else None
+    wide = kt in ("u64", "i64", "f64") and pairs
+    cache = tmp_path / "tune.txt"
+    tk, to = dev(keys), dev(off)
+    tv = dev(vals) if pairs else None
+    plan = pdq.Plan(tk, to, tv, autotune=True, tune_cache_path=str(cache))
+    threads, ms = plan.classes()
+    for k in range(7):
+        shapes = CLASS_SHAPES[wide][k]
+        if not shapes[0]:
+            continue
+        assert threads[k] in shapes
+        # every existing variant was timed, and the kept one is the fastest
+        for v in range(3):
+            assert (ms[k][v] > 0) == (shapes[v] > 0), (k, v, ms[k])
+        assert ms[k][shapes.index(threads[k])] == min(m for m in ms[k] if m > 0)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("pdq-tune 1 ")
+    fields = lines[0].split()
+    assert len(fields) == 2 + 5 + 1 + 7  # tag, version, arch/CUs, type, payload, n, segments, shape, 7 variants
+    assert int(fields[5]) == n and int(fields[6]) == off.size - 1
+    # the caller's data is back in place after the timing runs
+    assert np.array_equal(as_bytes(host(tk)), as_bytes(keys))
+    plan.launch()
+    check_segmented(keys, off, host(tk), host(tv) if pairs else None)
+    plan.destroy()
+    # an invalid line after the valid one: skipped by the reader
+    with open(cache, "a") as f:
+        f.write(" ".join(fields[:8]) + " 9 9 9 9 9 9 9\n")
+    tk2 = dev(keys)
+    tv2 = dev(vals) if pairs else None
+    plan2 = pdq.Plan(tk2, to, tv2, autotune=True, tune_cache_path=str(cache))
+    threads2, ms2 = plan2.classes()
+    assert threads2 == threads
+    assert all(m == 0 for row in ms2 for m in row)
+    assert len(cache.read_text().splitlines()) == 2
+    plan2.launch()
+    check_segmented(keys, off, host(tk2), host(tv2) if pairs else None)
+    plan2.destroy()
+    # the eager batched call with the same cache: same keys as the plan
+    tk3 = dev(keys)
+    tv3 = dev(vals) if pairs else None
+    pdq.segmented_sort_(tk3, to, tv3, batched=True, tune_cache_path=str(cache))
+    check_segmented(keys, off, host(tk3), host(tv3) if pairs else None)
