@@ -40,9 +40,15 @@
  * pdq_workspace_bytes; 256-byte alignment recommended). d_ws must stay
  * allocated until the work queued on `stream` has finished. No pointer is
  * kept after a call returns. `stream` is a hipStream_t (NULL = the default
- * stream). Calls run asynchronously on `stream` unless `stats` is non-NULL
- * or PDQ_VALIDATE is set; the current implementation synchronises `stream`
- * once per partition pass to read the number of live segments.
+ * stream). The host-driven sorts (pdq_sort, pdq_sort_pairs, and
+ * pdq_segmented_sort without PDQ_BATCHED) read the number of live segments
+ * after each partition pass: each pass ends with an asynchronous copy of the
+ * pass counters into pinned host memory (a few small blocks the library
+ * allocates on first use, one per concurrent call and device, kept until
+ * the process ends), and the host waits for one pass's counters while the
+ * next pass already runs. They return once the last pass is queued (its
+ * finishing work may still run) unless `stats` is non-NULL or PDQ_VALIDATE
+ * is set, which synchronise `stream` at the end.
  *
  * Errors: every entry point returns PDQ_OK (0) or a negative status; no
  * exception crosses the ABI. n <= 1 is a no-op returning PDQ_OK.
@@ -281,8 +287,11 @@ void pdq_plan_destroy(pdq_plan* plan);
  * A call whose
  * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt) exceeds
  * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
- * (without PDQ_LEARNED: up to 16,149,632 uint32 keys, 8,227,712 uint32 keys
- * with payloads or uint64 keys, 5,519,936 uint64 keys with payloads). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return
+ * (without PDQ_LEARNED: up to 15,662,528 uint32 keys, 8,079,232 uint32 keys
+ * with payloads, 8,079,264 uint64 keys, 5,443,392 uint64 keys with
+ * payloads). Unlike pdq_sort, it runs one host synchronisation per partition
+ * pass (the pipelined pass loop needs pinned host memory, which it does not
+ * allocate). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return
  * PDQ_ERR_UNSUPPORTED. Every call on one GPU shares that GPU's array, which
  * keeps the previous call's contents (the call clears what must start at
  * zero): calls that overlap in time on one GPU -- on different streams, or

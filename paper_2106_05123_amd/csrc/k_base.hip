@@ -32,7 +32,7 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
   // a list longer than its capacity (only invalid offsets make one; it is
   // flagged) is read no further than its capacity
-  uint32_t count = c.device_counts ? c.ctr->nbase[cls] : nitems;
+  uint32_t count = c.device_counts ? c.icnt[cls] : nitems;
   if (count > c.max_items) count = c.max_items;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     // an opaque copy of the lane index keeps the per-slot addresses inside

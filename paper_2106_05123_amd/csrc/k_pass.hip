@@ -33,7 +33,7 @@ __device__ __forceinline__ void push_item(const Ctx& c, Item* list, uint32_t* ct
 __device__ __forceinline__ void push_base(const Ctx& c, bool want, uint64_t b, uint64_t e, uint32_t buf) {
   const int cls = want ? base_class(e - b) : -1;
 #pragma unroll
-  for (int k = 0; k < kBaseClasses; ++k) push_item(c, c.base[k], &c.ctr->nbase[k], cls == k, b, e, buf, 0u);
+  for (int k = 0; k < kBaseClasses; ++k) push_item(c, c.base[k], &c.icnt[k], cls == k, b, e, buf, 0u);
 }
 
 // Append a live segment to list `parity` and reserve its tile tickets.
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_init(Ctx c) {
   const bool to_base = size >= 2 && !big;
   const bool to_heap = big && budget == 0;
   push_base(c, to_base, b, e, 0u);
-  push_item(c, c.heap, &c.ctr->nheap, to_heap, b, e, 0u, 0u);
+  push_item(c, c.heap, &c.icnt[kItemHeap], to_heap, b, e, 0u, 0u);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? size : 0);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), to_heap ? 1 : 0);
@@ -126,12 +126,12 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
   uint32_t budget = 0;
   if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
   const bool big = size > c.base_max;
-  push_item(c, c.copy, &c.ctr->ncopy, eq, b, e, 1u, 0u);
+  push_item(c, c.copy, &c.icnt[kItemCopy], eq, b, e, 1u, 0u);
   push_seg(c, 0, range && big && budget > 0, b, e, budget, kSegLeftmost);
   const bool to_base = range && !big;
   const bool to_heap = range && big && budget == 0;
   push_base(c, to_base, b, e, 1u);
-  push_item(c, c.heap, &c.ctr->nheap, to_heap, b, e, 1u, 0u);
+  push_item(c, c.heap, &c.icnt[kItemHeap], to_heap, b, e, 1u, 0u);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? size : 0);
   wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), to_heap ? 1 : 0);
@@ -141,7 +141,8 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
 
 // Pivot choice for every live segment (choose_pivot, pivot.h). The first
 // lane also clears the counters of the list the bookkeeping will fill (and,
-// unless the item lists accumulate over the passes, the item counts).
+// unless the item lists accumulate over the passes, the counts of the item
+// set it fills).
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32_t nseg, uint32_t src) {
   using T = typename K::T;
@@ -152,11 +153,8 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
     c.ctr->list[parity ^ 1] = 0;
     c.ctr->elems[parity ^ 1] = 0;
     c.ctr->maxlen[parity ^ 1] = 0;
-    if (!c.device_counts) {
-      for (int k = 0; k < kBaseClasses; ++k) c.ctr->nbase[k] = 0;
-      c.ctr->nheap = 0;
-      c.ctr->ncopy = 0;
-    }
+    if (!c.accumulate)
+      for (int k = 0; k < kItemCounts; ++k) c.icnt[k] = 0;
   }
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
     Seg* sp = &c.segs[parity][i];
@@ -235,10 +233,10 @@ __device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t 
   }
   // already ordered: copy (reversed when descending) into the user buffer
   const bool ordered = asc_sorted || desc_sorted;
-  push_item(c, c.copy, &c.ctr->ncopy, ordered && !(src == 0 && asc_sorted), s.begin, s.end, src,
+  push_item(c, c.copy, &c.icnt[kItemCopy], ordered && !(src == 0 && asc_sorted), s.begin, s.end, src,
             desc_sorted ? 1u : 0u);
   // partition_left: the left side equals the pivot and is final
-  push_item(c, c.copy, &c.ctr->ncopy, split && is_left && L > 0 && dst != 0, s.begin, s.begin + L, dst, 0u);
+  push_item(c, c.copy, &c.icnt[kItemCopy], split && is_left && L > 0 && dst != 0, s.begin, s.begin + L, dst, 0u);
 
   const uint32_t cbudget = s.budget - (bad ? 1u : 0u);
   const uint32_t cflag_fresh = bad ? kSegFresh : 0u;
@@ -253,7 +251,7 @@ __device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t 
     const bool to_heap = has && cs > c.base_max && cbudget == 0;
     const bool to_live = has && cs > c.base_max && cbudget > 0;
     push_base(c, to_base, cb, ce, dst);
-    push_item(c, c.heap, &c.ctr->nheap, to_heap, cb, ce, dst, 0u);
+    push_item(c, c.heap, &c.icnt[kItemHeap], to_heap, cb, ce, dst, 0u);
     push_seg(c, parity ^ 1, to_live, cb, ce, cbudget, cflags);
     wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_segments), to_base ? 1 : 0);
     wave_add(reinterpret_cast<unsigned long long*>(&c.ctr->base_elements), to_base ? cs : 0);
@@ -289,7 +287,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_bookkeep(Ctx c, int parity, uin
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
   using T = typename K::T;
-  uint32_t count = c.device_counts ? c.ctr->ncopy : nitems;
+  uint32_t count = c.device_counts ? c.icnt[kItemCopy] : nitems;
   if (count > c.max_items) count = c.max_items;  // an overfull list is flagged, never read past
   T* out = static_cast<T*>(c.keys[0]);
   uint32_t* outv = c.vals[0];
@@ -332,7 +330,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
 template <class K>
 __global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c, uint32_t nitems) {
   using T = typename K::T;
-  uint32_t count = c.device_counts ? c.ctr->nheap : nitems;
+  uint32_t count = c.device_counts ? c.icnt[kItemHeap] : nitems;
   if (count > c.max_items) count = c.max_items;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const Item it = c.heap[item];

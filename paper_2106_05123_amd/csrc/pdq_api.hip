@@ -76,6 +76,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t scratch_keys = 0, scratch_vals = 0, segs0 = 0, segs1 = 0, cur = 0, tickets = 0, tilemap = 0, status = 0;
   size_t base[kBaseClasses] = {}, heap = 0, copy = 0, ctr = 0, total = 0;
+  // the second item set of the pipelined pass loop (zero in the batched form)
+  size_t base1[kBaseClasses] = {}, heap1 = 0, copy1 = 0;
   uint32_t max_active = 0, max_tiles = 0, max_items = 0;
   // learned first pass (zero sizes when not requested)
   size_t fit_out = 0, fit_scratch = 0, bucket = 0;
@@ -221,6 +223,13 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
   for (int k = 0; k < kBaseClasses; ++k) L.base[k] = take(sizeof(Item) * L.max_items);
   L.heap = take(sizeof(Item) * L.max_items);
   L.copy = take(sizeof(Item) * L.max_items);
+  if (!batched) {
+    // the pipelined pass loop finishes one pass's items while the next pass
+    // fills the other set
+    for (int k = 0; k < kBaseClasses; ++k) L.base1[k] = take(sizeof(Item) * L.max_items);
+    L.heap1 = take(sizeof(Item) * L.max_items);
+    L.copy1 = take(sizeof(Item) * L.max_items);
+  }
   L.total = off + kAlign;  // room to align the caller's base pointer
   return L;
 }
@@ -325,26 +334,88 @@ struct Timed {
   uint64_t bytes = 0;
 };
 
-int read_counters(const Ctx& c, Counters* snap, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (snap->errors & kErrCapacity) return PDQ_ERR_INVALID;  // only bad offsets can overfill a list
-  if (snap->errors) return PDQ_ERR_DEVICE;
-  const uint32_t nact0 = static_cast<uint32_t>(snap->list[0] >> 32), nact1 = static_cast<uint32_t>(snap->list[1] >> 32);
-  if (nact0 > c.max_active || nact1 > c.max_active || static_cast<uint32_t>(snap->list[0]) > c.max_tiles ||
-      static_cast<uint32_t>(snap->list[1]) > c.max_tiles || snap->nheap > c.max_items || snap->ncopy > c.max_items)
+// A counter snapshot's consistency: device-side error bits, and counts that
+// fit their lists (only bad offsets can overfill a list).
+int check_snapshot(const Ctx& c, const Counters& snap) {
+  if (snap.errors & kErrCapacity) return PDQ_ERR_INVALID;
+  if (snap.errors) return PDQ_ERR_DEVICE;
+  const uint32_t nact0 = static_cast<uint32_t>(snap.list[0] >> 32), nact1 = static_cast<uint32_t>(snap.list[1] >> 32);
+  if (nact0 > c.max_active || nact1 > c.max_active || static_cast<uint32_t>(snap.list[0]) > c.max_tiles ||
+      static_cast<uint32_t>(snap.list[1]) > c.max_tiles)
     return PDQ_ERR_INVALID;
-  for (int k = 0; k < kBaseClasses; ++k)
-    if (snap->nbase[k] > c.max_items) return PDQ_ERR_INVALID;
+  for (int set = 0; set < 2; ++set)
+    for (int k = 0; k < kItemCounts; ++k)
+      if (item_counts(&snap, set)[k] > c.max_items) return PDQ_ERR_INVALID;
   return PDQ_OK;
 }
 
-int finish_items(const Ctx& c, const Counters& snap, hipStream_t s) {
+int read_counters(const Ctx& c, Counters* snap, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return check_snapshot(c, *snap);
+}
+
+// The base cases, heapsorts and copies of one item set, with the counts of
+// a snapshot (`cnt`: item_counts of that set); c's lists are that set's.
+int finish_set(Ctx c, const uint32_t* cnt, hipStream_t s) {
+  c.device_counts = 0;
   for (int k = 0; k < kBaseClasses; ++k)
-    if (snap.nbase[k]) HIP_TRY(launch_base(c, k, snap.nbase[k], s));
-  if (snap.nheap) HIP_TRY(launch_heap(c, snap.nheap, s));
-  if (snap.ncopy) HIP_TRY(launch_copy(c, snap.ncopy, s));
+    if (cnt[k]) HIP_TRY(launch_base(c, k, cnt[k], s));
+  if (cnt[kItemHeap]) HIP_TRY(launch_heap(c, cnt[kItemHeap], s));
+  if (cnt[kItemCopy]) HIP_TRY(launch_copy(c, cnt[kItemCopy], s));
   return PDQ_OK;
+}
+
+int finish_items(const Ctx& c, const Counters& snap, hipStream_t s) { return finish_set(c, item_counts(&snap, 0), s); }
+
+// Host side of the pipelined pass loop: pinned host memory that counter
+// snapshots are copied into asynchronously, with one completion event per
+// slot. A call takes a block from the pool for its duration; blocks are
+// created on first need (one per concurrent call and device) and kept until
+// the process ends.
+constexpr int kPinSlots = 4;
+struct PinBlock {
+  int dev = -1;
+  Counters* host = nullptr;
+  hipEvent_t ev[kPinSlots] = {};
+};
+std::mutex g_pin_mu;
+std::vector<PinBlock*> g_pin_free;
+// set while pdq_sort_noalloc runs: it allocates nothing, so it keeps the
+// loop with one synchronisation per pass
+thread_local bool t_no_pin = false;
+
+PinBlock* pin_acquire() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (size_t i = 0; i < g_pin_free.size(); ++i)
+      if (g_pin_free[i]->dev == dev) {
+        PinBlock* b = g_pin_free[i];
+        g_pin_free.erase(g_pin_free.begin() + static_cast<long>(i));
+        return b;
+      }
+  }
+  PinBlock* b = new PinBlock;
+  b->dev = dev;
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&b->host), kPinSlots * sizeof(Counters), hipHostMallocDefault) ==
+            hipSuccess;
+  for (int i = 0; ok && i < kPinSlots; ++i) ok = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();  // the failure must not be reported by a later launch
+    for (auto& e : b->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (b->host) (void)hipHostFree(b->host);
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+void pin_release(PinBlock* b) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(b);
 }
 
 int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
@@ -587,6 +658,7 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   c.heap = reinterpret_cast<Item*>(base + L.heap);
   c.copy = reinterpret_cast<Item*>(base + L.copy);
   c.ctr = reinterpret_cast<Counters*>(base + L.ctr);
+  c.icnt = item_counts(c.ctr, 0);
   c.offsets = offsets;
   c.nseg = offsets ? nseg : 1;
   c.tile = o.tile ? o.tile : kDefaultTile;
@@ -765,6 +837,7 @@ BatchArgs batch_args(const Layout& L, char* base) {
 // the wide LDS classes, the shape's partition tile and the classes' shapes.
 Ctx batch_ctx(Ctx c, const Opts& o, const Tuned& t) {
   c.device_counts = 1;
+  c.accumulate = 1;
   c.base_max = batch_base_max(c.key_type, c.has_vals != 0);
   c.tile = o.tile ? o.tile : kShapes[t.shape].tile;
   for (int k = 0; k < kBaseClasses; ++k) c.base_var[k] = t.var[k];
@@ -879,6 +952,164 @@ int run_batched(const Ctx& c0, const Opts& o, const Layout& L, char* base, pdq_s
   return PDQ_OK;
 }
 
+// Pass loop with one host synchronisation per pass: the counters after a
+// pass size the next one exactly. Used where pinned host memory is not to
+// be allocated (pdq_sort_noalloc) or cannot be.
+int run_passes_sync(Ctx& c, const Opts& o, Counters& snap, uint32_t src, bool prof, uint64_t bytes_per_key,
+                    std::vector<Timed>& timed, uint32_t* passes, uint64_t* visits_out, hipStream_t s) {
+  int parity = 0;
+  uint32_t pass = 0;
+  uint64_t visits = 0;
+  for (;;) {
+    const uint32_t nact = static_cast<uint32_t>(snap.list[parity] >> 32);
+    const uint32_t ntiles = static_cast<uint32_t>(snap.list[parity]);
+    if (nact == 0) break;
+    if (pass >= kMaxPasses) return PDQ_ERR_HIP;
+    visits += snap.elems[parity];
+    HIP_TRY(launch_pivot(c, parity, nact, src, s));
+    HIP_TRY(launch_tilemap(c, parity, ntiles, s));
+    Timed tm;
+    if (prof) {
+      HIP_TRY(hipEventCreate(&tm.a));
+      timed.push_back(tm);
+      HIP_TRY(hipEventCreate(&timed.back().b));
+      timed.back().bytes = snap.elems[parity] * bytes_per_key;
+      HIP_TRY(hipEventRecord(timed.back().a, s));
+    }
+    HIP_TRY(launch_partition(c, parity, ntiles, src, s));
+    if (prof) HIP_TRY(hipEventRecord(timed.back().b, s));
+    // the children filed now are tiled for the next pass: about two per
+    // segment, sharing its keys; the next pass's largest segment is taken as
+    // half this pass's largest
+    if (!o.tile) c.tile = auto_tile(snap.elems[parity], (snap.maxlen[parity] + 1) / 2);
+    HIP_TRY(launch_bookkeep(c, parity, nact, src, pass, s));
+    int r = read_counters(c, &snap, s);
+    if (r == PDQ_OK) r = finish_items(c, snap, s);
+    if (r != PDQ_OK) return r;
+    parity ^= 1;
+    src ^= 1u;
+    ++pass;
+  }
+  *passes = pass;
+  *visits_out = visits;
+  return PDQ_OK;
+}
+
+// The context of item set `set`: its lists and its counts.
+Ctx with_items(Ctx c, const Layout& L, char* base, int set) {
+  for (int k = 0; k < kBaseClasses; ++k) c.base[k] = reinterpret_cast<Item*>(base + (set ? L.base1[k] : L.base[k]));
+  c.heap = reinterpret_cast<Item*>(base + (set ? L.heap1 : L.heap));
+  c.copy = reinterpret_cast<Item*>(base + (set ? L.copy1 : L.copy));
+  c.icnt = item_counts(c.ctr, set);
+  return c;
+}
+
+// Pass loop that keeps the GPU fed. Pass q + 1 is queued before the host
+// has seen the counters after pass q: its kernels take their counts on the
+// device, and their grids come from bounds on pass q's live list (at most
+// two children per segment, no more keys), which the counters after pass
+// q - 1 give. The counters after every pass are copied into pinned host
+// memory as the pass's last step, and while the GPU runs pass q + 1 the
+// host reads those of pass q, queues the finishing of pass q - 1's items
+// and then pass q + 2. Passes alternate between two item sets, so the
+// items of pass q - 1 are finished while pass q fills the other set; every
+// item range is retired, so no later pass touches it. The loop ends when
+// the counters show an empty live list: the pass already queued for it
+// finds nothing to do.
+int run_passes_pipelined(Ctx c, const Opts& o, const Layout& L, char* base, const Counters& init, uint32_t src0,
+                         bool prof, uint64_t bytes_per_key, std::vector<Timed>& timed, uint32_t* passes,
+                         uint64_t* visits_out, PinBlock* pin, hipStream_t s) {
+  Ctx cp = c;
+  cp.device_counts = 1;
+  // tile_of[q % 4]: the tile of pass q (its segments were tiled for it by
+  // the bookkeeping of pass q - 1)
+  uint32_t tile_of[4];
+  tile_of[0] = c.tile;
+  int last = -1;  // the last slot a counter copy was queued into
+  auto enqueue = [&](uint32_t q, uint32_t live_bound, uint32_t tile_bound) -> int {
+    const int parity = static_cast<int>(q & 1u);
+    const uint32_t src = src0 ^ (q & 1u);
+    Ctx cq = with_items(cp, L, base, static_cast<int>((q + 1) & 1u));
+    cq.tile = tile_of[q % 4];
+    HIP_TRY(launch_pivot(cq, parity, live_bound, src, s));
+    HIP_TRY(launch_tilemap(cq, parity, tile_bound, s));
+    if (prof) {
+      Timed tm;
+      HIP_TRY(hipEventCreate(&tm.a));
+      timed.push_back(tm);
+      HIP_TRY(hipEventCreate(&timed.back().b));
+      HIP_TRY(hipEventRecord(timed.back().a, s));
+    }
+    HIP_TRY(launch_partition(cq, parity, tile_bound, src, s));
+    if (prof) HIP_TRY(hipEventRecord(timed.back().b, s));
+    cq.tile = tile_of[(q + 1) % 4];
+    HIP_TRY(launch_bookkeep(cq, parity, live_bound, src, q, s));
+    const int slot = static_cast<int>(q % kPinSlots);
+    HIP_TRY(hipMemcpyAsync(&pin->host[slot], c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(pin->ev[slot], s));
+    last = slot;
+    return PDQ_OK;
+  };
+  // no copy may still be landing in the pinned block once it is handed back
+  auto drain = [&](int rc) {
+    if (last >= 0) (void)hipEventSynchronize(pin->ev[last]);
+    return rc;
+  };
+  const uint32_t live0 = static_cast<uint32_t>(init.list[0] >> 32);
+  if (live0 == 0) {
+    *passes = 0;
+    *visits_out = 0;
+    return PDQ_OK;
+  }
+  tile_of[1] = o.tile ? o.tile : auto_tile(init.elems[0], (init.maxlen[0] + 1) / 2);
+  int rc = enqueue(0, live0, static_cast<uint32_t>(init.list[0]));
+  if (rc != PDQ_OK) return drain(rc);
+  Counters prev = init;  // the counters after pass q - 1 (the initial lists for q = 0)
+  uint64_t visits = 0;
+  uint32_t q = 0;
+  for (;;) {
+    const int parity = static_cast<int>(q & 1u);
+    // pass q - 1's items (set q & 1), queued before pass q + 1 clears that set
+    if (q > 0) {
+      rc = finish_set(with_items(c, L, base, parity), item_counts(&prev, parity), s);
+      if (rc != PDQ_OK) return drain(rc);
+    }
+    const uint32_t live = static_cast<uint32_t>(prev.list[parity] >> 32);
+    if (live == 0) break;  // pass q, already queued, runs empty
+    if (q + 1 >= kMaxPasses) return drain(PDQ_ERR_HIP);
+    visits += prev.elems[parity];
+    if (prof && q < timed.size()) timed[q].bytes = prev.elems[parity] * bytes_per_key;
+    // pass q + 1: at most two children per live segment of pass q, no more keys
+    const uint64_t live_bound = 2ull * live < c.max_active ? 2ull * live : c.max_active;
+    const uint32_t next_tile = tile_of[(q + 1) % 4];
+    uint64_t tile_bound = prev.elems[parity] / next_tile + 1 + live_bound;
+    if (tile_bound > c.max_tiles) tile_bound = c.max_tiles;
+    // the tile pass q + 2 is filed with: its largest segment taken as a
+    // quarter of pass q's largest
+    tile_of[(q + 2) % 4] = o.tile ? o.tile : auto_tile(prev.elems[parity], (prev.maxlen[parity] + 3) / 4);
+    rc = enqueue(q + 1, static_cast<uint32_t>(live_bound), static_cast<uint32_t>(tile_bound));
+    if (rc != PDQ_OK) return drain(rc);
+    // the counters after pass q
+    const int slot = static_cast<int>(q % kPinSlots);
+    if (hipEventSynchronize(pin->ev[slot]) != hipSuccess) return drain(PDQ_ERR_HIP);
+    prev = pin->host[slot];
+    rc = check_snapshot(c, prev);
+    if (rc != PDQ_OK) return drain(rc);
+    ++q;
+  }
+  // the last queued pass found its live list empty: not a pass
+  if (prof && timed.size() > q) {
+    for (size_t i = q; i < timed.size(); ++i) {
+      (void)hipEventDestroy(timed[i].a);
+      (void)hipEventDestroy(timed[i].b);
+    }
+    timed.resize(q);
+  }
+  *passes = q;
+  *visits_out = visits;
+  return drain(PDQ_OK);
+}
+
 int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
              void* ws, size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* st) {
   g_last_hip = 0;
@@ -963,49 +1194,18 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   if (rc != PDQ_OK) return rc;
 
   const uint64_t bytes_per_key = 2ull * kb + (vals ? 8ull : 0ull);
-  int parity = 0;
   uint32_t pass = 0;
   uint64_t visits = 0;
-  for (;;) {
-    const uint32_t nact = static_cast<uint32_t>(snap.list[parity] >> 32);
-    const uint32_t ntiles = static_cast<uint32_t>(snap.list[parity]);
-    if (nact == 0) break;
-    if (pass >= kMaxPasses) {
-      cleanup();
-      return PDQ_ERR_HIP;
-    }
-    visits += snap.elems[parity];
-    int r2 = PDQ_OK;
-    do {
-      hipError_t e;
-      if ((e = launch_pivot(c, parity, nact, src, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
-      if ((e = launch_tilemap(c, parity, ntiles, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
-      Timed tm;
-      if (prof) {
-        if (hipEventCreate(&tm.a) != hipSuccess || hipEventCreate(&tm.b) != hipSuccess) { r2 = PDQ_ERR_HIP; break; }
-        tm.bytes = snap.elems[parity] * bytes_per_key;
-        (void)hipEventRecord(tm.a, s);
-      }
-      if ((e = launch_partition(c, parity, ntiles, src, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
-      if (prof) {
-        (void)hipEventRecord(tm.b, s);
-        timed.push_back(tm);
-      }
-      // the children filed now are tiled for the next pass: about two per
-      // segment, sharing its keys
-      // the next pass's largest segment is taken as half this pass's largest
-      if (!o.tile) c.tile = auto_tile(snap.elems[parity], (snap.maxlen[parity] + 1) / 2);
-      if ((e = launch_bookkeep(c, parity, nact, src, pass, s)) != hipSuccess) { g_last_hip = e; r2 = PDQ_ERR_HIP; break; }
-    } while (0);
-    if (r2 == PDQ_OK) r2 = read_counters(c, &snap, s);
-    if (r2 == PDQ_OK) r2 = finish_items(c, snap, s);
-    if (r2 != PDQ_OK) {
-      cleanup();
-      return r2;
-    }
-    parity ^= 1;
-    src ^= 1u;
-    ++pass;
+  PinBlock* pin = t_no_pin ? nullptr : pin_acquire();
+  if (pin) {
+    rc = run_passes_pipelined(c, o, L, base, snap, src, prof, bytes_per_key, timed, &pass, &visits, pin, s);
+    pin_release(pin);
+  } else {
+    rc = run_passes_sync(c, o, snap, src, prof, bytes_per_key, timed, &pass, &visits, s);
+  }
+  if (rc != PDQ_OK) {
+    cleanup();
+    return rc;
   }
 
   if (st) {
@@ -1243,7 +1443,10 @@ int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_
     const int r2 = noalloc_scratch(&ws);
     if (r2 != PDQ_OK) return r2;
   }
-  return sort_entry(d_keys, d_vals, n, nullptr, 1, key_type, order, ws, kNoAllocBytes, stream, opt, stats);
+  t_no_pin = true;
+  const int r3 = sort_entry(d_keys, d_vals, n, nullptr, 1, key_type, order, ws, kNoAllocBytes, stream, opt, stats);
+  t_no_pin = false;
+  return r3;
 }
 
 // ---- captured batched sort --------------------------------------------------

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pdq {
@@ -75,12 +76,18 @@ struct Item {
   uint32_t reverse; // copy items: write the range in reverse order
 };
 
+// Item counts of one set of item lists: the base-case classes, heapsort,
+// copies (in this order, contiguous).
+constexpr int kItemHeap = kBaseClasses;
+constexpr int kItemCopy = kBaseClasses + 1;
+constexpr int kItemCounts = kBaseClasses + 2;
+
 // Device-side counters. Host reads a snapshot after each pass.
 struct Counters {
   uint64_t list[2];        // per list parity: (segments << 32) | tiles
   uint64_t elems[2];       // per list parity: keys in the list
   uint64_t maxlen[2];      // per list parity: keys of its largest segment
-  uint32_t nbase[kBaseClasses];
+  uint32_t nbase[kBaseClasses];  // item set 0: nbase[], nheap, ncopy
   uint32_t nheap, ncopy, ticket, pad1_;
   // statistics (accumulated over the call)
   uint64_t partitions_right, partitions_left, bad_partitions;
@@ -95,7 +102,20 @@ struct Counters {
   uint32_t bad_offsets;    // validation: offsets not monotone / not covering [0, n)
   uint32_t errors;         // kErr* bits: an internal inconsistency was caught and its writes skipped
   uint32_t pad_;
+  uint32_t items1[kItemCounts];  // item set 1 (the pipelined pass loop alternates sets)
+  uint32_t pad3_;
 };
+static_assert(offsetof(Counters, nheap) == offsetof(Counters, nbase) + 4 * kItemHeap, "item set 0 layout");
+static_assert(offsetof(Counters, ncopy) == offsetof(Counters, nbase) + 4 * kItemCopy, "item set 0 layout");
+
+// Item counts of set `set` inside a counter block (kItemCounts words).
+__host__ __device__ inline uint32_t* item_counts(Counters* ctr, int set) {
+  return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ctr) +
+                                     (set ? offsetof(Counters, items1) : offsetof(Counters, nbase)));
+}
+__host__ __device__ inline const uint32_t* item_counts(const Counters* ctr, int set) {
+  return item_counts(const_cast<Counters*>(ctr), set);
+}
 
 constexpr uint32_t kErrCapacity = 1u;  // a list append found its list full (only reachable with bad offsets)
 constexpr uint32_t kErrLookback = 2u;  // a tile's reservation did not fit its segment
@@ -111,10 +131,11 @@ struct Ctx {
   Cursor* cur;          // segment index -> its partition cursor (the pass being run)
   uint32_t* tickets;    // reservation partition: kTicketQueues counters, kTicketStride words apart
   uint64_t* status;     // ticket -> look-back status word (deterministic partition only)
-  Item* base[kBaseClasses];
+  Item* base[kBaseClasses];  // the item set being filled or finished
   Item* heap;
   Item* copy;
   Counters* ctr;
+  uint32_t* icnt;       // its counts (item_counts): [class] base cases, [kItemHeap], [kItemCopy]
   const uint64_t* offsets;  // segmented input (null: one segment [0, n))
   uint64_t nseg;
   uint32_t tile;        // keys per partition tile
@@ -125,8 +146,11 @@ struct Ctx {
   uint32_t key_type;
   uint32_t has_vals;
   uint32_t single;      // 1: one segment [0, n) (records the first partition)
-  uint32_t device_counts;  // 1 (batched form): every kernel takes its counts from ctr, item lists
-                           // accumulate over the passes and are finished once at the end
+  uint32_t device_counts;  // 1: the pass kernels (and finishing kernels launched with this flag)
+                           // take their counts from ctr instead of their arguments
+  uint32_t accumulate;  // 1 (batched form): item lists accumulate over the passes and are
+                        // finished once at the end; 0: each pass's pivot kernel clears the
+                        // counts of the set its bookkeeping fills
   uint64_t seed;        // seeds the candidate positions taken after a bad partition
   uint32_t base_max;    // segments of at most this many keys go to the LDS base case
   uint8_t base_var[kBaseClasses];  // workgroup shape of each base-case class (kBaseThreads)
