@@ -51,6 +51,10 @@ float32), so that it can be read against this summary:
              keys in a range bin); the smallest wins, ties in that order
   bins       b = number of splitters <= key; equality bin 2b - 1 when
              key == s[b - 1], range bin 2b otherwise (2u + 1 bins)
+  budget     staged: a fit of 32 steps first; it is kept when its chosen
+             splitters put at most 1.3 m / 256 sample keys into one range bin
+             (in integers: judge * 2560 <= 13 m), else the fit is redone from
+             the same initial parameters with 128 steps
 
 Where a float32 result decides an integer (the splitters), the float32
 inference is the C routine oracle_mlp_infer_f32 (pdq_oracle.cpp), which
@@ -411,3 +415,26 @@ def fit(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, steps: int = 128, bat
     sp, choice, est, leaves = choose_splitters(samp, x, t, y)
     return dict(sample=samp, x=x, use_log=use_log, t=t, p0=p0, params=p, losses=losses, pred=y, splitters=sp,
                 choice=choice, estimates=est, leaf_pred=leaves, root_splitters=splitters(samp, y))
+
+
+STAGE1_STEPS = 32
+STAGE2_STEPS = 128
+
+
+def early_accept(judge: int, m: int) -> bool:
+    """Whether a short fit is kept: its fullest range bin holds at most
+    1.3 m / 256 sample keys."""
+    return judge * 2560 <= 13 * m
+
+
+def fit_staged(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, batch: int = 1024, residual: bool = True):
+    """The default budget: a 32-step fit, kept if early_accept holds for its
+    chosen splitters, else a 128-step fit from the same initial parameters.
+    Adds `stage` (1 or 2) to fit's dict."""
+    f = fit(keys, seed, m, STAGE1_STEPS, batch, residual)
+    if early_accept(f["estimates"][f["choice"]], m):
+        f["stage"] = 1
+        return f
+    f = fit(keys, seed, m, STAGE2_STEPS, batch, residual)
+    f["stage"] = 2
+    return f

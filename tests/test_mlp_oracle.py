@@ -357,3 +357,33 @@ def test_choice_takes_the_smallest_sample_judge_first_on_ties():
     # a perfect root: all three candidates tie and the root wins
     sp2, choice2, est2, _ = M.choose_splitters(s, x, t, t)
     assert choice2 == 0 and est2[0] == min(est2)
+
+
+def test_early_accept_threshold():
+    """The short fit is kept while its fullest range bin holds at most
+    1.3 m / 256 sample keys: 332.8 for m = 65536, so 332 passes and 333 does
+    not; m = 2560 gives exactly 13."""
+    assert M.early_accept(332, 1 << 16) and not M.early_accept(333, 1 << 16)
+    assert M.early_accept(13, 2560) and not M.early_accept(14, 2560)
+    assert M.early_accept(0, 1)
+
+
+def test_staged_budget_keeps_the_short_fit_or_redoes_the_long_one():
+    """Uniform keys are split well after 32 steps, so the staged fit is the
+    32-step fit; lognormal keys are not, so it is the 128-step fit from the
+    same initial parameters (same splitters, same losses)."""
+    n = 1 << 20
+    keys = W.uniform_u32(n, seed=0)
+    f = M.fit_staged(keys, seed=0)
+    short = M.fit(keys, seed=0, steps=M.STAGE1_STEPS)
+    assert f["stage"] == 1
+    assert np.array_equal(f["splitters"], short["splitters"])
+    assert M.early_accept(short["estimates"][short["choice"]], 1 << 16)
+    keys = W.lognormal_u64(n, seed=0)
+    f = M.fit_staged(keys, seed=0)
+    short = M.fit(keys, seed=0, steps=M.STAGE1_STEPS)
+    long = M.fit(keys, seed=0, steps=M.STAGE2_STEPS)
+    assert f["stage"] == 2
+    assert not M.early_accept(short["estimates"][short["choice"]], 1 << 16)
+    assert np.array_equal(f["splitters"], long["splitters"])
+    assert np.array_equal(f["losses"], long["losses"])
