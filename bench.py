@@ -129,6 +129,7 @@ def summarize(ms, stats, n):
             "splitters": s0["learned_splitters"],
             "max_range_bin_over_fair": round(s0["learned_max_range_bin"] / (n / 256), 3),
             "final_loss": s0["learned_final_loss"],
+            "train_steps": s0["learned_steps"],
         })
     return out, part_ms, part_bytes, launches
 
@@ -489,6 +490,7 @@ def bench_learned_mixtures(pdq, torch, W, dev, args):
                 row[name].update({"learned_state": s0["learned"], "splitters": s0["learned_splitters"],
                                   "max_range_bin_over_fair": round(s0["learned_max_range_bin"] / (n / 256), 3),
                                   "fit_ms": round(float(np.mean([x["learned_fit_ms"] for x in st[1:]])), 3),
+                                  "train_steps": s0["learned_steps"],
                                   "equal_bin_keys": s0["learned_equal_elements"]})
         row["learned_over_plain"] = round(row["plain"]["ms"] / row["learned"]["ms"], 3)
         rows[dist] = row

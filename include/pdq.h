@@ -143,7 +143,10 @@ typedef struct pdq_options {
                             the sample, initial weights and minibatches of PDQ_LEARNED */
   float learned_imbalance_limit; /* PDQ_LEARNED: fall back to the plain path when a range bin holds
                                     more than limit * n / 256 keys; 0 = 2.0; < 0 = always fall back */
-  uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps, 0 = 128 (at most 65536) */
+  uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps (at most 65536); 0 = the staged budget: a
+                            32-step fit, kept when its chosen splitters put at most 1.3 m/256 of
+                            the m sample keys into one range bin, else a 128-step fit from the
+                            same initial parameters (one synchronisation between the two) */
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
@@ -212,7 +215,8 @@ typedef struct pdq_stats {
   uint64_t near_sorted_outliers;  /* keys in short runs (near_sorted == 1) */
   uint32_t learned_choice;        /* PDQ_LEARNED: splitters taken from 0 the network, 1 its x-leaves,
                                      2 its y-leaves (pdq_learned.h) */
-  uint32_t pad2_;
+  uint32_t learned_steps;         /* PDQ_LEARNED: Adam steps of the kept fit (with learn_steps 0: 32
+                                     when the short fit was kept, else 128) */
   uint64_t learned_sample_judge;  /* PDQ_LEARNED: sample keys in the fullest range bin of the chosen
                                      splitters (of PDQ_LEARN_SAMPLE) */
 } pdq_stats;

@@ -9,7 +9,8 @@
  *   2. pdq_learned_features: feature x and mid-rank CDF target t of every
  *      sorted sample key;
  *   3. pdq_mlp_train: Adam on the 1 -> 32 -> 32 -> 1 ReLU MLP
- *      y = x + W3 . relu(W2 relu(W1 x + b1) + b2) + b3;
+ *      y = x + W3 . relu(W2 relu(W1 x + b1) + b2) + b3 (by default 32
+ *      steps, and 128 when steps 4-5 judge the 32-step fit too uneven);
  *   4. pdq_mlp_infer, then pdq_learned_leaves: a second stage of 64 linear
  *      leaves (a two-level learned CDF model, as in learned index
  *      structures) refines the network's prediction two ways;
@@ -153,7 +154,8 @@ typedef struct pdq_fit_buffers {
   float* d_t;            /* [PDQ_LEARN_SAMPLE] targets */
   float* d_pred;         /* [PDQ_LEARN_SAMPLE] float32 predictions after training */
   float* d_params;       /* [PDQ_MLP_PARAMS] trained parameters */
-  float* d_losses;       /* [learn_steps] minibatch losses */
+  float* d_losses;       /* [learn_steps, or 128 with the staged budget] minibatch losses of the
+                            kept fit */
   uint64_t* d_splitters; /* [PDQ_MAX_SPLITTERS] the chosen splitters */
   uint32_t* d_count;     /* [1] number of splitters */
   uint64_t* d_info;      /* [8]: [0..2] as in pdq_learned_features; [3] the chosen candidate (0 the
@@ -166,7 +168,9 @@ size_t pdq_learned_fit_workspace_bytes(const pdq_options* opt);
 
 /* Steps 1-5 on d_keys[0..n) (n >= 1) with opt's seed and learn_* fields:
  * the whole fit that PDQ_LEARNED runs before its histogram, queued on
- * `stream` without a synchronisation. */
+ * `stream` without a synchronisation when learn_steps is set; with
+ * learn_steps 0 it runs the staged budget (pdq.h), which synchronises
+ * `stream` once to judge the 32-step fit. d_losses needs 128 entries then. */
 int pdq_learned_fit(const void* d_keys, size_t n, pdq_key_type key_type, void* d_ws, size_t ws_bytes,
                     void* stream, const pdq_options* opt, const pdq_fit_buffers* out);
 

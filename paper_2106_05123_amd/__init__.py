@@ -114,12 +114,12 @@ class Stats(ctypes.Structure):
         ("near_sorted_runs", ctypes.c_uint64),
         ("near_sorted_outliers", ctypes.c_uint64),
         ("learned_choice", ctypes.c_uint32),
-        ("pad2_", ctypes.c_uint32),
+        ("learned_steps", ctypes.c_uint32),
         ("learned_sample_judge", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "pad_", "pad2_")}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f not in ("struct_size", "pad_")}
 
 
 class FitBuffers(ctypes.Structure):

@@ -70,6 +70,7 @@ constexpr uint32_t kMaxPasses = 20000;  // far above any reachable pass count; a
 constexpr uint64_t kLearnSample = PDQ_LEARN_SAMPLE;
 constexpr uint32_t kMaxTrainGrid = 64;
 constexpr uint32_t kMaxLearnSteps = 65536;
+constexpr uint32_t kStage1Steps = 32;  // the staged budget's short fit
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -275,6 +276,7 @@ struct Opts {
   uint64_t seed = 0;
   float limit = 2.0f;
   uint32_t steps = 128;
+  bool staged = true;        // learn_steps 0: the staged budget (kStage1Steps, then `steps` if needed)
   uint32_t batch = 1024;
   uint32_t grid = 16;
   uint32_t batch_shape = 0;  // 0 = tuned or default, else shape index + 1
@@ -295,7 +297,10 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, seed) + sizeof(uint64_t)) out->seed = o->seed;
   if (sz >= offsetof(pdq_options, learned_imbalance_limit) + sizeof(float) && o->learned_imbalance_limit != 0.0f)
     out->limit = o->learned_imbalance_limit;
-  if (sz >= offsetof(pdq_options, learn_steps) + sizeof(uint32_t) && o->learn_steps) out->steps = o->learn_steps;
+  if (sz >= offsetof(pdq_options, learn_steps) + sizeof(uint32_t) && o->learn_steps) {
+    out->steps = o->learn_steps;
+    out->staged = false;
+  }
   if (sz >= offsetof(pdq_options, learn_batch) + sizeof(uint32_t) && o->learn_batch) out->batch = o->learn_batch;
   if (sz >= offsetof(pdq_options, learn_grid) + sizeof(uint32_t) && o->learn_grid) out->grid = o->learn_grid;
   if (sz >= offsetof(pdq_options, batch_shape) + sizeof(uint32_t)) out->batch_shape = o->batch_shape;
@@ -457,18 +462,29 @@ FitBufs fit_bufs(char* out, char* scratch, uint32_t steps, uint32_t grid) {
 // all queued on the stream without a synchronisation. info[7] says whether
 // the winner's sample judge is within `go_limit` sample keys (the histogram
 // kernels run only then).
-int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s,
-            uint64_t go_limit = ~0ull) {
+// The sample: m keys at hashed positions, sorted, with their features and
+// targets.
+int run_fit_sample(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s) {
   const uint64_t m = kLearnSample;
   HIP_TRY(launch_sample(kt, keys, n, m, o.seed, f.raw, s));
   HIP_TRY(launch_sample_sort(f.raw, m, f.sample, s));
   HIP_TRY(launch_features(f.sample, m, f.x, f.t, f.info, s));
+  return PDQ_OK;
+}
+
+// Training of `steps` Adam steps from the seeded initial parameters,
+// inference, the second stage, three candidate splitter sets judged on the
+// sample and the best one kept, all queued without a synchronisation.
+// info[7] says whether the winner's sample judge is within `go_limit`
+// sample keys (the histogram kernels run only then).
+int run_fit_model(const Opts& o, uint32_t steps, const FitBufs& f, hipStream_t s, uint64_t go_limit) {
+  const uint64_t m = kLearnSample;
   TrainArgs a;
   a.x = f.x;
   a.t = f.t;
   a.m = m;
   a.seed = o.seed;
-  a.steps = o.steps;
+  a.steps = steps;
   a.batch = o.batch;
   a.grid = o.grid;
   a.residual = 1;
@@ -489,6 +505,37 @@ int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitB
   HIP_TRY(launch_sample_judge(f.sample, m, f.cand, 256, f.cand_count, kCandidates, f.est, s));
   HIP_TRY(launch_pick(f.cand, 256, f.cand_count, f.est, kCandidates, go_limit, f.splitters, f.count, f.info, s));
   return PDQ_OK;
+}
+
+// Whether a short fit is kept: its fullest range bin holds at most
+// 1.3 m / 256 sample keys (judge * 2560 <= 13 m).
+bool early_accept(uint64_t judge, uint64_t m) { return judge * 2560ull <= 13ull * m; }
+
+// The whole fit. With the staged budget (learn_steps 0) a kStage1Steps fit
+// is judged first (one synchronisation to read its sample judge) and kept
+// when early_accept holds; otherwise the model is trained again from the
+// same initial parameters for o.steps steps. *steps_run receives the steps
+// of the kept fit.
+int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s,
+            uint64_t go_limit = ~0ull, uint32_t* steps_run = nullptr) {
+  int rc = run_fit_sample(keys, n, kt, o, f, s);
+  if (rc != PDQ_OK) return rc;
+  uint32_t steps = o.steps;
+  if (o.staged && kStage1Steps < o.steps) {
+    rc = run_fit_model(o, kStage1Steps, f, s, go_limit);
+    if (rc != PDQ_OK) return rc;
+    uint64_t info[kInfoWords] = {};
+    HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t choice = info[3] < kCandidates ? info[3] : 0;
+    if (early_accept(info[4 + choice], kLearnSample)) {
+      if (steps_run) *steps_run = kStage1Steps;
+      return PDQ_OK;
+    }
+  }
+  rc = run_fit_model(o, steps, f, s, go_limit);
+  if (rc == PDQ_OK && steps_run) *steps_run = steps;
+  return rc;
 }
 
 BucketBufs bucket_bufs(char* area, uint64_t n, const uint64_t* splitters, const uint32_t* count) {
@@ -525,7 +572,7 @@ struct EventPair {
 // What the learned first pass found, for the statistics.
 struct LearnedResult {
   uint32_t state = 0;  // 0 not run, 1 used, 2 fell back
-  uint32_t splitters = 0, use_log = 0, ordered = 0, choice = 0;
+  uint32_t splitters = 0, use_log = 0, ordered = 0, choice = 0, steps = 0;
   uint64_t sample_judge = 0;
   uint64_t max_range = 0, equal = 0;
   float loss = 0.0f;
@@ -566,8 +613,10 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
                                      : -1.0;
   const uint64_t go_limit = lim >= 0.0 ? static_cast<uint64_t>(lim) : 0ull;
   b.go = f.info + 7;
-  int rc = run_fit(c.keys[0], n, kt, o, f, s, go_limit);
+  uint32_t steps_run = o.steps;
+  int rc = run_fit(c.keys[0], n, kt, o, f, s, go_limit, &steps_run);
   if (rc != PDQ_OK) return rc;
+  res.steps = steps_run;
   if (prof) {
     HIP_TRY(hipEventRecord(e_fit.b, s));
     HIP_TRY(hipEventRecord(e_hist.a, s));
@@ -584,7 +633,7 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   HIP_TRY(hipMemcpyAsync(&count, f.count, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(sync, f.sync, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&loss, f.losses + (o.steps - 1), 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&loss, f.losses + (steps_run - 1), 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   res.splitters = count;
   res.use_log = static_cast<uint32_t>(info[2]);
@@ -1236,6 +1285,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     st->learned_final_loss = lres.loss;
     st->learned_use_log = lres.use_log;
     st->learned_choice = lres.choice;
+    st->learned_steps = lres.steps;
     st->learned_sample_judge = lres.sample_judge;
     st->learned_fit_ms = lres.fit_ms;
     st->learned_hist_ms = lres.hist_ms;

@@ -297,7 +297,7 @@ def test_trained_network_gains_over_untrained(dist):
     sort partitions far fewer keys than the plain path."""
     n = 1 << 22
     keys = DISTS[dist](n, 0)
-    f = pdq.learned_fit(dev(keys), seed=0)
+    f = pdq.learned_fit(dev(keys), seed=0, learn_steps=128)
     sp_tr, _ = pdq.learned_extract(f["sample"], f["pred"])
     h_tr = host(pdq.bucket_histogram(dev(keys), sp_tr))
     p0 = M.init_params(0, host(f["x"]))
@@ -314,6 +314,31 @@ def test_trained_network_gains_over_untrained(dist):
     assert st_l["learned"] == 1
     assert st_l["element_visits"] < 0.6 * st_p["element_visits"]
     assert st_l["passes"] < st_p["passes"]
+
+
+@pytest.mark.parametrize("dist", ["uniform_u32", "lognormal_u64", "zipf_u64"])
+def test_staged_budget_follows_the_rule(dist):
+    """The default budget: the 32-step fit is kept exactly when its sample
+    judge passes the early-accept rule (checked with the oracle's rule on the
+    GPU's own 32-step judge), else the fit is the 128-step fit; parameters
+    and splitters are bitwise those of the corresponding single-budget fit,
+    and the sort reports the steps it kept."""
+    n = 1 << 22
+    keys = DISTS[dist](n, 0)
+    short = pdq.learned_fit(dev(keys), seed=0, learn_steps=M.STAGE1_STEPS)
+    info = host(short["info"])
+    keep = M.early_accept(int(info[4 + int(info[3])]), pdq.LEARN_SAMPLE)
+    staged = pdq.learned_fit(dev(keys), seed=0)
+    want = short if keep else pdq.learned_fit(dev(keys), seed=0, learn_steps=M.STAGE2_STEPS)
+    assert np.array_equal(host(staged["splitters"]), host(want["splitters"]))
+    assert np.array_equal(host(staged["params"]).view(np.uint32), host(want["params"]).view(np.uint32))
+    out, _, st = gpu_sort(keys, learned=True)
+    assert st["learned_steps"] == (M.STAGE1_STEPS if keep else M.STAGE2_STEPS)
+    assert np.array_equal(out, np.sort(keys))
+    if dist == "uniform_u32":
+        assert keep  # uniform keys are split evenly after the short fit
+    if dist == "lognormal_u64":
+        assert not keep
 
 
 @pytest.mark.parametrize("dist", ["uniform_u32", "lognormal_u64", "zipf_u64", "gmm_u64"])
