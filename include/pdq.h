@@ -40,15 +40,17 @@
  * pdq_workspace_bytes; 256-byte alignment recommended). d_ws must stay
  * allocated until the work queued on `stream` has finished. No pointer is
  * kept after a call returns. `stream` is a hipStream_t (NULL = the default
- * stream). The host-driven sorts (pdq_sort, pdq_sort_pairs, and
- * pdq_segmented_sort without PDQ_BATCHED) read the number of live segments
- * after each partition pass: each pass ends with an asynchronous copy of the
- * pass counters into pinned host memory (a few small blocks the library
- * allocates on first use, one per concurrent call and device, kept until
- * the process ends), and the host waits for one pass's counters while the
- * next pass already runs. They return once the last pass is queued (its
- * finishing work may still run) unless `stats` is non-NULL or PDQ_VALIDATE
- * is set, which synchronise `stream` at the end.
+ * stream). pdq_sort and pdq_sort_pairs queue their partition passes with
+ * device-side counts (see pdq_sort). The host-driven pass loop
+ * (pdq_segmented_sort without PDQ_BATCHED, PDQ_HOST_LOOP) reads the number
+ * of live segments after each pass: each pass ends with an asynchronous
+ * copy of the pass counters into pinned host memory (a few small blocks the
+ * library allocates on first use, one per concurrent call and device, kept
+ * until the process ends), and the host waits for one pass's counters while
+ * the next pass already runs. Calls return once their work is queued (it
+ * may still run) unless `stats` is non-NULL or PDQ_VALIDATE is set, which
+ * synchronise `stream` at the end; pdq_check reports device-side errors of
+ * a call that returned early.
  *
  * Errors: every entry point returns PDQ_OK (0) or a negative status; no
  * exception crosses the ABI. n <= 1 is a no-op returning PDQ_OK.
@@ -124,6 +126,9 @@ enum pdq_flags {
                              pdq_plan_create and pdq_sort_noalloc points to uint64_t payloads
                              (8-byte aligned) instead of uint32_t; pass the same options to
                              pdq_workspace_bytes (12 more bytes per key) */
+  PDQ_HOST_LOOP = 1u << 8, /* pdq_sort / pdq_sort_pairs: the host-driven pass loop (the host reads
+                             each pass's counters, one pass behind) instead of the default
+                             device-counted passes; needs less workspace */
   PDQ_FRESH_FIXED = 1u << 6 /* after a bad partition take the fresh pivot candidates at the fixed
                              quarter offsets of Section 4.2's deterministic rule instead of the
                              default hashed positions (Section 4.2's randomised rule; the hash
@@ -152,10 +157,11 @@ typedef struct pdq_options {
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape
                             (partition tile, slots per lane of the two widest LDS classes):
                             (8192, 16), (16384, 16), (32768, 16), (8192, 32) */
-  uint32_t batch_passes; /* PDQ_BATCHED: 0 = automatic (the halvings that bring the largest
-                            segment to the widest LDS class, plus 2); k > 0 = k - 1 passes (at
-                            most 20); segments still live after them finish in the persistent
-                            tail */
+  uint32_t batch_passes; /* device-counted passes (PDQ_BATCHED, and pdq_sort without
+                            PDQ_HOST_LOOP): 0 = automatic (h + 2 + h/3, h the halvings that
+                            bring the largest segment to the widest LDS class); k > 0 = k - 1
+                            passes (at most 24); segments still live after them finish in the
+                            persistent tail */
   uint32_t waves;        /* 0 = each LDS base-case size class takes its default (or tuned)
                             workgroup shape; 1, 2, 4, 8 or 16 = every class that has a shape of
                             that many waves per workgroup takes it (pdq_plan_classes lists the
@@ -227,7 +233,12 @@ typedef struct pdq_stats {
 size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has_vals,
                            const pdq_options* opt);
 
-/* Sort d_keys[0..n) ascending in place. */
+/* Sort d_keys[0..n) ascending in place (Sections 3-5; the paper's pdqsort on
+ * one range). By default the partition passes take their counts on the
+ * device: after the near-sorted check (a single synchronisation for n >=
+ * 16384) and, with PDQ_LEARNED, the fit and the judge, the passes, the
+ * persistent tail and the finishing kernels are queued without reading
+ * anything back. PDQ_HOST_LOOP selects the host-driven pass loop. */
 int pdq_sort(void* d_keys, size_t n, pdq_key_type key_type, pdq_order order, void* d_ws,
              size_t ws_bytes, void* stream, const pdq_options* opt, pdq_stats* stats);
 
@@ -246,7 +257,9 @@ int pdq_segmented_sort(void* d_keys, uint32_t* d_vals, size_t n, const uint64_t*
 
 /* A captured batched segmented sort: the launch sequence of
  * pdq_segmented_sort with PDQ_BATCHED for these exact buffers, instantiated
- * once as a HIP graph and replayed by pdq_plan_launch. The plan owns host
+ * once as a HIP graph and replayed by pdq_plan_launch; with d_offsets NULL
+ * and nseg 1 the sort of the one range [0, n) (the device-counted passes of
+ * pdq_sort without the near-sorted check). The plan owns host
  * memory and the graph only; the caller keeps d_keys, d_vals, d_offsets and
  * d_ws alive and unchanged in size while the plan exists, and may refill
  * them between launches. With PDQ_AUTOTUNE in opt->flags the persistent
@@ -289,13 +302,13 @@ void pdq_plan_destroy(pdq_plan* plan);
  * allocation). d_vals may be NULL (keys only, as pdq_sort) or a uint32
  * (uint64 with PDQ_VALS64) payload moved with the keys (as pdq_sort_pairs).
  * A call whose
- * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt) exceeds
+ * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt with PDQ_HOST_LOOP added) exceeds
  * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
  * (without PDQ_LEARNED: up to 15,662,528 uint32 keys, 8,079,232 uint32 keys
  * with payloads, 8,079,264 uint64 keys, 5,443,392 uint64 keys with
- * payloads). Unlike pdq_sort, it runs one host synchronisation per partition
- * pass (the pipelined pass loop needs pinned host memory, which it does not
- * allocate). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return
+ * payloads). Unlike pdq_sort, it runs the host-driven pass loop with one host
+ * synchronisation per partition pass (its smaller workspace fits more keys
+ * into the array, and it allocates no pinned host memory). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return
  * PDQ_ERR_UNSUPPORTED. Every call on one GPU shares that GPU's array, which
  * keeps the previous call's contents (the call clears what must start at
  * zero): calls that overlap in time on one GPU -- on different streams, or

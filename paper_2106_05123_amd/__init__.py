@@ -27,7 +27,7 @@ __all__ = [
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
     "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "learned_leaves", "sample_judge", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
-    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED", "FLAG_VALS64",
+    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED", "FLAG_VALS64", "FLAG_HOST_LOOP",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -45,6 +45,7 @@ FLAG_AUTOTUNE = 16
 FLAG_DETERMINISTIC = 32
 FLAG_FRESH_FIXED = 64
 FLAG_VALS64 = 128
+FLAG_HOST_LOOP = 256
 # batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
 BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
@@ -281,19 +282,22 @@ def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
           workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
           learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False,
-          fresh_fixed: bool = False, waves: int = 0):
+          fresh_fixed: bool = False, waves: int = 0, host_loop: bool = False, batch_passes: int | None = None):
     """Sort a 1-D device tensor in place (ascending canonical order).
     learned=True runs the learned multiway first pass (see pdq_learned.h);
     deterministic=True selects the look-back partition (PDQ_DETERMINISTIC);
     fresh_fixed=True takes fresh pivot candidates at fixed offsets after a
     bad partition (PDQ_FRESH_FIXED) instead of hashed positions; waves
-    (1, 2, 4, 8, 16) sets the workgroup shape of the LDS base-case classes."""
+    (1, 2, 4, 8, 16) sets the workgroup shape of the LDS base-case classes;
+    host_loop=True runs the host-driven pass loop (PDQ_HOST_LOOP) instead of
+    the device-counted passes, whose number batch_passes overrides."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
-                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace,
-                                         dict(learn, waves=waves))
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0) |
+                                         (FLAG_HOST_LOOP if host_loop else 0), workspace,
+                                         dict(learn, waves=waves, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
                         need, stream, ctypes.byref(opt), ctypes.byref(st) if st is not None else None)
@@ -304,15 +308,17 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
 def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
                 imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
-                deterministic: bool = False, fresh_fixed: bool = False, waves: int = 0):
+                deterministic: bool = False, fresh_fixed: bool = False, waves: int = 0, host_loop: bool = False,
+                batch_passes: int | None = None):
     """Sort keys in place and move the payload `vals` (uint32, or uint64:
     PDQ_VALS64) with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, vals, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
-                                         (FLAG_FRESH_FIXED if fresh_fixed else 0), workspace,
-                                         dict(learn, waves=waves))
+                                         (FLAG_FRESH_FIXED if fresh_fixed else 0) |
+                                         (FLAG_HOST_LOOP if host_loop else 0), workspace,
+                                         dict(learn, waves=waves, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),
                               kt, 0, ctypes.c_void_p(ws.data_ptr()), need, stream, ctypes.byref(opt),
@@ -526,16 +532,18 @@ def _destroy_live_plans():
 
 class Plan:
     """A captured batched segmented sort bound to these tensors (see
-    pdq_plan_create). launch() replays the graph on the current stream."""
+    pdq_plan_create); offsets=None captures the sort of one range [0, n).
+    launch() replays the graph on the current stream."""
 
     def __init__(self, keys, offsets, vals=None, *, autotune: bool = False, batch_shape: int = 0,
                  batch_passes: int | None = None, force_budget: int = -1, workspace=None, waves: int = 0,
                  tune_cache_path: str | None = None):
         # the workspace must be sized with the same flags (batched, autotune)
         import torch
-        if offsets.dtype != torch.uint64 or not offsets.is_cuda or not offsets.is_contiguous():
+        if offsets is not None and (offsets.dtype != torch.uint64 or not offsets.is_cuda or
+                                    not offsets.is_contiguous()):
             raise ValueError("offsets must be a contiguous uint64 device tensor")
-        nseg = offsets.numel() - 1
+        nseg = offsets.numel() - 1 if offsets is not None else 1
         flags = FLAG_BATCHED | (FLAG_AUTOTUNE if autotune else 0)
         kt, opt, ws, need, stream = _prepare(keys, vals, nseg, force_budget, 0, flags, workspace,
                                              dict(batch_shape=batch_shape, batch_passes=batch_passes, waves=waves,

@@ -60,9 +60,9 @@ constexpr BatchShape kShapes[kBatchShapes] = {{8192, 16, 0}, {16384, 16, 0}, {32
 // the widest classes (shape 3) is one of their per-class variants.
 constexpr int kTunedShapes = 3;
 
-// Passes the batched form captures at most; deeper recursions finish in the
-// persistent tail.
-constexpr uint32_t kMaxBatchPasses = 20;
+// Passes the device-counted form queues at most; deeper recursions finish in
+// the persistent tail.
+constexpr uint32_t kMaxBatchPasses = 24;
 
 struct BatchArgs {
   BatchQ* q;

@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_pivot(Ctx c, int parity, uint32
   if (nseg > c.max_active) nseg = c.max_active;  // an overfull list is flagged, never read past
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c.ctr->visits += c.ctr->elems[parity];
+    if (nseg) c.ctr->live_passes += 1;
     c.ctr->list[parity ^ 1] = 0;
     c.ctr->elems[parity ^ 1] = 0;
     c.ctr->maxlen[parity ^ 1] = 0;

@@ -310,7 +310,7 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, tune_cache_path) + sizeof(const char*)) out->tune_cache = o->tune_cache_path;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
-                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64))
+                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64 | PDQ_HOST_LOOP))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->waves != 0 && out->waves != 1 && out->waves != 2 && out->waves != 4 && out->waves != 8 &&
@@ -386,9 +386,10 @@ struct PinBlock {
 };
 std::mutex g_pin_mu;
 std::vector<PinBlock*> g_pin_free;
-// set while pdq_sort_noalloc runs: it allocates nothing, so it keeps the
-// loop with one synchronisation per pass
-thread_local bool t_no_pin = false;
+// set while pdq_sort_noalloc runs (and sizes its call): it allocates
+// nothing and its scratch array is sized for the host-driven loop, so it
+// keeps that loop with one synchronisation per pass
+thread_local bool t_noalloc = false;
 
 PinBlock* pin_acquire() {
   int dev = -1;
@@ -896,6 +897,11 @@ Ctx batch_ctx(Ctx c, const Opts& o, const Tuned& t) {
 // Passes queued for a largest segment of m keys: the halvings that bring it
 // to the widest LDS class, plus two for uneven splits. Anything deeper
 // finishes in the persistent tail.
+// Device-counted passes to queue for a largest segment of m keys: the
+// halvings that bring it to base_max, plus 2 and a third of them again
+// (splits are uneven, so some paths need more passes; a pass that finds no
+// live segment costs a few microseconds, while a segment left to the
+// persistent tail is partitioned by a single workgroup).
 uint32_t batch_passes(uint64_t m, uint32_t base_max) {
   uint32_t p = 0;
   while (m > base_max && p < kMaxBatchPasses) {
@@ -903,7 +909,7 @@ uint32_t batch_passes(uint64_t m, uint32_t base_max) {
     ++p;
   }
   if (p == 0) return 0;
-  p += 2;
+  p += 2 + p / 3;
   return p < kMaxBatchPasses ? p : kMaxBatchPasses;
 }
 
@@ -929,17 +935,27 @@ int batch_probe(const Ctx& c, const Opts& o, hipStream_t s, uint32_t* passes) {
 // The rest, with no host synchronisation (capturable): `passes` partition
 // passes whose kernels read their counts on the device, the persistent tail
 // over whatever is still live, then every item list finished once.
+// `src0`: the buffer the live segments of list 0 are in. `timed`: events
+// around every partition launch (PDQ_PROFILE).
 int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passes, int tail, hipStream_t s,
-                       EventPair* class_ev = nullptr) {
+                       EventPair* class_ev = nullptr, uint32_t src0 = 0, std::vector<Timed>* timed = nullptr) {
   const BatchArgs b = batch_args(L, base);
   const uint32_t grid = batch_grid(c, tail);
   if (grid == 0) return PDQ_ERR_HIP;
   int parity = 0;
-  uint32_t src = 0;
+  uint32_t src = src0;
   for (uint32_t p = 0; p < passes; ++p) {
     HIP_TRY(launch_pivot(c, parity, c.max_active, src, s));
     HIP_TRY(launch_tilemap(c, parity, c.max_tiles, s));
+    if (timed) {
+      Timed tm;
+      HIP_TRY(hipEventCreate(&tm.a));
+      timed->push_back(tm);
+      HIP_TRY(hipEventCreate(&timed->back().b));
+      HIP_TRY(hipEventRecord(timed->back().a, s));
+    }
     HIP_TRY(launch_partition(c, parity, c.max_tiles, src, s));
+    if (timed) HIP_TRY(hipEventRecord(timed->back().b, s));
     HIP_TRY(launch_bookkeep(c, parity, c.max_active, src, p, s));
     parity ^= 1;
     src ^= 1u;
@@ -956,6 +972,91 @@ int enqueue_batch_rest(const Ctx& c, const Layout& L, char* base, uint32_t passe
   }
   HIP_TRY(launch_heap(c, c.max_items, s));
   HIP_TRY(launch_copy(c, c.max_items, s));
+  return PDQ_OK;
+}
+
+// Whether a call runs the device-counted passes: single-range sorts, unless
+// PDQ_HOST_LOOP asks for the host-driven loop or pdq_sort_noalloc runs (its
+// scratch array is sized for the host loop's smaller workspace).
+bool device_passes(const uint64_t* offsets, const Opts& o) {
+  return !offsets && !(o.flags & PDQ_HOST_LOOP) && !t_noalloc;
+}
+
+// The statistics every form reads from the final counters.
+void fill_pass_stats(pdq_stats* st, const Counters& snap) {
+  st->element_visits = snap.visits;
+  st->partitions_right = snap.partitions_right;
+  st->partitions_left = snap.partitions_left;
+  st->bad_partitions = snap.bad_partitions;
+  st->heapsort_segments = snap.heap_segments;
+  st->heapsort_elements = snap.heap_elements;
+  st->base_segments = snap.base_segments;
+  st->base_elements = snap.base_elements;
+  st->sorted_segments = snap.sorted_segments;
+  st->sorted_elements = snap.sorted_elements;
+  st->equal_elements = snap.equal_elements;
+  st->first_pivot_image = snap.first_pivot_image;
+  st->first_left_size = snap.first_left;
+  st->first_mode = snap.first_mode;
+}
+
+void fill_learned_stats(pdq_stats* st, const LearnedResult& lres) {
+  st->learned = lres.state;
+  st->learned_splitters = lres.splitters;
+  st->learned_max_range_bin = lres.max_range;
+  st->learned_equal_elements = lres.state == 1 ? lres.equal : 0;
+  st->learned_final_loss = lres.loss;
+  st->learned_use_log = lres.use_log;
+  st->learned_choice = lres.choice;
+  st->learned_steps = lres.steps;
+  st->learned_sample_judge = lres.sample_judge;
+  st->learned_fit_ms = lres.fit_ms;
+  st->learned_hist_ms = lres.hist_ms;
+  st->learned_scatter_ms = lres.scatter_ms;
+  st->learned_hist_bytes = lres.hist_bytes;
+  st->learned_scatter_bytes = lres.scatter_bytes;
+}
+
+// Partition launch times of PDQ_PROFILE: their sum, and the first launch.
+void fill_profile_stats(pdq_stats* st, const std::vector<Timed>& timed, uint64_t total_bytes) {
+  double total = 0;
+  for (size_t i = 0; i < timed.size(); ++i) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, timed[i].a, timed[i].b);
+    total += ms;
+    if (i == 0) {
+      st->first_pass_ms = ms;
+      st->first_pass_bytes = timed[i].bytes;
+    }
+  }
+  st->partition_launches = static_cast<uint32_t>(timed.size());
+  st->partition_ms = total;
+  st->partition_bytes = total_bytes;
+}
+
+// Statistics of a single-range sort that ran the device-counted passes (one
+// synchronisation, here at the end). Device-side errors are reported now.
+int device_pass_stats(const Ctx& c, const Layout& L, char* base, uint32_t kb, bool vals, const LearnedResult& lres,
+                      bool prof, const std::vector<Timed>& timed, pdq_stats* st, hipStream_t s) {
+  Counters snap = {};
+  BatchQ q = {};
+  HIP_TRY(hipMemcpyAsync(&snap, c.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&q, batch_args(L, base).q, sizeof(BatchQ), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (snap.errors & kErrCapacity) return PDQ_ERR_INVALID;
+  if (snap.errors || q.error) return PDQ_ERR_DEVICE;
+  fill_pass_stats(st, snap);
+  st->passes = snap.live_passes;
+  st->batch_items = q.tail;
+  fill_learned_stats(st, lres);
+  if (prof) {
+    // the first launch's bytes are known for a plain single range (n keys);
+    // after the learned split they depend on the bins and are left at 0
+    std::vector<Timed> t = timed;
+    const uint64_t bpk = 2ull * kb + (vals ? 8ull : 0ull);
+    if (!t.empty() && lres.state != 1) t[0].bytes = c.n * bpk;
+    fill_profile_stats(st, t, snap.visits * bpk);
+  }
   return PDQ_OK;
 }
 
@@ -983,18 +1084,8 @@ int run_batched(const Ctx& c0, const Opts& o, const Layout& L, char* base, pdq_s
   HIP_TRY(hipStreamSynchronize(s));
   if (snap.errors & kErrCapacity) return PDQ_ERR_INVALID;
   if (snap.errors || q.error) return PDQ_ERR_DEVICE;
+  fill_pass_stats(st, snap);
   st->passes = passes;
-  st->element_visits = snap.visits;
-  st->partitions_right = snap.partitions_right;
-  st->partitions_left = snap.partitions_left;
-  st->bad_partitions = snap.bad_partitions;
-  st->heapsort_segments = snap.heap_segments;
-  st->heapsort_elements = snap.heap_elements;
-  st->base_segments = snap.base_segments;
-  st->base_elements = snap.base_elements;
-  st->sorted_segments = snap.sorted_segments;
-  st->sorted_elements = snap.sorted_elements;
-  st->equal_elements = snap.equal_elements;
   st->batch_items = q.tail;
   st->batch_shape = static_cast<uint32_t>(shape);
   if (prof) st->batch_ms = ev.ms();
@@ -1184,14 +1275,20 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   if (nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
   const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
   const bool batched = (o.flags & PDQ_BATCHED) && offsets;
+  const bool dev_passes = device_passes(offsets, o);
   const Layout L = make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals != nullptr, learned,
-                                    o.steps, o.grid, batched, false);
+                                    o.steps, o.grid, batched || dev_passes, false);
   if (!ws || ws_bytes < L.total) return PDQ_ERR_WORKSPACE;
 
   char* base = align_ptr(ws);
   Ctx c = make_ctx(keys, vals, n, offsets, nseg, kt, o, L, base);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (batched) return run_batched(c, o, L, base, st, s);
+  Tuned tc;
+  if (dev_passes) {
+    tc = tuned_config(c, o);
+    c = batch_ctx(c, o, tc);
+  }
   const bool prof = (o.flags & PDQ_PROFILE) && st;
   std::vector<Timed> timed;
   auto cleanup = [&]() {
@@ -1224,7 +1321,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   // the tile of the first pass, from the average size of its segments
   // (the learned bins hold at most 2n/256 keys each, or the fit is judged
   // failed; input segments are taken as equal until the first pass has run)
-  if (!o.tile) c.tile = auto_tile(n, learned ? n / 128 : n / (offsets ? nseg : 1));
+  if (!o.tile && !dev_passes) c.tile = auto_tile(n, learned ? n / 128 : n / (offsets ? nseg : 1));
   LearnedResult lres;
   uint32_t src = 0;
   if (learned) {
@@ -1232,9 +1329,18 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
     rc = run_learned(c, o, L, base, prof, lres, s);
     if (rc != PDQ_OK) return rc;
     if (lres.state == 1) src = 1;
-    else if (!o.tile) c.tile = auto_tile(n, n);  // judged and fell back: one segment [0, n)
+    else if (!o.tile && !dev_passes) c.tile = auto_tile(n, n);  // judged and fell back: one segment [0, n)
   }
   if (src == 0) HIP_TRY(launch_init(c, s));
+  if (dev_passes) {
+    // the largest live segment: the fullest range bin, or the whole input
+    const uint64_t maxseg = lres.state == 1 ? lres.max_range : n;
+    const uint32_t passes = o.batch_passes ? o.batch_passes - 1 : batch_passes(maxseg, c.base_max);
+    rc = enqueue_batch_rest(c, L, base, passes, kShapes[tc.shape].tail, s, nullptr, src, prof ? &timed : nullptr);
+    if (rc == PDQ_OK && st) rc = device_pass_stats(c, L, base, kb, vals != nullptr, lres, prof, timed, st, s);
+    cleanup();
+    return rc;
+  }
   rc = read_counters(c, &snap, s);
   if (rc != PDQ_OK) return rc;
   if ((o.flags & PDQ_VALIDATE) && snap.bad_offsets) return PDQ_ERR_INVALID;
@@ -1245,7 +1351,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   const uint64_t bytes_per_key = 2ull * kb + (vals ? 8ull : 0ull);
   uint32_t pass = 0;
   uint64_t visits = 0;
-  PinBlock* pin = t_no_pin ? nullptr : pin_acquire();
+  PinBlock* pin = t_noalloc ? nullptr : pin_acquire();
   if (pin) {
     rc = run_passes_pipelined(c, o, L, base, snap, src, prof, bytes_per_key, timed, &pass, &visits, pin, s);
     pin_release(pin);
@@ -1263,51 +1369,14 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
       cleanup();
       return r3;
     }
+    fill_pass_stats(st, snap);
     st->passes = pass;
     st->element_visits = visits;
-    st->partitions_right = snap.partitions_right;
-    st->partitions_left = snap.partitions_left;
-    st->bad_partitions = snap.bad_partitions;
-    st->heapsort_segments = snap.heap_segments;
-    st->heapsort_elements = snap.heap_elements;
-    st->base_segments = snap.base_segments;
-    st->base_elements = snap.base_elements;
-    st->sorted_segments = snap.sorted_segments;
-    st->sorted_elements = snap.sorted_elements;
-    st->equal_elements = snap.equal_elements;
-    st->first_pivot_image = snap.first_pivot_image;
-    st->first_left_size = snap.first_left;
-    st->first_mode = snap.first_mode;
-    st->learned = lres.state;
-    st->learned_splitters = lres.splitters;
-    st->learned_max_range_bin = lres.max_range;
-    st->learned_equal_elements = lres.state == 1 ? lres.equal : 0;
-    st->learned_final_loss = lres.loss;
-    st->learned_use_log = lres.use_log;
-    st->learned_choice = lres.choice;
-    st->learned_steps = lres.steps;
-    st->learned_sample_judge = lres.sample_judge;
-    st->learned_fit_ms = lres.fit_ms;
-    st->learned_hist_ms = lres.hist_ms;
-    st->learned_scatter_ms = lres.scatter_ms;
-    st->learned_hist_bytes = lres.hist_bytes;
-    st->learned_scatter_bytes = lres.scatter_bytes;
+    fill_learned_stats(st, lres);
     if (prof) {
-      double total = 0;
       uint64_t bytes = 0;
-      for (size_t i = 0; i < timed.size(); ++i) {
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, timed[i].a, timed[i].b);
-        total += ms;
-        bytes += timed[i].bytes;
-        if (i == 0) {
-          st->first_pass_ms = ms;
-          st->first_pass_bytes = timed[i].bytes;
-        }
-      }
-      st->partition_launches = static_cast<uint32_t>(timed.size());
-      st->partition_ms = total;
-      st->partition_bytes = bytes;
+      for (const Timed& t : timed) bytes += t.bytes;
+      fill_profile_stats(st, timed, bytes);
     }
   }
   cleanup();
@@ -1323,7 +1392,7 @@ size_t vals64_bytes(size_t n) { return align_up(n * 4) + align_up(n * 8); }
 // The layout a call uses (the same decisions as run_sort).
 Layout call_layout(size_t n, const uint64_t* offsets, size_t nseg, int kt, bool vals, const Opts& o) {
   const bool learned = (o.flags & PDQ_LEARNED) && !offsets && n > kLearnSample;
-  const bool batched = (o.flags & PDQ_BATCHED) && offsets;
+  const bool batched = ((o.flags & PDQ_BATCHED) && offsets) || device_passes(offsets, o);
   return make_layout_opts(n, offsets ? nseg : 1, static_cast<uint32_t>(kt), vals, learned, o.steps, o.grid, batched,
                           false);
 }
@@ -1415,7 +1484,9 @@ size_t pdq_workspace_bytes(size_t n, size_t nseg, pdq_key_type key_type, int has
   if (read_opts(opt, &o) != PDQ_OK) return 0;
   if (nseg == 0) nseg = 1;
   const bool learned = (o.flags & PDQ_LEARNED) && nseg == 1 && n > kLearnSample;
-  const bool batched = (o.flags & (PDQ_BATCHED | PDQ_AUTOTUNE)) != 0;
+  // one segment: enough for pdq_sort's device-counted passes as well
+  const bool batched = (o.flags & (PDQ_BATCHED | PDQ_AUTOTUNE)) != 0 ||
+                       (nseg == 1 && !(o.flags & PDQ_HOST_LOOP) && !t_noalloc);
   const size_t total = make_layout_opts(n, nseg, static_cast<uint32_t>(key_type), has_vals != 0, learned, o.steps,
                                         o.grid, batched, (o.flags & PDQ_AUTOTUNE) != 0)
                            .total;
@@ -1484,8 +1555,11 @@ int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_
   if (!valid_key_type(key_type) || order != PDQ_ASCENDING || n >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
   if (n > 1) {
     if (!d_keys) return PDQ_ERR_INVALID;
-    // the size check comes before anything touches the GPU
+    // the size check comes before anything touches the GPU (the layout of
+    // the host-driven pass loop, which this entry point runs)
+    t_noalloc = true;
     const size_t need = pdq_workspace_bytes(n, 1, key_type, d_vals != nullptr, opt);
+    t_noalloc = false;
     if (need == 0 || need > kNoAllocBytes) return PDQ_ERR_SCRATCH;
   }
   void* ws = nullptr;
@@ -1493,9 +1567,9 @@ int pdq_sort_noalloc(void* d_keys, uint32_t* d_vals, size_t n, pdq_key_type key_
     const int r2 = noalloc_scratch(&ws);
     if (r2 != PDQ_OK) return r2;
   }
-  t_no_pin = true;
+  t_noalloc = true;
   const int r3 = sort_entry(d_keys, d_vals, n, nullptr, 1, key_type, order, ws, kNoAllocBytes, stream, opt, stats);
-  t_no_pin = false;
+  t_noalloc = false;
   return r3;
 }
 
@@ -1525,7 +1599,8 @@ int pdq_plan_create(pdq_plan** plan, void* d_keys, uint32_t* d_vals, size_t n, c
   if (n == 0 || n >= (1ull << 32) || nseg == 0 || nseg >= (1ull << 32)) return PDQ_ERR_UNSUPPORTED;
   const uint32_t kb = key_bytes(static_cast<uint32_t>(key_type));
   const bool v64 = d_vals && (o.flags & PDQ_VALS64);
-  if (!d_keys || !d_offsets || reinterpret_cast<uintptr_t>(d_keys) % kb ||
+  // d_offsets NULL with nseg 1: one range [0, n)
+  if (!d_keys || (!d_offsets && nseg != 1) || reinterpret_cast<uintptr_t>(d_keys) % kb ||
       reinterpret_cast<uintptr_t>(d_offsets) % 8 || (d_vals && reinterpret_cast<uintptr_t>(d_vals) % (v64 ? 8 : 4)))
     return PDQ_ERR_INVALID;
   const bool tune = (o.flags & PDQ_AUTOTUNE) != 0;

@@ -101,7 +101,7 @@ struct Counters {
   int32_t first_mode;
   uint32_t bad_offsets;    // validation: offsets not monotone / not covering [0, n)
   uint32_t errors;         // kErr* bits: an internal inconsistency was caught and its writes skipped
-  uint32_t pad_;
+  uint32_t live_passes;    // partition passes that found at least one live segment
   uint32_t items1[kItemCounts];  // item set 1 (the pipelined pass loop alternates sets)
   uint32_t pad3_;
 };

@@ -280,10 +280,12 @@ def test_learned_equality_bins_and_fallback():
     assert st4["learned"] == 0 and np.array_equal(out4, np.sort(small))
 
 
-def test_learned_forced_heapsort_inside_bins():
-    n = 1 << 21
+# budget 0: range bins above the LDS base case go to heapsort (above 16384
+# keys with the device-counted passes, above 4096 with the host-driven loop)
+@pytest.mark.parametrize("n,host_loop", [(1 << 21, True), (1 << 23, False)])
+def test_learned_forced_heapsort_inside_bins(n, host_loop):
     a = W.uniform_u32(n, seed=8)
-    out, _, st = gpu_sort(a, learned=True, force_budget=0)
+    out, _, st = gpu_sort(a, learned=True, force_budget=0, host_loop=host_loop)
     assert st["learned"] == 1 and st["heapsort_segments"] >= 1
     assert np.array_equal(out, np.sort(a))
 

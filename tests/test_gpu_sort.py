@@ -238,7 +238,12 @@ def test_near_sorted_both_forms_and_sizes(learned):
         assert (st["near_sorted"] != 0) == (n >= 16384)
     a = W.uniform_u32(1 << 20, seed=2)
     out, _, st = gpu_sort(a, learned=learned)
-    assert np.array_equal(out, np.sort(a)) and st["near_sorted"] == 0 and st["passes"] > 0
+    assert np.array_equal(out, np.sort(a)) and st["near_sorted"] == 0
+    if learned:
+        # the learned split ran; its bins (~4096 keys) fit the LDS classes
+        assert st["learned"] == 1
+    else:
+        assert st["passes"] > 0
 
 
 # ------------------------------------------------------------------ fresh candidates (Section 4.2)
@@ -362,21 +367,87 @@ def test_segmented_validate_rejects_bad_offsets():
 
 # ------------------------------------------------------------------ fallbacks
 
-@pytest.mark.parametrize("n", [4097, 5000, 20000])
-def test_forced_heapsort(n):
+# a budget of 0 sends every segment above the LDS base case to heapsort: above
+# 4096 keys in the host-driven loop, above 16384 in the device-counted passes
+@pytest.mark.parametrize("n,host_loop", [(4097, True), (5000, True), (20000, True), (16385, False),
+                                         (20000, False), (100003, False)])
+def test_forced_heapsort(n, host_loop):
     a = W.uniform_u32(n, seed=n)
     v = W.index_payload(n)
-    out, vo, st = gpu_sort(a, v, force_budget=0)
+    out, vo, st = gpu_sort(a, v, force_budget=0, host_loop=host_loop)
     assert st["heapsort_segments"] == 1 and st["heapsort_elements"] == n
     assert np.array_equal(out, oracle.sort(a)[0])
     check_pairs(a, out, vo)
 
 
-def test_budget_one_reaches_heapsort_after_bad_partition():
-    a = W.pattern_i32("organ_pipe", 1 << 16)
-    out, _, st = gpu_sort(a, force_budget=1)
+@pytest.mark.parametrize("n,host_loop", [(1 << 16, True), (1 << 18, False)])
+def test_budget_one_reaches_heapsort_after_bad_partition(n, host_loop):
+    a = W.pattern_i32("organ_pipe", n)
+    out, _, st = gpu_sort(a, force_budget=1, host_loop=host_loop)
     assert st["bad_partitions"] >= 1 and st["heapsort_segments"] >= 1
     assert np.array_equal(out, oracle.sort(a)[0])
+
+
+# ------------------------------------------------------------------ pass loops
+
+@pytest.mark.parametrize("kt", ["u32", "f32", "u64", "i64"])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_host_loop_and_device_passes_agree(kt, pairs):
+    """The host-driven pass loop (PDQ_HOST_LOOP) and the default
+    device-counted passes give the oracle's keys, and payloads that travel
+    with their keys."""
+    n = (1 << 21) + 4321
+    a = W.random_keys(kt, n, seed=31)
+    v = W.index_payload(n) if pairs else None
+    ref = oracle.sort(a)[0]
+    for host_loop in (False, True):
+        out, vo, st = gpu_sort(a, v, host_loop=host_loop)
+        assert np.array_equal(as_bytes(out), as_bytes(ref)), f"host_loop={host_loop}"
+        if pairs:
+            check_pairs(a, out, vo)
+        assert st["passes"] > 0 and st["heapsort_segments"] == 0
+
+
+@pytest.mark.parametrize("passes", [0, 1, 3, 8])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_device_passes_cut_short_leave_the_rest_to_the_tail(passes, pairs):
+    """With fewer device-counted passes than the recursion needs, the
+    persistent tail partitions what is still live (single workgroups, a
+    device queue) and sorts the small pieces in LDS: keys still bit-exact."""
+    n = (1 << 20) + 77
+    a = W.uniform_u32(n, seed=passes)
+    v = W.index_payload(n) if pairs else None
+    out, vo, st = gpu_sort(a, v, batch_passes=passes)
+    assert np.array_equal(out, oracle.sort(a)[0])
+    if pairs:
+        check_pairs(a, out, vo)
+    assert st["passes"] <= passes
+    if passes < 3:
+        assert st["batch_items"] > 0
+
+
+def test_single_range_plan_replays_bit_exact():
+    """pdq_plan_create with no offsets captures the device-counted sort of
+    one range as a HIP graph: three replays on refilled buffers (eager work
+    and synchronisation between them) equal the oracle and the eager call."""
+    n = (1 << 22) + 1234
+    keys0 = W.uniform_u32(n, seed=40)
+    vals0 = W.index_payload(n)
+    tk, tv = to_dev(keys0), to_dev(vals0)
+    plan = pdq.Plan(tk, None, tv)
+    for rep in range(3):
+        keys = W.uniform_u32(n, seed=41 + rep)
+        tk.copy_(to_dev(keys))
+        tv.copy_(to_dev(vals0))
+        plan.launch()
+        torch.cuda.synchronize()
+        out, vo = tk.cpu().numpy(), tv.cpu().numpy()
+        assert np.array_equal(out, oracle.sort(keys)[0])
+        check_pairs(keys, out, vo)
+        eager, _, _ = gpu_sort(keys)
+        assert np.array_equal(eager, out)
+        _ = torch.ones(1000, device="cuda:0").sum().item()
+    plan.destroy()
 
 
 # ------------------------------------------------------------------ full size, sampled
