@@ -304,8 +304,8 @@ void pdq_plan_destroy(pdq_plan* plan);
  * A call whose
  * pdq_workspace_bytes(n, 1, key_type, d_vals != NULL, opt with PDQ_HOST_LOOP added) exceeds
  * PDQ_NOALLOC_SCRATCH_BYTES returns PDQ_ERR_SCRATCH before touching the GPU
- * (without PDQ_LEARNED: up to 15,662,528 uint32 keys, 8,079,232 uint32 keys
- * with payloads, 8,079,264 uint64 keys, 5,443,392 uint64 keys with
+ * (without PDQ_LEARNED: up to 15,637,440 uint32 keys, 8,072,320 uint32 keys
+ * with payloads, 8,072,352 uint64 keys, 5,440,704 uint64 keys with
  * payloads). Unlike pdq_sort, it runs the host-driven pass loop with one host
  * synchronisation per partition pass (its smaller workspace fits more keys
  * into the array, and it allocates no pinned host memory). PDQ_PROFILE, PDQ_BATCHED and PDQ_AUTOTUNE return

@@ -29,6 +29,21 @@ __device__ __forceinline__ void push_item(const Ctx& c, Item* list, uint32_t* ct
   }
 }
 
+// Append a range to the copy list, as one item per chunk of kCopyChunk keys
+// (of swapped pairs, for an in-place reversal). Every lane calls.
+__device__ __forceinline__ void push_copy(const Ctx& c, bool want, uint64_t b, uint64_t e, uint32_t buf,
+                                          uint32_t reverse) {
+  const uint64_t span = want ? ((reverse && buf == 0) ? (e - b) / 2 : e - b) : 0;
+  const uint32_t nch = want ? static_cast<uint32_t>(span > kCopyChunk ? (span + kCopyChunk - 1) / kCopyChunk : 1)
+                            : 0u;
+  const uint32_t first = wave_reserve_n(&c.icnt[kItemCopy], nch);
+  for (uint32_t k = 0; k < nch; ++k) {
+    const uint32_t slot = first + k;
+    if (slot < c.max_items) c.copy[slot] = Item{b, e, buf, reverse | (k << 1)};
+    else atomicOr(&c.ctr->errors, kErrCapacity);
+  }
+}
+
 // Append a base-case segment to the list of its size class.
 __device__ __forceinline__ void push_base(const Ctx& c, bool want, uint64_t b, uint64_t e, uint32_t buf) {
   const int cls = want ? base_class(e - b) : -1;
@@ -126,7 +141,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_bucket_init(Ctx c, const uint64
   uint32_t budget = 0;
   if (size >= 2) budget = c.force_budget >= 0 ? static_cast<uint32_t>(c.force_budget) : floor_log2_u64(size);
   const bool big = size > c.base_max;
-  push_item(c, c.copy, &c.icnt[kItemCopy], eq, b, e, 1u, 0u);
+  push_copy(c, eq, b, e, 1u, 0u);
   push_seg(c, 0, range && big && budget > 0, b, e, budget, kSegLeftmost);
   const bool to_base = range && !big;
   const bool to_heap = range && big && budget == 0;
@@ -234,10 +249,9 @@ __device__ __forceinline__ void bookkeep_one(const Ctx& c, int parity, uint32_t 
   }
   // already ordered: copy (reversed when descending) into the user buffer
   const bool ordered = asc_sorted || desc_sorted;
-  push_item(c, c.copy, &c.icnt[kItemCopy], ordered && !(src == 0 && asc_sorted), s.begin, s.end, src,
-            desc_sorted ? 1u : 0u);
+  push_copy(c, ordered && !(src == 0 && asc_sorted), s.begin, s.end, src, desc_sorted ? 1u : 0u);
   // partition_left: the left side equals the pivot and is final
-  push_item(c, c.copy, &c.icnt[kItemCopy], split && is_left && L > 0 && dst != 0, s.begin, s.begin + L, dst, 0u);
+  push_copy(c, split && is_left && L > 0 && dst != 0, s.begin, s.begin + L, dst, 0u);
 
   const uint32_t cbudget = s.budget - (bad ? 1u : 0u);
   const uint32_t cflag_fresh = bad ? kSegFresh : 0u;
@@ -299,8 +313,13 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
     const uint64_t len = it.end - it.begin;
     const T* in = static_cast<const T*>(c.keys[it.buf]);
     const uint32_t* inv = c.vals[it.buf];
-    if (it.reverse && it.buf == 0) {
-      for (uint64_t j = start; j < len / 2; j += stride) {
+    const bool rev = (it.reverse & 1u) != 0;
+    // this item's chunk of the range (of the swapped pairs, in place)
+    const uint64_t c0 = static_cast<uint64_t>(it.reverse >> 1) * kCopyChunk;
+    const uint64_t span = rev && it.buf == 0 ? len / 2 : len;
+    const uint64_t c1 = c0 + kCopyChunk < span ? c0 + kCopyChunk : span;
+    if (rev && it.buf == 0) {
+      for (uint64_t j = c0 + start; j < c1; j += stride) {
         const uint64_t a = it.begin + j, z = it.end - 1 - j;
         T ka = out[a], kz = out[z];
         out[a] = kz;
@@ -311,13 +330,13 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
           outv[z] = va;
         }
       }
-    } else if (it.reverse) {
-      for (uint64_t j = start; j < len; j += stride) {
+    } else if (rev) {
+      for (uint64_t j = c0 + start; j < c1; j += stride) {
         out[it.begin + j] = in[it.end - 1 - j];
         if (c.has_vals) outv[it.begin + j] = inv[it.end - 1 - j];
       }
     } else {
-      for (uint64_t j = start; j < len; j += stride) {
+      for (uint64_t j = c0 + start; j < c1; j += stride) {
         out[it.begin + j] = in[it.begin + j];
         if (c.has_vals) outv[it.begin + j] = inv[it.begin + j];
       }
@@ -399,7 +418,8 @@ struct CopyL {
   static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
     const uint32_t g = c.device_counts && nitems > 2048 ? 2048 : nitems;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy<K>, dim3(g, c.device_counts ? 8 : 64), dim3(kCtlThreads), 0, s, c, nitems);
+    // a row of 8 workgroups per item: items hold at most kCopyChunk keys
+    hipLaunchKernelGGL(k_copy<K>, dim3(g, 8), dim3(kCtlThreads), 0, s, c, nitems);
     return hipGetLastError();
   }
 };

@@ -210,7 +210,9 @@ Layout make_layout(size_t n, size_t nseg, uint32_t kt, bool vals, bool batched) 
     // the disjoint live segments of every pass
     items = nseg + 2ull * kMaxBatchPasses * (n / (batch_base_max(kt, vals) + 1) + 2);
   }
-  L.max_items = static_cast<uint32_t>(items + 64);
+  // copy items cover at most kCopyChunk keys each: a retired range of r keys
+  // takes up to r / kCopyChunk more slots, and retired ranges are disjoint
+  L.max_items = static_cast<uint32_t>(items + n / kCopyChunk + 64);
   // the counter block comes first, so pdq_check finds it from d_ws alone
   L.ctr = take(sizeof(Counters));
   L.scratch_keys = take(n * key_bytes(kt));

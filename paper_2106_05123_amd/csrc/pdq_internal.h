@@ -73,8 +73,14 @@ struct Item {
   uint64_t begin;
   uint64_t end;
   uint32_t buf;     // 0 user buffer, 1 scratch buffer
-  uint32_t reverse; // copy items: write the range in reverse order
+  uint32_t reverse; // copy items: bit 0 = write the range in reverse order; bits 1.. = the chunk
+                    // of kCopyChunk keys this item covers (of the swapped pairs, for an
+                    // in-place reversal)
 };
+
+// Keys per copy item: a large retired range is filed as several items, so
+// that many workgroups copy it.
+constexpr uint64_t kCopyChunk = 1ull << 16;
 
 // Item counts of one set of item lists: the base-case classes, heapsort,
 // copies (in this order, contiguous).

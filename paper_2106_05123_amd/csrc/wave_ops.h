@@ -55,6 +55,17 @@ __device__ __forceinline__ uint64_t wave_reserve_packed(unsigned long long* ctr,
   return base + (incl - v);
 }
 
+// Every lane must call this. Lane i gets n_i consecutive slots of a 32-bit
+// counter (lanes in order); returns the first.
+__device__ __forceinline__ uint32_t wave_reserve_n(uint32_t* ctr, uint32_t n) {
+  const uint64_t incl = wave_incl_scan_u64(n);
+  const uint64_t total = __shfl(incl, 63, 64);
+  uint32_t base = 0;
+  if (lane_id() == 63 && total != 0) base = atomicAdd(ctr, static_cast<uint32_t>(total));
+  base = __shfl(base, 63, 64);
+  return base + static_cast<uint32_t>(incl - n);
+}
+
 // Every lane must call this. Wanting lanes get consecutive slots of a
 // 32-bit counter; returns the slot index.
 __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, bool want) {
