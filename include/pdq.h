@@ -13,10 +13,13 @@
  *     Lemmas 1-4, Theorem 1);
  *   - branchless block classification (Section 5.3) as wave ballots and
  *     LDS prefix sums with a decoupled look-back scatter;
- *   - bad-partition budget with heapsort fallback (Section 4.1);
+ *   - bad-partition budget with an O(n log n) fallback sort (Section 4.1;
+ *     the paper heapsorts in place, here one workgroup merge-sorts the
+ *     segment, lanes sharing every merge);
  *   - detection of already ordered segments (Section 5.2);
- *   - an LDS-resident base case for segments of at most 4096 keys
- *     (Section 5.1's small-case sort, as a sorting network).
+ *   - an LDS-resident base case for segments of at most 4096 keys, 16384
+ *     with device-counted passes (Section 5.1's small-case sort, as a
+ *     sorting network and an LDS merge sort).
  * With PDQ_LEARNED a multiway first pass runs before the partition passes
  * (the multiway partitioning Section 2 mentions as the road not taken): a
  * small MLP fitted to the CDF of a key sample proposes up to 255
@@ -183,7 +186,8 @@ typedef struct pdq_stats {
   uint64_t partitions_right;
   uint64_t partitions_left;
   uint64_t bad_partitions;
-  uint64_t heapsort_segments;
+  uint64_t heapsort_segments;     /* segments out of bad-partition budget, given to the fallback
+                                     sort (Section 4.1's heapsort; a workgroup merge sort here) */
   uint64_t heapsort_elements;
   uint64_t base_segments;         /* segments sorted by the LDS base case */
   uint64_t base_elements;

@@ -12,7 +12,8 @@
 //             kernels (Sections 3, 4.1, 4.2, 5.2) -- into the other buffer;
 //             its children are sorted at once when they fit in LDS (while
 //             they are still in this XCD's cache) or queued otherwise.
-//             A segment out of budget is heapsorted (Section 4.1).
+//             A segment out of budget is filed for the fallback sort
+//             (Section 4.1), which runs after the launch.
 //
 // Inside the persistent launch a segment written by one workgroup may be read
 // by a workgroup on another XCD, whose L2 is not coherent with the writer's.
@@ -429,16 +430,15 @@ __global__ __launch_bounds__(NT) void k_batch(Ctx c, BatchArgs bq) {
     if (size <= static_cast<uint64_t>(B::kLdsMax)) {
       sort_segment<K, PAIRS, NT>(c, b, e, it.buf, sh);
     } else if (it.budget == 0) {
-      // out of budget: heapsort in the user buffer (one lane)
-      copy_out<K, PAIRS, NT>(c, b, e, it.buf, false);
-      __threadfence_block();
-      __syncthreads();
-      if (tid == 0) heapsort_range<K>(static_cast<T*>(c.keys[0]) + b, PAIRS ? c.vals[0] + b : nullptr, size);
+      // out of budget: filed for the fallback sort (Section 4.1), which
+      // runs after this launch with a whole workgroup per segment
       if (tid == 0) {
+        const uint32_t slot = atomicAdd(&c.icnt[kItemHeap], 1u);
+        if (slot < c.max_items) c.heap[slot] = Item{b, e, it.buf, 0u};
+        else atomicOr(&c.ctr->errors, kErrCapacity);
         atomicAdd(reinterpret_cast<unsigned long long*>(&c.ctr->heap_segments), 1ull);
         atomicAdd(reinterpret_cast<unsigned long long*>(&c.ctr->heap_elements), static_cast<unsigned long long>(size));
       }
-      __syncthreads();
     } else {
       if (tid == 0) {
         // the candidates (written by the partition that made this segment)

@@ -1,6 +1,7 @@
 // Per-pass control kernels of the partition sort: initial segment lists,
 // pivot choice, tile map, segment bookkeeping, and the finishing copies and
-// heapsort fallback.
+// the fallback sort of segments out of budget.
+#include "bitonic.h"
 #include "learn_internal.h"
 #include "pdq_internal.h"
 #include "pivot.h"
@@ -344,31 +345,123 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
   }
 }
 
-// Heapsort fallback (Section 4.1: a segment that used up its bad-partition
-// budget), one workgroup per segment: the workgroup moves the segment into
-// the user buffer, then one lane sorts it there (heapsort_range, pivot.h).
-template <class K>
-__global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c, uint32_t nitems) {
+// Fallback sort of Section 4.1, for a segment that used up its bad-partition
+// budget. The paper heapsorts the segment in place: O(n log n) whatever the
+// input, but one element at a time. Here one workgroup merge-sorts it, also
+// O(n log n) whatever the input, with every lane busy: chunks of kFbChunk
+// keys are sorted in LDS (the base case's merge sort, each key paired with
+// its index so that its payload follows) into the other buffer, then merge
+// passes alternate between the two buffers. In a pass, every lane finds
+// where its kFbRun outputs of a merged pair of runs start (a merge-path
+// binary search) and merges them one by one, ties from the left run. The
+// segment's range of the other buffer is free (its keys left it), and the
+// result ends in the user buffer.
+constexpr int kFbE = 8;
+constexpr int kFbChunk = kFbE * kCtlThreads;
+constexpr uint64_t kFbRun = 8;
+
+template <class K, bool PAIRS>
+__device__ void fallback_sort(const Ctx& c, const Item& it, unsigned char* sh) {
   using T = typename K::T;
+  using S = net::Slot<K, PAIRS>;
+  using V = typename S::V;
+  const int tid = static_cast<int>(threadIdx.x);
+  const uint64_t len = it.end - it.begin;
+  uint32_t src = it.buf;
+  // sorted chunks, into the other buffer
+  {
+    const T* kin = static_cast<const T*>(c.keys[src]) + it.begin;
+    const uint32_t* vin = PAIRS ? c.vals[src] + it.begin : nullptr;
+    T* kout = static_cast<T*>(c.keys[src ^ 1u]) + it.begin;
+    uint32_t* vout = PAIRS ? c.vals[src ^ 1u] + it.begin : nullptr;
+    for (uint64_t cb = 0; cb < len; cb += kFbChunk) {
+      const int clen = static_cast<int>(len - cb < static_cast<uint64_t>(kFbChunk) ? len - cb : kFbChunk);
+      V x[kFbE];
+#pragma unroll
+      for (int r = 0; r < kFbE; ++r) {
+        const int j = tid * kFbE + r;
+        x[r] = j < clen ? S::make(kin[cb + j], static_cast<uint32_t>(j)) : S::pad();
+      }
+      net::merge_sort<S, kFbE, kCtlThreads>(x, sh, tid);
+#pragma unroll
+      for (int r = 0; r < kFbE; ++r) {
+        const int j = tid * kFbE + r;
+        if (j < clen) {
+          kout[cb + j] = S::key(x[r]);
+          if constexpr (PAIRS) vout[cb + j] = vin[cb + S::idx(x[r])];
+        }
+      }
+    }
+    src ^= 1u;
+    __threadfence_block();
+    __syncthreads();
+  }
+  // merge passes
+  for (uint64_t w = kFbChunk; w < len; w *= 2) {
+    const T* sk = static_cast<const T*>(c.keys[src]) + it.begin;
+    const uint32_t* sv = PAIRS ? c.vals[src] + it.begin : nullptr;
+    T* dk = static_cast<T*>(c.keys[src ^ 1u]) + it.begin;
+    uint32_t* dv = PAIRS ? c.vals[src ^ 1u] + it.begin : nullptr;
+    for (uint64_t lo = 0; lo < len; lo += 2 * w) {
+      const uint64_t mid = lo + w < len ? lo + w : len;
+      const uint64_t hi = lo + 2 * w < len ? lo + 2 * w : len;
+      const uint64_t na = mid - lo, nb = hi - mid;
+      for (uint64_t o = static_cast<uint64_t>(tid) * kFbRun; o < na + nb;
+           o += static_cast<uint64_t>(kCtlThreads) * kFbRun) {
+        // i = keys of the left run among the first o outputs: A[i'] is among
+        // them exactly when A[i'] <= B[o - i' - 1]
+        uint64_t ilo = o > nb ? o - nb : 0, ihi = o < na ? o : na;
+        while (ilo < ihi) {
+          const uint64_t im = (ilo + ihi) / 2;
+          if (!(K::ord(sk[mid + (o - im - 1)]) < K::ord(sk[lo + im]))) ilo = im + 1;
+          else ihi = im;
+        }
+        uint64_t i = ilo, j = o - ilo;
+        const uint64_t oend = o + kFbRun < na + nb ? o + kFbRun : na + nb;
+        for (uint64_t q = o; q < oend; ++q) {
+          const bool take_a = j >= nb || (i < na && !(K::ord(sk[mid + j]) < K::ord(sk[lo + i])));
+          const uint64_t from = take_a ? lo + i : mid + j;
+          dk[lo + q] = sk[from];
+          if constexpr (PAIRS) dv[lo + q] = sv[from];
+          if (take_a) ++i;
+          else ++j;
+        }
+      }
+    }
+    src ^= 1u;
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (src != 0) {
+    const T* sk = static_cast<const T*>(c.keys[src]) + it.begin;
+    T* dk = static_cast<T*>(c.keys[0]) + it.begin;
+    for (uint64_t j = static_cast<uint64_t>(tid); j < len; j += kCtlThreads) {
+      dk[j] = sk[j];
+      if constexpr (PAIRS) c.vals[0][it.begin + j] = c.vals[src][it.begin + j];
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+}
+
+// One workgroup per fallback item (Section 4.1).
+template <class K, bool PAIRS>
+__global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c, uint32_t nitems) {
+  using S = net::Slot<K, PAIRS>;
+  __shared__ __align__(16) unsigned char sh[net::lds_plane<kFbChunk, kFbE>() * S::kLdsBytes];
   uint32_t count = c.device_counts ? c.icnt[kItemHeap] : nitems;
   if (count > c.max_items) count = c.max_items;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const Item it = c.heap[item];
-    const uint64_t len = it.end - it.begin;
-    T* a = static_cast<T*>(c.keys[0]) + it.begin;
-    uint32_t* v = c.has_vals ? c.vals[0] + it.begin : nullptr;
-    if (it.buf != 0) {
-      const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
-      const uint32_t* inv = c.has_vals ? c.vals[it.buf] + it.begin : nullptr;
-      for (uint64_t j = threadIdx.x; j < len; j += blockDim.x) {
-        a[j] = in[j];
-        if (v) v[j] = inv[j];
+    if (it.end - it.begin < 2) {
+      // one key: only its place in the user buffer
+      if (threadIdx.x == 0 && it.end > it.begin && it.buf != 0) {
+        static_cast<typename K::T*>(c.keys[0])[it.begin] = static_cast<const typename K::T*>(c.keys[it.buf])[it.begin];
+        if constexpr (PAIRS) c.vals[0][it.begin] = c.vals[it.buf][it.begin];
       }
-      __threadfence_block();
-      __syncthreads();
+      continue;
     }
-    if (threadIdx.x == 0) heapsort_range<K>(a, v, len);
-    __syncthreads();
+    fallback_sort<K, PAIRS>(c, it, sh);
   }
 }
 
@@ -428,7 +521,8 @@ struct HeapL {
   static hipError_t run(const Ctx& c, uint32_t nitems, hipStream_t s) {
     const uint32_t g = c.device_counts && nitems > 2048 ? 2048 : nitems;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_heap<K>, dim3(g), dim3(kCtlThreads), 0, s, c, nitems);
+    if (c.has_vals) hipLaunchKernelGGL((k_heap<K, true>), dim3(g), dim3(kCtlThreads), 0, s, c, nitems);
+    else hipLaunchKernelGGL((k_heap<K, false>), dim3(g), dim3(kCtlThreads), 0, s, c, nitems);
     return hipGetLastError();
   }
 };

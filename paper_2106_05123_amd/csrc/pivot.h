@@ -1,5 +1,5 @@
-// Pivot choice and heapsort fallback of one segment, shared by the
-// pass-based partition sort and the batched segmented sort.
+// Pivot choice of one segment, shared by the pass-based partition sort and
+// the persistent tail of the device-counted passes.
 #pragma once
 
 #include "pdq_internal.h"
@@ -88,43 +88,6 @@ __device__ __forceinline__ PivotChoice<K> choose_pivot(const typename K::T* keys
     if (!(static_cast<uint64_t>(K::ord(pred)) < mo[sel])) pc.mode = kModeLeft;
   }
   return pc;
-}
-
-// Williams' heapsort of a[0..len) (and payloads v, if any) by one lane.
-template <class K>
-__device__ void sift_down(typename K::T* a, uint32_t* v, uint64_t root, uint64_t n) {
-  for (;;) {
-    uint64_t child = 2 * root + 1;
-    if (child >= n) return;
-    if (child + 1 < n && K::ord(a[child]) < K::ord(a[child + 1])) ++child;
-    if (!(K::ord(a[root]) < K::ord(a[child]))) return;
-    typename K::T t = a[root];
-    a[root] = a[child];
-    a[child] = t;
-    if (v) {
-      uint32_t tv = v[root];
-      v[root] = v[child];
-      v[child] = tv;
-    }
-    root = child;
-  }
-}
-
-template <class K>
-__device__ void heapsort_range(typename K::T* a, uint32_t* v, uint64_t len) {
-  if (len < 2) return;
-  for (uint64_t r = len / 2; r-- > 0;) sift_down<K>(a, v, r, len);
-  for (uint64_t end = len - 1; end > 0; --end) {
-    typename K::T t = a[0];
-    a[0] = a[end];
-    a[end] = t;
-    if (v) {
-      uint32_t tv = v[0];
-      v[0] = v[end];
-      v[end] = tv;
-    }
-    sift_down<K>(a, v, 0, end);
-  }
 }
 
 }  // namespace pdq

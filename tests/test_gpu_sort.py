@@ -370,12 +370,29 @@ def test_segmented_validate_rejects_bad_offsets():
 # a budget of 0 sends every segment above the LDS base case to heapsort: above
 # 4096 keys in the host-driven loop, above 16384 in the device-counted passes
 @pytest.mark.parametrize("n,host_loop", [(4097, True), (5000, True), (20000, True), (16385, False),
-                                         (20000, False), (100003, False)])
-def test_forced_heapsort(n, host_loop):
-    a = W.uniform_u32(n, seed=n)
+                                         (20000, False), (100003, False), ((1 << 21) + 3, False)])
+@pytest.mark.parametrize("kt", ["u32", "f64"])
+def test_forced_heapsort(n, host_loop, kt):
+    """The fallback sort (a workgroup merge sort: LDS-sorted chunks of 2048
+    keys, then merge passes between the two buffers) on a whole input whose
+    budget is 0: one item, keys bit-exact, payloads travel with them."""
+    a = W.random_keys(kt, n, seed=n)
     v = W.index_payload(n)
     out, vo, st = gpu_sort(a, v, force_budget=0, host_loop=host_loop)
     assert st["heapsort_segments"] == 1 and st["heapsort_elements"] == n
+    assert np.array_equal(as_bytes(out), as_bytes(oracle.sort(a)[0]))
+    check_pairs(a, out, vo)
+
+
+def test_fallback_sort_of_segments_out_of_budget_in_the_tail():
+    """With no device-counted pass, the persistent tail partitions the
+    input; its planted bad first partition uses up a budget of 1, so the
+    big child is filed for the fallback sort, which runs after the tail."""
+    n = (1 << 20) + 99
+    a = planted_bad_first_pivot(n, seed=7)
+    v = W.index_payload(n)
+    out, vo, st = gpu_sort(a, v, force_budget=1, batch_passes=0)
+    assert st["heapsort_segments"] >= 1 and st["heapsort_elements"] > n // 2
     assert np.array_equal(out, oracle.sort(a)[0])
     check_pairs(a, out, vo)
 
