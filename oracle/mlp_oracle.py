@@ -53,8 +53,10 @@ float32), so that it can be read against this summary:
              key == s[b - 1], range bin 2b otherwise (2u + 1 bins)
   budget     staged: a fit of 32 steps first; it is kept when its chosen
              splitters put at most 1.3 m / 256 sample keys into one range bin
-             (in integers: judge * 2560 <= 13 m), else the fit is redone from
-             the same initial parameters with 128 steps
+             (in integers: judge * 2560 <= 13 m), and also when they put more
+             than 4 m / 256 there (judge * 64 > m: longer training does not
+             rescue such a fit, and the judge will reject it); otherwise the
+             fit is redone from the same initial parameters with 128 steps
 
 Where a float32 result decides an integer (the splitters), the float32
 inference is the C routine oracle_mlp_infer_f32 (pdq_oracle.cpp), which
@@ -427,12 +429,19 @@ def early_accept(judge: int, m: int) -> bool:
     return judge * 2560 <= 13 * m
 
 
+def hopeless(judge: int, m: int) -> bool:
+    """Whether a short fit is too uneven for longer training to rescue: its
+    fullest range bin holds more than 4 m / 256 sample keys."""
+    return judge * 64 > m
+
+
 def fit_staged(keys: np.ndarray, seed: int = 0, m: int = 1 << 16, batch: int = 1024, residual: bool = True):
-    """The default budget: a 32-step fit, kept if early_accept holds for its
-    chosen splitters, else a 128-step fit from the same initial parameters.
-    Adds `stage` (1 or 2) to fit's dict."""
+    """The default budget: a 32-step fit, kept if early_accept or hopeless
+    holds for its chosen splitters, else a 128-step fit from the same initial
+    parameters. Adds `stage` (1 or 2) to fit's dict."""
     f = fit(keys, seed, m, STAGE1_STEPS, batch, residual)
-    if early_accept(f["estimates"][f["choice"]], m):
+    judge = f["estimates"][f["choice"]]
+    if early_accept(judge, m) or hopeless(judge, m):
         f["stage"] = 1
         return f
     f = fit(keys, seed, m, STAGE2_STEPS, batch, residual)

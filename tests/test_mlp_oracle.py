@@ -366,6 +366,8 @@ def test_early_accept_threshold():
     assert M.early_accept(332, 1 << 16) and not M.early_accept(333, 1 << 16)
     assert M.early_accept(13, 2560) and not M.early_accept(14, 2560)
     assert M.early_accept(0, 1)
+    # retraining is skipped above 4 m / 256: 1024 for m = 65536
+    assert not M.hopeless(1024, 1 << 16) and M.hopeless(1025, 1 << 16)
 
 
 def test_staged_budget_keeps_the_short_fit_or_redoes_the_long_one():
@@ -387,3 +389,10 @@ def test_staged_budget_keeps_the_short_fit_or_redoes_the_long_one():
     assert not M.early_accept(short["estimates"][short["choice"]], 1 << 16)
     assert np.array_equal(f["splitters"], long["splitters"])
     assert np.array_equal(f["losses"], long["losses"])
+    # the paper's dup8 keys: the short fit is far over the limit (about 4.9
+    # times the fair share), so it is kept without retraining
+    keys = W.paper_pattern_u64("dup8", n, seed=0)
+    f = M.fit_staged(keys, seed=0)
+    short = M.fit(keys, seed=0, steps=M.STAGE1_STEPS)
+    assert f["stage"] == 1 and M.hopeless(short["estimates"][short["choice"]], 1 << 16)
+    assert np.array_equal(f["splitters"], short["splitters"])
