@@ -153,8 +153,9 @@ typedef struct pdq_options {
                                     more than limit * n / 256 keys; 0 = 2.0; < 0 = always fall back */
   uint32_t learn_steps;  /* PDQ_LEARNED: Adam steps (at most 65536); 0 = the staged budget: a
                             32-step fit, kept when its chosen splitters put at most 1.3 m/256 of
-                            the m sample keys into one range bin, else a 128-step fit from the
-                            same initial parameters (one synchronisation between the two) */
+                            the m sample keys into one range bin (or more than 4 m/256: too
+                            uneven to rescue, and rejected), else a 128-step fit from the same
+                            initial parameters (one synchronisation between the two) */
   uint32_t learn_batch;  /* PDQ_LEARNED: minibatch, 0 = 1024; a multiple of learn_grid, at most 65536 */
   uint32_t learn_grid;   /* PDQ_LEARNED: cooperating trainer workgroups, 0 = 16 (1 ... 64) */
   uint32_t batch_shape;  /* PDQ_BATCHED: 0 = the tuned (or default) shape; 1 ... 4 = shape

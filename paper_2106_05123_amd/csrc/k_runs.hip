@@ -66,14 +66,18 @@ __global__ __launch_bounds__(kScanNT) void k_run_scan(const typename K::T* __res
     // the successor of a key is the next lane's key; the last lane of a wave
     // loads it (it belongs to the next wave or the next row)
     const bool last_lane = lane_id() == 63;
+    bool asc = false;
 #pragma unroll
     for (int r = 0; r < kScanRows; ++r) {
       const uint64_t i = ch * kScanChunk + static_cast<uint64_t>(r) * kScanNT + tid;
       T nxt = __shfl_down(k[r], 1, 64);
       if (last_lane) nxt = i + 1 < n ? keys[i + 1] : T(0);
       d[r] = i + 1 < n && K::ord(nxt) < K::ord(k[r]);
+      asc = asc || (i + 1 < n && K::ord(k[r]) < K::ord(nxt));
       mine += d[r] ? 1u : 0u;
     }
+    // some adjacent pair ascends (the learned pass needs both directions)
+    if (__ballot(asc) != 0 && lane_id() == 0) rb.count[1] = 1u;
     const uint64_t wsum = wave_sum_u64(mine);
     if (lane_id() == 0 && wsum) atomicAdd(&s_local, static_cast<uint32_t>(wsum));
     __syncthreads();
@@ -129,6 +133,7 @@ __global__ __launch_bounds__(kPlanNT) void k_run_plan(uint64_t n, RunBufs rb) {
   const uint32_t count = __hip_atomic_load(rb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   RunPlan plan = {};
   plan.descents = count;
+  plan.ascent = rb.count[1];
   if (count > kRunMaxDescents) {
     if (tid == 0) *rb.plan = plan;  // state 0: the partition passes sort it
     return;
@@ -333,7 +338,10 @@ __global__ __launch_bounds__(kMergeNT) void k_merge(const typename K::T* __restr
 }
 
 __global__ void k_run_reset(RunBufs rb) {
-  if (threadIdx.x == 0) *rb.count = 0;
+  if (threadIdx.x == 0) {
+    rb.count[0] = 0;
+    rb.count[1] = 0;
+  }
 }
 
 template <class K>

@@ -170,7 +170,7 @@ struct RunsLayout {
 RunsLayout runs_layout(size_t n) {
   RunsLayout r;
   Bump b;
-  r.count = b.take(4);
+  r.count = b.take(8);
   r.pos = b.take(4ull * kRunMaxDescents);
   r.plan = b.take(sizeof(RunPlan));
   r.shorts = b.take(sizeof(RunSpan) * (kRunMaxDescents + 1ull));
@@ -511,14 +511,16 @@ int run_fit_model(const Opts& o, uint32_t steps, const FitBufs& f, hipStream_t s
 }
 
 // Whether a short fit is kept: its fullest range bin holds at most
-// 1.3 m / 256 sample keys (judge * 2560 <= 13 m).
+// 1.3 m / 256 sample keys (judge * 2560 <= 13 m), or more than 4 m / 256
+// (judge * 64 > m), which longer training does not bring to the limit.
 bool early_accept(uint64_t judge, uint64_t m) { return judge * 2560ull <= 13ull * m; }
+bool hopeless(uint64_t judge, uint64_t m) { return judge * 64ull > m; }
 
 // The whole fit. With the staged budget (learn_steps 0) a kStage1Steps fit
 // is judged first (one synchronisation to read its sample judge) and kept
-// when early_accept holds; otherwise the model is trained again from the
-// same initial parameters for o.steps steps. *steps_run receives the steps
-// of the kept fit.
+// when early_accept or hopeless holds; otherwise the model is trained again
+// from the same initial parameters for o.steps steps. *steps_run receives
+// the steps of the kept fit.
 int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s,
             uint64_t go_limit = ~0ull, uint32_t* steps_run = nullptr) {
   int rc = run_fit_sample(keys, n, kt, o, f, s);
@@ -531,7 +533,7 @@ int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitB
     HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const uint64_t choice = info[3] < kCandidates ? info[3] : 0;
-    if (early_accept(info[4 + choice], kLearnSample)) {
+    if (early_accept(info[4 + choice], kLearnSample) || hopeless(info[4 + choice], kLearnSample)) {
       if (steps_run) *steps_run = kStage1Steps;
       return PDQ_OK;
     }
@@ -586,7 +588,10 @@ struct LearnedResult {
 // Fit, histogram, judge and (if the judge agrees) scatter into bins.
 // Returns with res.state 1 when the bins were set up as the first lists,
 // 2 when the caller must start the plain path.
-int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, LearnedResult& res, hipStream_t s) {
+// `unordered`: the run scan has already seen both a descending and an
+// ascending adjacent pair, so the order scan is skipped.
+int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, LearnedResult& res, hipStream_t s,
+                bool unordered = false) {
   const uint32_t kt = c.key_type;
   const uint64_t n = c.n;
   const uint32_t kb = key_bytes(kt);
@@ -595,7 +600,7 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   b.errors = &c.ctr->errors;
   EventPair e_fit, e_hist, e_scat;
   if (prof && !(e_fit.make() && e_hist.make() && e_scat.make())) return PDQ_ERR_HIP;
-  {
+  if (!unordered) {
     // an input that is already non-decreasing or non-increasing is retired
     // by the plain path's first pass: find out before the fit is paid for
     uint32_t order_bits = 0;
@@ -1302,9 +1307,11 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
+  bool unordered = false;  // both a descending and an ascending pair seen
   if (!offsets && uses_runs(n, 1)) {
     RunPlan plan = {};
     rc = run_near_sorted(c, L, base, &plan, s);
+    unordered = plan.descents > 0 && plan.ascent != 0;
     if (rc != PDQ_OK) return rc;
     if (plan.state != kRunUnsorted) {
       if (st) {
@@ -1328,7 +1335,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   uint32_t src = 0;
   if (learned) {
     c.single = 0;  // the first partition pass sees the bins, not the whole range
-    rc = run_learned(c, o, L, base, prof, lres, s);
+    rc = run_learned(c, o, L, base, prof, lres, s, unordered);
     if (rc != PDQ_OK) return rc;
     if (lres.state == 1) src = 1;
     else if (!o.tile && !dev_passes) c.tile = auto_tile(n, n);  // judged and fell back: one segment [0, n)

@@ -31,6 +31,8 @@ struct RunPlan {
   uint64_t outliers;  // keys in short runs
   uint64_t a0, a1;    // the (first) long run [a0, a1)
   uint64_t b0, b1;    // the second long run (kRunTwoRuns)
+  uint32_t ascent;    // 1: the scanned part has an ascending adjacent pair
+  uint32_t pad_;
 };
 
 // A short run [start, start + len) gathered to outlier slot dest.
@@ -41,7 +43,7 @@ struct RunSpan {
 };
 
 struct RunBufs {
-  uint32_t* count;    // descents counted
+  uint32_t* count;    // [0] descents counted, [1] an ascending pair was seen
   uint32_t* pos;      // kRunMaxDescents logged positions
   RunPlan* plan;
   RunSpan* shorts;    // kRunMaxDescents + 1 entries

@@ -318,18 +318,19 @@ def test_trained_network_gains_over_untrained(dist):
     assert st_l["passes"] < st_p["passes"]
 
 
-@pytest.mark.parametrize("dist", ["uniform_u32", "lognormal_u64", "zipf_u64"])
+@pytest.mark.parametrize("dist", ["uniform_u32", "lognormal_u64", "zipf_u64", "gmm_u64"])
 def test_staged_budget_follows_the_rule(dist):
     """The default budget: the 32-step fit is kept exactly when its sample
-    judge passes the early-accept rule (checked with the oracle's rule on the
-    GPU's own 32-step judge), else the fit is the 128-step fit; parameters
-    and splitters are bitwise those of the corresponding single-budget fit,
-    and the sort reports the steps it kept."""
+    judge passes the early-accept rule or is hopeless (checked with the
+    oracle's rules on the GPU's own 32-step judge), else the fit is the
+    128-step fit; parameters and splitters are bitwise those of the
+    corresponding single-budget fit, and the sort reports the steps it kept."""
     n = 1 << 22
     keys = DISTS[dist](n, 0)
     short = pdq.learned_fit(dev(keys), seed=0, learn_steps=M.STAGE1_STEPS)
     info = host(short["info"])
-    keep = M.early_accept(int(info[4 + int(info[3])]), pdq.LEARN_SAMPLE)
+    judge = int(info[4 + int(info[3])])
+    keep = M.early_accept(judge, pdq.LEARN_SAMPLE) or M.hopeless(judge, pdq.LEARN_SAMPLE)
     staged = pdq.learned_fit(dev(keys), seed=0)
     want = short if keep else pdq.learned_fit(dev(keys), seed=0, learn_steps=M.STAGE2_STEPS)
     assert np.array_equal(host(staged["splitters"]), host(want["splitters"]))
@@ -341,6 +342,9 @@ def test_staged_budget_follows_the_rule(dist):
         assert keep  # uniform keys are split evenly after the short fit
     if dist == "lognormal_u64":
         assert not keep
+    if dist == "gmm_u64":
+        # far over the limit after 32 steps: kept as it is, and judged failed
+        assert keep and st["learned"] == 2
 
 
 @pytest.mark.parametrize("dist", ["uniform_u32", "lognormal_u64", "zipf_u64", "gmm_u64"])
