@@ -14,8 +14,8 @@
  *   - branchless block classification (Section 5.3) as wave ballots and
  *     LDS prefix sums with a decoupled look-back scatter;
  *   - bad-partition budget with an O(n log n) fallback sort (Section 4.1;
- *     the paper heapsorts in place, here one workgroup merge-sorts the
- *     segment, lanes sharing every merge);
+ *     by default one workgroup merge-sorts the segment, lanes sharing every
+ *     merge; PDQ_HEAPSORT selects the paper's in-place heapsort);
  *   - detection of already ordered segments (Section 5.2);
  *   - an LDS-resident base case for segments of at most 4096 keys, 16384
  *     with device-counted passes (Section 5.1's small-case sort, as a
@@ -132,6 +132,9 @@ enum pdq_flags {
   PDQ_HOST_LOOP = 1u << 8, /* pdq_sort / pdq_sort_pairs: the host-driven pass loop (the host reads
                              each pass's counters, one pass behind) instead of the default
                              device-counted passes; needs less workspace */
+  PDQ_HEAPSORT = 1u << 9, /* the fallback of segments out of bad-partition budget (Section 4.1)
+                             is the paper's heapsort, one lane per segment in the user buffer,
+                             instead of the default workgroup merge sort (also O(n log n)) */
   PDQ_FRESH_FIXED = 1u << 6 /* after a bad partition take the fresh pivot candidates at the fixed
                              quarter offsets of Section 4.2's deterministic rule instead of the
                              default hashed positions (Section 4.2's randomised rule; the hash
@@ -162,9 +165,9 @@ typedef struct pdq_options {
                             (partition tile, slots per lane of the two widest LDS classes):
                             (8192, 16), (16384, 16), (32768, 16), (8192, 32) */
   uint32_t batch_passes; /* device-counted passes (PDQ_BATCHED, and pdq_sort without
-                            PDQ_HOST_LOOP): 0 = automatic (h + 2 + h/3, h the halvings that
+                            PDQ_HOST_LOOP): 0 = automatic (h + 2 + h/2, h the halvings that
                             bring the largest segment to the widest LDS class); k > 0 = k - 1
-                            passes (at most 24); segments still live after them finish in the
+                            passes (at most 32); segments still live after them finish in the
                             persistent tail */
   uint32_t waves;        /* 0 = each LDS base-case size class takes its default (or tuned)
                             workgroup shape; 1, 2, 4, 8 or 16 = every class that has a shape of

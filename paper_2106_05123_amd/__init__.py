@@ -27,7 +27,7 @@ __all__ = [
     "segmented_sort_", "status_string", "abi_version", "KEY_TYPES", "FLAG_VALIDATE", "FLAG_PROFILE",
     "FLAG_LEARNED", "MLP_PARAMS", "LEARN_SAMPLE", "mlp_infer", "mlp_gradient", "mlp_train",
     "learned_features", "learned_extract", "bucket_histogram", "learned_fit", "learned_leaves", "sample_judge", "FLAG_BATCHED", "FLAG_AUTOTUNE", "FLAG_DETERMINISTIC",
-    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED", "FLAG_VALS64", "FLAG_HOST_LOOP",
+    "Plan", "sort_noalloc_", "NOALLOC_SCRATCH_BYTES", "check", "FLAG_FRESH_FIXED", "FLAG_VALS64", "FLAG_HOST_LOOP", "FLAG_HEAPSORT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -46,6 +46,7 @@ FLAG_DETERMINISTIC = 32
 FLAG_FRESH_FIXED = 64
 FLAG_VALS64 = 128
 FLAG_HOST_LOOP = 256
+FLAG_HEAPSORT = 512
 # batched shapes: (partition tile, slots per lane of the 8192 / 16384-key LDS classes)
 BATCH_SHAPES = ((8192, 16), (16384, 16), (32768, 16), (8192, 32))
 MLP_PARAMS = 1153
@@ -282,7 +283,8 @@ def _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_
 def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False, stats: bool = False,
           workspace=None, learned: bool = False, seed: int = 0, imbalance_limit: float = 0.0,
           learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0, deterministic: bool = False,
-          fresh_fixed: bool = False, waves: int = 0, host_loop: bool = False, batch_passes: int | None = None):
+          fresh_fixed: bool = False, waves: int = 0, host_loop: bool = False, batch_passes: int | None = None,
+          heapsort: bool = False):
     """Sort a 1-D device tensor in place (ascending canonical order).
     learned=True runs the learned multiway first pass (see pdq_learned.h);
     deterministic=True selects the look-back partition (PDQ_DETERMINISTIC);
@@ -290,13 +292,16 @@ def sort_(keys, *, force_budget: int = -1, tile: int = 0, profile: bool = False,
     bad partition (PDQ_FRESH_FIXED) instead of hashed positions; waves
     (1, 2, 4, 8, 16) sets the workgroup shape of the LDS base-case classes;
     host_loop=True runs the host-driven pass loop (PDQ_HOST_LOOP) instead of
-    the device-counted passes, whose number batch_passes overrides."""
+    the device-counted passes, whose number batch_passes overrides;
+    heapsort=True makes the fallback of segments out of budget the paper's
+    heapsort (PDQ_HEAPSORT)."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
     kt, opt, ws, need, stream = _prepare(keys, None, 1, force_budget, tile,
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
                                          (FLAG_FRESH_FIXED if fresh_fixed else 0) |
-                                         (FLAG_HOST_LOOP if host_loop else 0), workspace,
+                                         (FLAG_HOST_LOOP if host_loop else 0) |
+                                         (FLAG_HEAPSORT if heapsort else 0), workspace,
                                          dict(learn, waves=waves, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kt, 0, ctypes.c_void_p(ws.data_ptr()),
@@ -309,7 +314,7 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
                 stats: bool = False, workspace=None, learned: bool = False, seed: int = 0,
                 imbalance_limit: float = 0.0, learn_steps: int = 0, learn_batch: int = 0, learn_grid: int = 0,
                 deterministic: bool = False, fresh_fixed: bool = False, waves: int = 0, host_loop: bool = False,
-                batch_passes: int | None = None):
+                batch_passes: int | None = None, heapsort: bool = False):
     """Sort keys in place and move the payload `vals` (uint32, or uint64:
     PDQ_VALS64) with them."""
     lf, learn = _learn_opts(learned, seed, imbalance_limit, learn_steps, learn_batch, learn_grid)
@@ -317,7 +322,8 @@ def sort_pairs_(keys, vals, *, force_budget: int = -1, tile: int = 0, profile: b
                                          (FLAG_PROFILE if profile else 0) | lf |
                                          (FLAG_DETERMINISTIC if deterministic else 0) |
                                          (FLAG_FRESH_FIXED if fresh_fixed else 0) |
-                                         (FLAG_HOST_LOOP if host_loop else 0), workspace,
+                                         (FLAG_HOST_LOOP if host_loop else 0) |
+                                         (FLAG_HEAPSORT if heapsort else 0), workspace,
                                          dict(learn, waves=waves, batch_passes=batch_passes))
     st = Stats(ctypes.sizeof(Stats)) if (stats or profile) else None
     rc = lib().pdq_sort_pairs(ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()), keys.numel(),

@@ -62,7 +62,7 @@ constexpr int kTunedShapes = 3;
 
 // Passes the device-counted form queues at most; deeper recursions finish in
 // the persistent tail.
-constexpr uint32_t kMaxBatchPasses = 24;
+constexpr uint32_t kMaxBatchPasses = 32;
 
 struct BatchArgs {
   BatchQ* q;

@@ -345,6 +345,44 @@ __global__ __launch_bounds__(kCtlThreads) void k_copy(Ctx c, uint32_t nitems) {
   }
 }
 
+// The paper's fallback (PDQ_HEAPSORT): Williams' heapsort of a[0..len) (and
+// payloads v, if any) by one lane, in place in the user buffer.
+template <class K>
+__device__ void sift_down(typename K::T* a, uint32_t* v, uint64_t root, uint64_t n) {
+  for (;;) {
+    uint64_t child = 2 * root + 1;
+    if (child >= n) return;
+    if (child + 1 < n && K::ord(a[child]) < K::ord(a[child + 1])) ++child;
+    if (!(K::ord(a[root]) < K::ord(a[child]))) return;
+    typename K::T t = a[root];
+    a[root] = a[child];
+    a[child] = t;
+    if (v) {
+      uint32_t tv = v[root];
+      v[root] = v[child];
+      v[child] = tv;
+    }
+    root = child;
+  }
+}
+
+template <class K>
+__device__ void heapsort_range(typename K::T* a, uint32_t* v, uint64_t len) {
+  if (len < 2) return;
+  for (uint64_t r = len / 2; r-- > 0;) sift_down<K>(a, v, r, len);
+  for (uint64_t end = len - 1; end > 0; --end) {
+    typename K::T t = a[0];
+    a[0] = a[end];
+    a[end] = t;
+    if (v) {
+      uint32_t tv = v[0];
+      v[0] = v[end];
+      v[end] = tv;
+    }
+    sift_down<K>(a, v, 0, end);
+  }
+}
+
 // Fallback sort of Section 4.1, for a segment that used up its bad-partition
 // budget. The paper heapsorts the segment in place: O(n log n) whatever the
 // input, but one element at a time. Here one workgroup merge-sorts it, also
@@ -461,7 +499,26 @@ __global__ __launch_bounds__(kCtlThreads) void k_heap(Ctx c, uint32_t nitems) {
       }
       continue;
     }
-    fallback_sort<K, PAIRS>(c, it, sh);
+    if (c.heapsort) {
+      // the paper's heapsort: the segment moves to the user buffer, then one
+      // lane sorts it there
+      const uint64_t len = it.end - it.begin;
+      typename K::T* a = static_cast<typename K::T*>(c.keys[0]) + it.begin;
+      uint32_t* v = PAIRS ? c.vals[0] + it.begin : nullptr;
+      if (it.buf != 0) {
+        const typename K::T* in = static_cast<const typename K::T*>(c.keys[it.buf]) + it.begin;
+        for (uint64_t j = threadIdx.x; j < len; j += blockDim.x) {
+          a[j] = in[j];
+          if constexpr (PAIRS) v[j] = c.vals[it.buf][it.begin + j];
+        }
+        __threadfence_block();
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) heapsort_range<K>(a, v, len);
+      __syncthreads();
+    } else {
+      fallback_sort<K, PAIRS>(c, it, sh);
+    }
   }
 }
 

@@ -312,7 +312,7 @@ int read_opts(const pdq_options* o, Opts* out) {
   if (sz >= offsetof(pdq_options, tune_cache_path) + sizeof(const char*)) out->tune_cache = o->tune_cache_path;
   if (out->flags &
       ~static_cast<uint32_t>(PDQ_VALIDATE | PDQ_PROFILE | PDQ_LEARNED | PDQ_BATCHED | PDQ_AUTOTUNE |
-                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64 | PDQ_HOST_LOOP))
+                             PDQ_DETERMINISTIC | PDQ_FRESH_FIXED | PDQ_VALS64 | PDQ_HOST_LOOP | PDQ_HEAPSORT))
     return PDQ_ERR_UNSUPPORTED;
   if (out->batch_shape > static_cast<uint32_t>(kBatchShapes)) return PDQ_ERR_UNSUPPORTED;
   if (out->waves != 0 && out->waves != 1 && out->waves != 2 && out->waves != 4 && out->waves != 8 &&
@@ -732,6 +732,7 @@ Ctx make_ctx(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   apply_waves(c, o.waves);
   c.lookback = (o.flags & PDQ_DETERMINISTIC) ? 1u : 0u;
   c.fresh_fixed = (o.flags & PDQ_FRESH_FIXED) ? 1u : 0u;
+  c.heapsort = (o.flags & PDQ_HEAPSORT) ? 1u : 0u;
   return c;
 }
 
@@ -905,7 +906,7 @@ Ctx batch_ctx(Ctx c, const Opts& o, const Tuned& t) {
 // to the widest LDS class, plus two for uneven splits. Anything deeper
 // finishes in the persistent tail.
 // Device-counted passes to queue for a largest segment of m keys: the
-// halvings that bring it to base_max, plus 2 and a third of them again
+// halvings that bring it to base_max, plus 2 and half of them again
 // (splits are uneven, so some paths need more passes; a pass that finds no
 // live segment costs a few microseconds, while a segment left to the
 // persistent tail is partitioned by a single workgroup).
@@ -916,7 +917,7 @@ uint32_t batch_passes(uint64_t m, uint32_t base_max) {
     ++p;
   }
   if (p == 0) return 0;
-  p += 2 + p / 3;
+  p += 2 + p / 2;
   return p < kMaxBatchPasses ? p : kMaxBatchPasses;
 }
 

@@ -163,6 +163,7 @@ struct Ctx {
   uint8_t pad2_;
   uint32_t lookback;    // 1: tiles take their places by a decoupled look-back (deterministic order)
   uint32_t fresh_fixed; // 1: fresh candidates at the fixed quarter offsets instead of hashed positions
+  uint32_t heapsort;    // 1: the fallback of segments out of budget is the paper's one-lane heapsort
 };
 
 // ---- key traits: canonical unsigned image in registers only ---------------

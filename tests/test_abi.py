@@ -87,7 +87,7 @@ def test_argument_errors_without_gpu(pdq):
     assert _call_sort(pdq, 0x1000, 1 << 20, ws_bytes=100) == -3
     assert _call_sort(pdq, 0, 0) == 0                        # n <= 1 is a no-op
     assert _call_sort(pdq, 0, 1) == 0
-    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0x200, -1, 0, 0)) == -2  # unknown flag
+    assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0x400, -1, 0, 0)) == -2  # unknown flag
     assert _call_sort(pdq, 0x1000, 10, opt=Opt(ctypes.sizeof(Opt), 0, -1, 3000, 0)) == -2  # bad tile
     # pairs without payload, segmented without offsets
     assert L.pdq_sort_pairs(ctypes.c_void_p(0x1000), None, 10, 1, 0, ctypes.c_void_p(0x10000), 1 << 40, None,

@@ -384,6 +384,18 @@ def test_forced_heapsort(n, host_loop, kt):
     check_pairs(a, out, vo)
 
 
+@pytest.mark.parametrize("n,host_loop", [(5000, True), (100003, True), (20000, False), (100003, False)])
+def test_paper_heapsort_fallback_option(n, host_loop):
+    """PDQ_HEAPSORT: the fallback is the paper's heapsort (Section 4.1), one
+    lane per segment in the user buffer; same keys as the oracle."""
+    a = W.uniform_u32(n, seed=n + 1)
+    v = W.index_payload(n)
+    out, vo, st = gpu_sort(a, v, force_budget=0, host_loop=host_loop, heapsort=True)
+    assert st["heapsort_segments"] == 1 and st["heapsort_elements"] == n
+    assert np.array_equal(out, oracle.sort(a)[0])
+    check_pairs(a, out, vo)
+
+
 def test_fallback_sort_of_segments_out_of_budget_in_the_tail():
     """With no device-counted pass, the persistent tail partitions the
     input; its planted bad first partition uses up a budget of 1, so the
