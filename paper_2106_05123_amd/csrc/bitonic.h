@@ -32,6 +32,9 @@ struct Slot;
 template <class K>
 struct Slot<K, false, false> {
   using V = uint32_t;
+  using I = uint32_t;  // the key image (bucket sort)
+  static constexpr bool kBucket = true;
+  __device__ static I img(V v) { return v; }
   static constexpr int kLdsBytes = 4;
   __device__ static V make(uint32_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return 0xFFFFFFFFu; }
@@ -48,6 +51,9 @@ struct Slot<K, false, false> {
 template <class K>
 struct Slot<K, true, false> {
   using V = uint64_t;
+  using I = uint32_t;
+  static constexpr bool kBucket = true;
+  __device__ static I img(V v) { return static_cast<uint32_t>(v >> 32); }
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint32_t raw, uint32_t i) { return (static_cast<uint64_t>(K::ord(raw)) << 32) | i; }
   __device__ static V pad() { return ~0ull; }
@@ -64,6 +70,9 @@ struct Slot<K, true, false> {
 template <class K>
 struct Slot<K, false, true> {
   using V = uint64_t;
+  using I = uint64_t;
+  static constexpr bool kBucket = true;
+  __device__ static I img(V v) { return v; }
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint64_t raw, uint32_t) { return K::ord(raw); }
   __device__ static V pad() { return ~0ull; }
@@ -80,6 +89,9 @@ struct Slot<K, false, true> {
 template <class K>
 struct Slot<K, true, true> {
   using V = KV;
+  using I = uint64_t;
+  static constexpr bool kBucket = false;  // two LDS planes: the bucket sort does not serve it
+  __device__ static I img(V v) { return v.k; }
   static constexpr int kLdsBytes = 12;
   __device__ static V make(uint64_t raw, uint32_t i) { return KV{K::ord(raw), i}; }
   __device__ static V pad() { return KV{~0ull, 0xFFFFFFFFu}; }
@@ -234,6 +246,222 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
     }
     __syncthreads();
   }
+}
+
+
+// ---------------------------------------------------------------- bucket sort
+
+// Bucket sort of the real slots of a P = E * NT block, for segments whose
+// keys spread over their range (a segment that reaches the base case lies
+// between two pivots, or inside one bin of a learned model). The range
+// [lo, hi] of the key images is cut into nb = 2^b equal-width buckets, nb
+// the power of two with about kBkMean keys a bucket (at most P / kBkMean).
+// Every key takes a rank inside its bucket from an LDS atomic on its
+// bucket's 16-bit counter (two to a word), the counters are scanned into
+// bucket starts, and each key is stored at its bucket's start plus its
+// arrival rank. Then every key counts, over the members of its bucket, those
+// that sort before it (ties broken by arrival rank), which is its place
+// inside the bucket, and is written to its bucket's start plus that place.
+// Buckets are ordered like their keys, so the array is then sorted.
+//
+// On entry x[r] holds the slot of segment position r * NT + tid (padding
+// from position len on). Keys that cluster (a sample of one key a lane
+// crowds one sixty-fourth of the range) or a bucket of more than kBkMax keys
+// (many copies of few values) make the call return false with x untouched,
+// and the caller sorts x another way; on true the sorted sequence is in LDS
+// as a plain array of len slots (S::V each) at sh.
+constexpr int kBkMean = 4;
+constexpr int kBkMax = 32;
+// positions whose buckets are ranked together (independent LDS reads)
+constexpr int kBkGroup = 4;
+
+// coarse ranges of the sample test
+constexpr int kBkCoarse = 64;
+
+// LDS words the bucket sort needs besides the block's data plane.
+template <int P, int NT>
+constexpr int bucket_words() {
+  return P / kBkMean / 2 + 1 + kBkCoarse + 4 * (NT / 64) + 2;
+}
+
+template <class S, int E, int NT>
+__device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigned char* sh, uint32_t* bk, int tid,
+                                            int len) {
+  using V = typename S::V;
+  using I = typename S::I;
+  constexpr int P = E * NT;
+  constexpr int W = NT / 64;
+  constexpr int kWords = P / kBkMean / 2;  // packed counters, two buckets a word
+  const int lane = tid & 63, wave = tid >> 6;
+  uint32_t* cnt = bk;                                          // [kWords + 1]
+  uint32_t* coarse = bk + kWords + 1;                          // [kBkCoarse]
+  I* red = reinterpret_cast<I*>(bk + kWords + 1 + kBkCoarse);  // [2 W] wave minima and maxima
+  uint32_t* sc = bk + kWords + 1 + kBkCoarse + 4 * W;          // [0] largest bucket
+  static_assert(E * NT == P && (kBkGroup & (kBkGroup - 1)) == 0 && E % kBkGroup == 0, "bucket sort shape");
+  // x[r] is a real key for r < nreal (positions r * NT + tid below len)
+  const int nreal = tid < len ? (len - 1 - tid) / NT + 1 : 0;
+  // 1. range of the real images
+  I lo = ~I(0), hi = I(0);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (r < nreal) {
+      const I v = S::img(x[r]);
+      lo = v < lo ? v : lo;
+      hi = v > hi ? v : hi;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const I olo = __shfl_xor(lo, d, 64), ohi = __shfl_xor(hi, d, 64);
+    lo = olo < lo ? olo : lo;
+    hi = ohi > hi ? ohi : hi;
+  }
+  if (lane == 0) {
+    red[2 * wave] = lo;
+    red[2 * wave + 1] = hi;
+  }
+  for (int i = tid; i <= kWords + kBkCoarse; i += NT) cnt[i] = 0;  // counters and coarse ranges
+  if (tid == 0) sc[0] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const I plo = red[2 * w], phi = red[2 * w + 1];
+    lo = plo < lo ? plo : lo;
+    hi = phi > hi ? phi : hi;
+  }
+  const I span = hi > lo ? static_cast<I>(hi - lo) : I(0);
+  int nbits = 0;
+  while ((kBkMean << nbits) < len && (2 << nbits) <= 2 * kWords) ++nbits;
+  int sbits = 0;
+  if constexpr (sizeof(I) == 8) sbits = span ? 64 - __clzll(static_cast<long long>(span)) : 0;
+  else sbits = span ? 32 - __clz(static_cast<int>(span)) : 0;
+  const int shift = sbits > nbits ? sbits - nbits : 0;
+  // sample test: each lane's first key (lanes past the end take no part)
+  // goes to one of kBkCoarse ranges of buckets. Keys that
+  // spread evenly put a few times NT / kBkCoarse in each; a range holding
+  // over an eighth of the sample means clustered keys, whose buckets would
+  // overflow after the full count, so the merge sort takes them at once.
+  {
+    const int cshift = nbits > 6 ? nbits - 6 : 0;
+    if (tid < len) atomicAdd(&coarse[static_cast<uint32_t>((S::img(x[0]) - lo) >> shift) >> cshift], 1u);
+    __syncthreads();
+    uint32_t cm = coarse[lane];
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint32_t t = __shfl_xor(cm, d, 64);
+      cm = t > cm ? t : cm;
+    }
+    constexpr uint32_t kThr = NT / 8 > 8 ? NT / 8 : 8;
+    if (cm > kThr) return false;  // every wave reduces the same LDS words: a uniform exit
+  }
+  // 2. rank of every real key inside its bucket (bucket index in the high
+  //    half of br, arrival rank in the low half; both stay below 2^16)
+  uint32_t br[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    br[r] = 0;
+    if (r < nreal) {
+      const uint32_t d = static_cast<uint32_t>((S::img(x[r]) - lo) >> shift);
+      const uint32_t sh16 = (d & 1u) << 4;
+      const uint32_t old = atomicAdd(&cnt[d >> 1], 1u << sh16);
+      br[r] = (d << 16) | ((old >> sh16) & 0xFFFFu);
+    }
+  }
+  __syncthreads();
+  // 3. exclusive scan of the counters into bucket starts (kept packed);
+  //    the word after the last holds len, the end of the last bucket
+  constexpr int kPer = (kWords + NT - 1) / NT;
+  uint32_t cw[kPer];
+  uint32_t own = 0, mx = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid * kPer + k;
+    cw[k] = i < kWords ? cnt[i] : 0u;
+    const uint32_t c0 = cw[k] & 0xFFFFu, c1 = cw[k] >> 16;
+    own += c0 + c1;
+    mx = c0 > mx ? c0 : mx;
+    mx = c1 > mx ? c1 : mx;
+  }
+  uint32_t incl = own;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t t = __shfl_xor(mx, d, 64);
+    mx = t > mx ? t : mx;
+  }
+  uint32_t* wsum = reinterpret_cast<uint32_t*>(red);  // the range is consumed: reuse
+  __syncthreads();
+  if (lane == 63) wsum[wave] = incl;
+  if (lane == 0) atomicMax(&sc[0], mx);
+  __syncthreads();
+  if (sc[0] > static_cast<uint32_t>(kBkMax)) return false;  // one LDS word: the same for every lane
+  uint32_t run = incl - own;
+  for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid * kPer + k;
+    if (i < kWords) {
+      const uint32_t c0 = cw[k] & 0xFFFFu;
+      cnt[i] = run | ((run + c0) << 16);
+      run += c0 + (cw[k] >> 16);
+    }
+  }
+  if (tid == 0) cnt[kWords] = static_cast<uint32_t>(len);
+  __syncthreads();
+  // 4. scatter to bucket start + arrival rank
+  V* data = reinterpret_cast<V*>(sh);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (r < nreal) {
+      const uint32_t d = br[r] >> 16;
+      const uint32_t st = (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
+      data[st + (br[r] & 0xFFFFu)] = x[r];
+    }
+  }
+  __syncthreads();
+  // 5. every key counts the members of its bucket that sort before it (ties
+  //    by arrival rank), kBkGroup keys at a time for independent LDS reads;
+  //    br[r] becomes the key's final position. Reads past a bucket's end
+  //    stay inside the block (start + k < len + kBkMax <= P) and are masked.
+#pragma unroll
+  for (int g = 0; g < E; g += kBkGroup) {
+    int s[kBkGroup], n[kBkGroup], o[kBkGroup];
+    uint32_t rk[kBkGroup];
+    int nmax = 0;
+#pragma unroll
+    for (int q = 0; q < kBkGroup; ++q) {
+      const int r = g + q;
+      s[q] = 0;
+      n[q] = 0;
+      o[q] = static_cast<int>(br[r] & 0xFFFFu);
+      rk[q] = 0;
+      if (r < nreal) {
+        const uint32_t d = br[r] >> 16;
+        const uint32_t a = (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
+        const uint32_t e = (cnt[(d + 1) >> 1] >> (((d + 1) & 1u) << 4)) & 0xFFFFu;
+        s[q] = static_cast<int>(a);
+        n[q] = static_cast<int>(e - a);
+        nmax = n[q] > nmax ? n[q] : nmax;
+      }
+    }
+    for (int k = 0; k < nmax; ++k) {
+#pragma unroll
+      for (int q = 0; q < kBkGroup; ++q) {
+        const V v = data[s[q] + k];
+        const bool before = S::lt(v, x[g + q]) || (!S::lt(x[g + q], v) && k < o[q]);
+        rk[q] += (k < n[q] && before) ? 1u : 0u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kBkGroup; ++q) br[g + q] = static_cast<uint32_t>(s[q]) + rk[q];
+  }
+  __syncthreads();
+  // 6. every key to its place
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+    if (r < nreal) data[br[r]] = x[r];
+  __syncthreads();
+  return true;
 }
 
 }  // namespace net

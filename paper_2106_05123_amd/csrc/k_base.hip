@@ -3,10 +3,13 @@
 // the user buffer.
 //
 // The paper sorts small subsequences with insertion sort (Section 5.1) and
-// notes that sorting networks lost on its CPU through code size (Section 2);
-// on a GPU a bitonic network (bitonic.h) is the natural small sort. A
-// segment of P = E * NT slots (padded to a power of two) is held E slots per
-// lane in registers; payloads are gathered by index at the end.
+// notes that sorting networks lost on its CPU through code size (Section 2).
+// Here a segment of P = E * NT slots (padded to a power of two) is held E
+// slots per lane in registers and sorted in one workgroup (bitonic.h): a
+// bitonic network below 1024 slots; from 2048 slots an LDS bucket sort when
+// the keys spread over their range (a segment between two pivots usually
+// does), else, and from 1024 slots, a merge sort. Payloads are gathered by
+// index at the end.
 #include "bitonic.h"
 #include "pdq_internal.h"
 #include "wave_ops.h"
@@ -19,6 +22,11 @@ using net::lds_plane;
 using net::lds_pos;
 using net::Slot;
 
+// Smallest block (E * NT slots) that tries the bucket sort before the merge
+// sort: segments that reach the base case lie between two pivots, so their
+// keys usually spread over their range and the buckets come out even.
+constexpr int kBucketMinSlots = 2048;
+
 // One workgroup per base-case segment of at most E * NT keys; a workgroup
 // takes items blockIdx.x, blockIdx.x + gridDim.x, ... of its class list
 // (the list length comes from the device counters in the batched form).
@@ -29,7 +37,9 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   using V = typename S::V;
   constexpr int P = E * NT;
   constexpr int PL = lds_plane<P, E>();
+  constexpr bool kBucket = S::kBucket && P >= kBucketMinSlots;
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
+  __shared__ __align__(8) uint32_t bk[kBucket ? net::bucket_words<P, NT>() : 1];
   // a list longer than its capacity (only invalid offsets make one; it is
   // flagged) is read no further than its capacity
   uint32_t count = c.device_counts ? c.icnt[cls] : nitems;
@@ -41,30 +51,40 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
     asm volatile("" : "+v"(tid));
     const Item it = c.base[cls][item];
     const int len = static_cast<int>(it.end - it.begin);
+    if (len < 1) continue;  // never pushed; the loads below read position len - 1
     const T* in = static_cast<const T*>(c.keys[it.buf]) + it.begin;
 
-    // coalesced load into LDS, then each lane picks up its E consecutive slots
+    // coalesced load straight into registers: x[r] is segment position
+    // r * NT + tid (the sorts below take their slots in any arrangement).
+    // Every lane loads (positions past the end read the last key and are
+    // replaced by padding), so the E loads are in flight together.
+    V x[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int j = r * NT + tid;
-      S::st(sh, PL, lds_pos<E>(j), S::sel(j < len, S::make(j < len ? in[j] : T(0), static_cast<uint32_t>(j)), S::pad()));
+      const V v = S::make(in[j < len ? j : len - 1], static_cast<uint32_t>(j));
+      x[r] = S::sel(j < len, v, S::pad());
     }
-    __syncthreads();
-    V x[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) x[r] = S::ld(sh, PL, lds_pos<E>((tid << ilog2(E)) | r));
-    __syncthreads();
 
-    if constexpr (E * NT >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
-    else net::bitonic<S, E, NT>(x, sh, tid);
-
-    // back through LDS so that the final writes are coalesced
+    // the bucket sort leaves the sorted slots in LDS as a plain array; the
+    // networks leave them in registers, which go to the padded layout
+    bool plain = false;
+    if constexpr (kBucket) plain = net::bucket_sort<S, E, NT>(x, sh, bk, tid, len);
+    if (!plain) {
+      if constexpr (P >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
+      else net::bitonic<S, E, NT>(x, sh, tid);
+      // back through LDS so that the final writes are coalesced
 #pragma unroll
-    for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
-    __syncthreads();
+      for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
+      __syncthreads();
+    }
     V y[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) y[r] = S::ld(sh, PL, lds_pos<E>(r * NT + tid));
+    for (int r = 0; r < E; ++r) {
+      const int j = r * NT + tid;
+      if constexpr (kBucket) y[r] = plain ? reinterpret_cast<const V*>(sh)[j] : S::ld(sh, PL, lds_pos<E>(j));
+      else y[r] = S::ld(sh, PL, lds_pos<E>(j));
+    }
     T* out = static_cast<T*>(c.keys[0]) + it.begin;
     if constexpr (PAIRS) {
       // gather every payload before anything is written: the segment may be

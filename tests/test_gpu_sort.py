@@ -131,6 +131,55 @@ def test_all_equal_and_two_values():
         assert np.array_equal(out, np.sort(a))
 
 
+# ------------------------------------------------------------------ LDS base case paths
+
+def _base_case_keys(kind, n, seed):
+    """Single segments that go to the LDS base case whole, shaped for each
+    path of its block sort: keys that spread over their range (bucket sort),
+    keys that cluster (the sample test sends them to the merge sort), few
+    distinct values (a bucket overflows), exactly 32 and 33 copies of evenly
+    spaced values (the largest bucket at and just past its limit: ties inside
+    buckets), and 64-bit and floating-point images."""
+    rng = np.random.default_rng(seed)
+    if kind == "uniform_u32":
+        return rng.integers(0, 1 << 32, n, dtype=np.uint32)
+    if kind == "narrow_u32":
+        return (1000 + rng.integers(0, 3 * n, n)).astype(np.uint32)
+    if kind == "normal_f32":
+        return rng.standard_normal(n, dtype=np.float32)
+    if kind == "unit_f32":
+        return (1.0 + rng.random(n, dtype=np.float32)).astype(np.float32)
+    if kind == "few_u32":
+        return rng.integers(0, 40, n).astype(np.uint32)
+    if kind in ("copies32_u32", "copies33_u32"):
+        c = 32 if kind == "copies32_u32" else 33
+        a = np.repeat(np.arange(-(-n // c), dtype=np.uint64) * 1000003, c)[:n].astype(np.uint32)
+        return rng.permutation(a)
+    if kind == "signed_i64":
+        return rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
+    if kind == "uniform_f64":
+        return rng.standard_normal(n) * 1e-3 + 5.0
+    raise ValueError(kind)
+
+
+BASE_KINDS = ("uniform_u32", "narrow_u32", "normal_f32", "unit_f32", "few_u32", "copies32_u32",
+              "copies33_u32", "signed_i64", "uniform_f64")
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("host_loop", [False, True])
+@pytest.mark.parametrize("n", [2049, 4096, 8193, 16384])
+@pytest.mark.parametrize("kind", BASE_KINDS)
+def test_lds_base_case_block_sort_paths(kind, n, host_loop, pairs):
+    a = _base_case_keys(kind, n, seed=n)
+    v = W.index_payload(n) if pairs else None
+    out, vo, st = gpu_sort(a, v, host_loop=host_loop)
+    ref = oracle.sort(a)[0]
+    assert np.array_equal(as_bytes(out), as_bytes(ref))
+    if pairs:
+        check_pairs(a, out, vo)
+
+
 # ------------------------------------------------------------------ pairs / equal keys
 
 @pytest.mark.parametrize("k", [2, 16, 1024, 65536, "mix"])
