@@ -34,6 +34,7 @@ struct Slot<K, false, false> {
   using V = uint32_t;
   using I = uint32_t;  // the key image (bucket sort)
   static constexpr bool kBucket = true;
+  static constexpr bool kUnique = false;  // equal keys give equal slots
   __device__ static I img(V v) { return v; }
   static constexpr int kLdsBytes = 4;
   __device__ static V make(uint32_t raw, uint32_t) { return K::ord(raw); }
@@ -53,6 +54,7 @@ struct Slot<K, true, false> {
   using V = uint64_t;
   using I = uint32_t;
   static constexpr bool kBucket = true;
+  static constexpr bool kUnique = true;  // the index makes every slot distinct
   __device__ static I img(V v) { return static_cast<uint32_t>(v >> 32); }
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint32_t raw, uint32_t i) { return (static_cast<uint64_t>(K::ord(raw)) << 32) | i; }
@@ -72,6 +74,7 @@ struct Slot<K, false, true> {
   using V = uint64_t;
   using I = uint64_t;
   static constexpr bool kBucket = true;
+  static constexpr bool kUnique = false;
   __device__ static I img(V v) { return v; }
   static constexpr int kLdsBytes = 8;
   __device__ static V make(uint64_t raw, uint32_t) { return K::ord(raw); }
@@ -91,6 +94,7 @@ struct Slot<K, true, true> {
   using V = KV;
   using I = uint64_t;
   static constexpr bool kBucket = false;  // two LDS planes: the bucket sort does not serve it
+  static constexpr bool kUnique = true;
   __device__ static I img(V v) { return v.k; }
   static constexpr int kLdsBytes = 12;
   __device__ static V make(uint64_t raw, uint32_t i) { return KV{K::ord(raw), i}; }
@@ -259,10 +263,12 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
 // Every key takes a rank inside its bucket from an LDS atomic on its
 // bucket's 16-bit counter (two to a word), the counters are scanned into
 // bucket starts, and each key is stored at its bucket's start plus its
-// arrival rank. Then every key counts, over the members of its bucket, those
-// that sort before it (ties broken by arrival rank), which is its place
-// inside the bucket, and is written to its bucket's start plus that place.
-// Buckets are ordered like their keys, so the array is then sorted.
+// arrival rank. Then every key counts the members of its bucket that sort
+// before it, which is its place inside the bucket, and is written to its
+// bucket's start plus that place. Buckets are ordered like their keys, so
+// the array is then sorted. With a payload every slot is distinct; without
+// one, a key also counts its equals and writes its value over all of their
+// places (they hold the same bits).
 //
 // On entry x[r] holds the slot of segment position r * NT + tid (padding
 // from position len on). Keys that cluster (a sample of one key a lane
@@ -270,7 +276,7 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
 // (many copies of few values) make the call return false with x untouched,
 // and the caller sorts x another way; on true the sorted sequence is in LDS
 // as a plain array of len slots (S::V each) at sh.
-constexpr int kBkMean = 4;
+constexpr int kBkMean = 2;
 constexpr int kBkMax = 32;
 // positions whose buckets are ranked together (independent LDS reads)
 constexpr int kBkGroup = 4;
@@ -418,48 +424,66 @@ __device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigne
       data[st + (br[r] & 0xFFFFu)] = x[r];
     }
   }
+  // padding after the last key (len + kBkMax <= P + P / E: inside the
+  // block's LDS plane), so that reads past a bucket's end find keys of later
+  // buckets or padding, neither of which sorts before a key of the bucket
+  if (tid < kBkMax) data[len + tid] = S::pad();
   __syncthreads();
-  // 5. every key counts the members of its bucket that sort before it (ties
-  //    by arrival rank), kBkGroup keys at a time for independent LDS reads;
-  //    br[r] becomes the key's final position. Reads past a bucket's end
-  //    stay inside the block (start + k < len + kBkMax <= P) and are masked.
+  // 5. every key counts the slots of its bucket that sort before it, and
+  //    without a payload also its equals; kBkGroup keys at a time for
+  //    independent LDS reads. Reads run to the longest of the lane's buckets
+  //    (start + k < len + kBkMax); past a key's own bucket they find greater
+  //    keys or padding, so nothing is masked. (A key equal to the padding is
+  //    in the last bucket: the padding it counts as equal only stretches its
+  //    writes past position len, which is never read.) br[r] becomes the
+  //    key's first place.
+  uint32_t eq[E];
 #pragma unroll
   for (int g = 0; g < E; g += kBkGroup) {
-    int s[kBkGroup], n[kBkGroup], o[kBkGroup];
-    uint32_t rk[kBkGroup];
+    int s[kBkGroup];
+    uint32_t lt[kBkGroup], ne[kBkGroup];
     int nmax = 0;
 #pragma unroll
     for (int q = 0; q < kBkGroup; ++q) {
       const int r = g + q;
       s[q] = 0;
-      n[q] = 0;
-      o[q] = static_cast<int>(br[r] & 0xFFFFu);
-      rk[q] = 0;
+      lt[q] = 0;
+      ne[q] = 0;
       if (r < nreal) {
         const uint32_t d = br[r] >> 16;
         const uint32_t a = (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
         const uint32_t e = (cnt[(d + 1) >> 1] >> (((d + 1) & 1u) << 4)) & 0xFFFFu;
         s[q] = static_cast<int>(a);
-        n[q] = static_cast<int>(e - a);
-        nmax = n[q] > nmax ? n[q] : nmax;
+        const int n = static_cast<int>(e - a);
+        nmax = n > nmax ? n : nmax;
       }
     }
     for (int k = 0; k < nmax; ++k) {
 #pragma unroll
       for (int q = 0; q < kBkGroup; ++q) {
         const V v = data[s[q] + k];
-        const bool before = S::lt(v, x[g + q]) || (!S::lt(x[g + q], v) && k < o[q]);
-        rk[q] += (k < n[q] && before) ? 1u : 0u;
+        lt[q] += S::lt(v, x[g + q]) ? 1u : 0u;
+        if constexpr (!S::kUnique) ne[q] += v == x[g + q] ? 1u : 0u;
       }
     }
 #pragma unroll
-    for (int q = 0; q < kBkGroup; ++q) br[g + q] = static_cast<uint32_t>(s[q]) + rk[q];
+    for (int q = 0; q < kBkGroup; ++q) {
+      br[g + q] = static_cast<uint32_t>(s[q]) + lt[q];
+      eq[g + q] = ne[q];
+    }
   }
   __syncthreads();
-  // 6. every key to its place
+  // 6. every key to its place (without a payload, over its equals' places)
 #pragma unroll
-  for (int r = 0; r < E; ++r)
-    if (r < nreal) data[br[r]] = x[r];
+  for (int r = 0; r < E; ++r) {
+    if (r < nreal) {
+      if constexpr (S::kUnique) {
+        data[br[r]] = x[r];
+      } else {
+        for (uint32_t t = 0; t < eq[r]; ++t) data[br[r] + t] = x[r];
+      }
+    }
+  }
   __syncthreads();
   return true;
 }
