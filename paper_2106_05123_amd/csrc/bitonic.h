@@ -184,20 +184,11 @@ __device__ __forceinline__ void bitonic(typename S::V (&x)[E], unsigned char* sh
   }
 }
 
-// Merge sort of P = E * NT slots. On entry lane tid holds slots
-// [tid*E, tid*E + E) in any order; on exit the same positions of the sorted
-// sequence. Each lane first sorts its E registers (a bitonic network inside
-// the lane), then log2(NT) merge levels double the sorted run length: all
-// runs go to LDS, and each lane produces its E outputs of the merged pair by
-// a merge-path binary search for its starting split followed by E steps of a
-// sequential merge, one LDS read per step (ties taken from the left run).
-template <class S, int E, int NT>
-__device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char* sh, int tid) {
+// Ascending bitonic sort of one lane's E registers.
+template <class S, int E>
+__device__ __forceinline__ void lane_sort(typename S::V (&x)[E]) {
   using V = typename S::V;
   constexpr int e = ilog2(E);
-  constexpr int P = E * NT;
-  constexpr int PL = lds_plane<P, E>();
-  // runs of E inside each lane
 #pragma unroll
   for (int kb = 1; kb <= e; ++kb) {
 #pragma unroll
@@ -214,6 +205,38 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
       }
     }
   }
+}
+
+// Ascending bitonic merge of one lane's E registers holding a bitonic sequence.
+template <class S, int E>
+__device__ __forceinline__ void lane_merge(typename S::V (&x)[E]) {
+  using V = typename S::V;
+#pragma unroll
+  for (int j = E / 2; j > 0; j >>= 1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (r & j) continue;
+      const V a = x[r], c = x[r + j];
+      const bool sw = S::lt(c, a);
+      x[r] = S::sel(sw, c, a);
+      x[r + j] = S::sel(sw, a, c);
+    }
+  }
+}
+
+// Merge sort of P = E * NT slots. On entry lane tid holds slots
+// [tid*E, tid*E + E) in any order; on exit the same positions of the sorted
+// sequence. Each lane first sorts its E registers (a bitonic network inside
+// the lane), then log2(NT) merge levels double the sorted run length: all
+// runs go to LDS, and each lane produces its E outputs of the merged pair by
+// a merge-path binary search for its starting split followed by E steps of a
+// sequential merge, one LDS read per step (ties taken from the left run).
+template <class S, int E, int NT>
+__device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char* sh, int tid) {
+  using V = typename S::V;
+  constexpr int P = E * NT;
+  constexpr int PL = lds_plane<P, E>();
+  lane_sort<S, E>(x);  // runs of E inside each lane
   const V pad = S::pad();
   for (int run = E; run < P; run <<= 1) {
 #pragma unroll
@@ -263,19 +286,30 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
 // Every key takes a rank inside its bucket from an LDS atomic on its
 // bucket's 16-bit counter (two to a word), the counters are scanned into
 // bucket starts, and each key is stored at its bucket's start plus its
-// arrival rank. Then every key counts the members of its bucket that sort
-// before it, which is its place inside the bucket, and is written to its
-// bucket's start plus that place. Buckets are ordered like their keys, so
-// the array is then sorted. With a payload every slot is distinct; without
-// one, a key also counts its equals and writes its value over all of their
-// places (they hold the same bits).
+// arrival rank. Buckets are ordered like their keys, so every key now sits
+// inside the range of places it takes in the sorted block; only the order
+// inside each bucket is left. Two ways finish it:
+//  * NET (network finish): each lane sorts the E consecutive places
+//    [tid * E, tid * E + E) in its registers, then neighbouring lanes merge
+//    their runs twice, lanes (2m, 2m+1) and then (2m+1, 2m+2), each keeping
+//    its half of the pair (a half-cleaner and a bitonic merge). A bucket of
+//    at most E keys spans at most two lanes, and the merge at its boundary
+//    sorts it whole; merges at other boundaries leave it alone. Buckets are
+//    capped at min(E, 16) keys, and the result is left in x, lane tid
+//    holding places [tid * E, tid * E + E).
+//  * rank count: every key counts the members of its bucket that sort
+//    before it, which is its place inside the bucket, and is written to its
+//    bucket's start plus that place. With a payload every slot is distinct;
+//    without one, a key also counts its equals and writes its value over all
+//    of their places (they hold the same bits). Buckets are capped at kBkMax
+//    keys, and the result is left in LDS as a plain array of len slots.
 //
 // On entry x[r] holds the slot of segment position r * NT + tid (padding
 // from position len on). Keys that cluster (a sample of one key a lane
-// crowds one sixty-fourth of the range) or a bucket of more than kBkMax keys
-// (many copies of few values) make the call return false with x untouched,
-// and the caller sorts x another way; on true the sorted sequence is in LDS
-// as a plain array of len slots (S::V each) at sh.
+// crowds one sixty-fourth of the range) or a bucket above the cap (many
+// copies of few values) make the call return kBkFailed with x untouched,
+// and the caller sorts x another way.
+enum BucketResult : int { kBkFailed = 0, kBkInLds = 1, kBkInRegs = 2 };
 constexpr int kBkMean = 2;
 constexpr int kBkMax = 32;
 // positions whose buckets are ranked together (independent LDS reads)
@@ -290,14 +324,15 @@ constexpr int bucket_words() {
   return P / kBkMean / 2 + 1 + kBkCoarse + 4 * (NT / 64) + 2;
 }
 
-template <class S, int E, int NT>
-__device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigned char* sh, uint32_t* bk, int tid,
-                                            int len) {
+template <class S, int E, int NT, bool NET>
+__device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char* sh, uint32_t* bk, int tid,
+                                           int len) {
   using V = typename S::V;
   using I = typename S::I;
   constexpr int P = E * NT;
   constexpr int W = NT / 64;
   constexpr int kWords = P / kBkMean / 2;  // packed counters, two buckets a word
+  constexpr int kCap = NET ? (E < 16 ? E : 16) : kBkMax;  // largest bucket
   const int lane = tid & 63, wave = tid >> 6;
   uint32_t* cnt = bk;                                          // [kWords + 1]
   uint32_t* coarse = bk + kWords + 1;                          // [kBkCoarse]
@@ -356,7 +391,7 @@ __device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigne
       cm = t > cm ? t : cm;
     }
     constexpr uint32_t kThr = NT / 8 > 8 ? NT / 8 : 8;
-    if (cm > kThr) return false;  // every wave reduces the same LDS words: a uniform exit
+    if (cm > kThr) return kBkFailed;  // every wave reduces the same LDS words: a uniform exit
   }
   // 2. rank of every real key inside its bucket (bucket index in the high
   //    half of br, arrival rank in the low half; both stay below 2^16)
@@ -400,7 +435,7 @@ __device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigne
   if (lane == 63) wsum[wave] = incl;
   if (lane == 0) atomicMax(&sc[0], mx);
   __syncthreads();
-  if (sc[0] > static_cast<uint32_t>(kBkMax)) return false;  // one LDS word: the same for every lane
+  if (sc[0] > static_cast<uint32_t>(kCap)) return kBkFailed;  // one LDS word: the same for every lane
   uint32_t run = incl - own;
   for (int w = 0; w < wave; ++w) run += wsum[w];
 #pragma unroll
@@ -421,8 +456,44 @@ __device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigne
     if (r < nreal) {
       const uint32_t d = br[r] >> 16;
       const uint32_t st = (cnt[d >> 1] >> ((d & 1u) << 4)) & 0xFFFFu;
-      data[st + (br[r] & 0xFFFFu)] = x[r];
+      const int at = static_cast<int>(st + (br[r] & 0xFFFFu));
+      if constexpr (NET) data[lds_pos<E>(at)] = x[r];  // lane runs are read back: the padded layout
+      else data[at] = x[r];
     }
+  }
+  if constexpr (NET) {
+    __syncthreads();
+    // 5. sort the lane's run of E places, then merge with the neighbours
+    const V pad = S::pad();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int at = tid * E + r;
+      x[r] = at < len ? data[lds_pos<E>(at)] : pad;
+    }
+    lane_sort<S, E>(x);
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+      // the lane's own places only, which no other lane reads until the barrier
+#pragma unroll
+      for (int r = 0; r < E; ++r) data[lds_pos<E>(tid * E + r)] = x[r];
+      __syncthreads();
+      const int partner = round == 0 ? (tid ^ 1) : ((tid & 1) ? tid + 1 : tid - 1);
+      if (partner >= 0 && partner < NT) {
+        const bool lower = tid < partner;
+        // half-cleaner against the partner's run reversed: the lower lane
+        // keeps the E smallest of the pair, the upper lane the E largest,
+        // each as a bitonic sequence
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const V b = data[lds_pos<E>(partner * E + (E - 1 - r))];
+          const bool take = lower ? S::lt(b, x[r]) : S::lt(x[r], b);
+          x[r] = S::sel(take, b, x[r]);
+        }
+        lane_merge<S, E>(x);
+      }
+      __syncthreads();  // partner reads done before the next writes
+    }
+    return kBkInRegs;
   }
   // padding after the last key (len + kBkMax <= P + P / E: inside the
   // block's LDS plane), so that reads past a bucket's end find keys of later
@@ -485,7 +556,7 @@ __device__ __forceinline__ bool bucket_sort(const typename S::V (&x)[E], unsigne
     }
   }
   __syncthreads();
-  return true;
+  return kBkInLds;
 }
 
 }  // namespace net

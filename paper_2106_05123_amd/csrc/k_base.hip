@@ -38,6 +38,11 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
   constexpr int P = E * NT;
   constexpr int PL = lds_plane<P, E>();
   constexpr bool kBucket = S::kBucket && P >= kBucketMinSlots;
+  // the bucket sort's finish: sorted lane runs and neighbour merges without
+  // a payload, the in-bucket rank count (one compare a member) with one;
+  // with 8 slots a lane the network finish would cap buckets at 8 keys,
+  // which evenly spread keys overflow too often
+  constexpr bool kBucketNet = !PAIRS && E >= 16;
   __shared__ __align__(16) unsigned char sh[PL * S::kLdsBytes];
   __shared__ __align__(8) uint32_t bk[kBucket ? net::bucket_words<P, NT>() : 1];
   // a list longer than its capacity (only invalid offsets make one; it is
@@ -66,13 +71,16 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
       x[r] = S::sel(j < len, v, S::pad());
     }
 
-    // the bucket sort leaves the sorted slots in LDS as a plain array; the
-    // networks leave them in registers, which go to the padded layout
-    bool plain = false;
-    if constexpr (kBucket) plain = net::bucket_sort<S, E, NT>(x, sh, bk, tid, len);
-    if (!plain) {
-      if constexpr (P >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
-      else net::bitonic<S, E, NT>(x, sh, tid);
+    // the sorts leave lane tid holding places [tid * E, tid * E + E) in its
+    // registers, which go back through the padded LDS layout; the bucket
+    // sort's rank-count finish leaves a plain array in LDS instead
+    int res = net::kBkFailed;
+    if constexpr (kBucket) res = net::bucket_sort<S, E, NT, kBucketNet>(x, sh, bk, tid, len);
+    if (res != net::kBkInLds) {
+      if (res == net::kBkFailed) {
+        if constexpr (P >= 1024) net::merge_sort<S, E, NT>(x, sh, tid);
+        else net::bitonic<S, E, NT>(x, sh, tid);
+      }
       // back through LDS so that the final writes are coalesced
 #pragma unroll
       for (int r = 0; r < E; ++r) S::st(sh, PL, lds_pos<E>((tid << ilog2(E)) | r), x[r]);
@@ -82,8 +90,10 @@ __global__ __launch_bounds__(NT) void k_base(Ctx c, int cls, uint32_t nitems) {
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int j = r * NT + tid;
-      if constexpr (kBucket) y[r] = plain ? reinterpret_cast<const V*>(sh)[j] : S::ld(sh, PL, lds_pos<E>(j));
-      else y[r] = S::ld(sh, PL, lds_pos<E>(j));
+      if constexpr (kBucket && !kBucketNet)
+        y[r] = res == net::kBkInLds ? reinterpret_cast<const V*>(sh)[j] : S::ld(sh, PL, lds_pos<E>(j));
+      else
+        y[r] = S::ld(sh, PL, lds_pos<E>(j));
     }
     T* out = static_cast<T*>(c.keys[0]) + it.begin;
     if constexpr (PAIRS) {
