@@ -137,9 +137,10 @@ def _base_case_keys(kind, n, seed):
     """Single segments that go to the LDS base case whole, shaped for each
     path of its block sort: keys that spread over their range (bucket sort),
     keys that cluster (the sample test sends them to the merge sort), few
-    distinct values (a bucket overflows), exactly 32 and 33 copies of evenly
-    spaced values (the largest bucket at and just past its limit: ties inside
-    buckets), and 64-bit and floating-point images."""
+    distinct values (a bucket overflows), exactly 16, 17, 32 and 33 copies of
+    evenly spaced values (the largest bucket at and just past the two finishes'
+    caps: ties inside buckets, buckets over two lanes' runs), and 64-bit and
+    floating-point images."""
     rng = np.random.default_rng(seed)
     if kind == "uniform_u32":
         return rng.integers(0, 1 << 32, n, dtype=np.uint32)
@@ -151,8 +152,8 @@ def _base_case_keys(kind, n, seed):
         return (1.0 + rng.random(n, dtype=np.float32)).astype(np.float32)
     if kind == "few_u32":
         return rng.integers(0, 40, n).astype(np.uint32)
-    if kind in ("copies32_u32", "copies33_u32"):
-        c = 32 if kind == "copies32_u32" else 33
+    if kind.startswith("copies"):
+        c = int(kind[len("copies"):].split("_")[0])
         a = np.repeat(np.arange(-(-n // c), dtype=np.uint64) * 1000003, c)[:n].astype(np.uint32)
         return rng.permutation(a)
     if kind == "signed_i64":
@@ -162,8 +163,8 @@ def _base_case_keys(kind, n, seed):
     raise ValueError(kind)
 
 
-BASE_KINDS = ("uniform_u32", "narrow_u32", "normal_f32", "unit_f32", "few_u32", "copies32_u32",
-              "copies33_u32", "signed_i64", "uniform_f64")
+BASE_KINDS = ("uniform_u32", "narrow_u32", "normal_f32", "unit_f32", "few_u32", "copies16_u32",
+              "copies17_u32", "copies32_u32", "copies33_u32", "signed_i64", "uniform_f64")
 
 
 @pytest.mark.parametrize("pairs", [False, True])
