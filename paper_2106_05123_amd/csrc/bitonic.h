@@ -32,6 +32,7 @@ struct Slot;
 template <class K>
 struct Slot<K, false, false> {
   using V = uint32_t;
+  using Key = K;
   using I = uint32_t;  // the key image (bucket sort)
   static constexpr bool kBucket = true;
   static constexpr bool kUnique = false;  // equal keys give equal slots
@@ -52,6 +53,7 @@ struct Slot<K, false, false> {
 template <class K>
 struct Slot<K, true, false> {
   using V = uint64_t;
+  using Key = K;
   using I = uint32_t;
   static constexpr bool kBucket = true;
   static constexpr bool kUnique = true;  // the index makes every slot distinct
@@ -72,6 +74,7 @@ struct Slot<K, true, false> {
 template <class K>
 struct Slot<K, false, true> {
   using V = uint64_t;
+  using Key = K;
   using I = uint64_t;
   static constexpr bool kBucket = true;
   static constexpr bool kUnique = false;
@@ -92,6 +95,7 @@ struct Slot<K, false, true> {
 template <class K>
 struct Slot<K, true, true> {
   using V = KV;
+  using Key = K;
   using I = uint64_t;
   static constexpr bool kBucket = false;  // two LDS planes: the bucket sort does not serve it
   static constexpr bool kUnique = true;
@@ -278,11 +282,38 @@ __device__ __forceinline__ void merge_sort(typename S::V (&x)[E], unsigned char*
 
 // ---------------------------------------------------------------- bucket sort
 
+// Floating-point keys: the value behind a canonical image. The bucket sort
+// cuts the range of values, not of images, when every key is finite.
+template <class K>
+struct FloatOf {
+  static constexpr bool kFloat = false;
+  using F = float;
+  template <class I>
+  __device__ static F val(I) { return F(0); }
+};
+template <>
+struct FloatOf<KeyF32> {
+  static constexpr bool kFloat = true;
+  using F = float;
+  __device__ static F val(uint32_t img) { return __uint_as_float(KeyF32::inv(img)); }
+};
+template <>
+struct FloatOf<KeyF64> {
+  static constexpr bool kFloat = true;
+  using F = double;
+  __device__ static F val(uint64_t img) { return __longlong_as_double(static_cast<long long>(KeyF64::inv(img))); }
+};
+
+
 // Bucket sort of the real slots of a P = E * NT block, for segments whose
 // keys spread over their range (a segment that reaches the base case lies
 // between two pivots, or inside one bin of a learned model). The range
 // [lo, hi] of the key images is cut into nb = 2^b equal-width buckets, nb
 // the power of two with about kBkMean keys a bucket (at most P / kBkMean).
+// Floating-point keys cut the range of their values instead when every key
+// is finite: images crowd a few exponents (values near zero, or a range
+// that spans zero, put most keys in a sliver of the image range), values
+// do not. Either way the bucket index never decreases as the key grows.
 // Every key takes a rank inside its bucket from an LDS atomic on its
 // bucket's 16-bit counter (two to a word), the counters are scanned into
 // bucket starts, and each key is stored at its bucket's start plus its
@@ -376,6 +407,34 @@ __device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char*
   if constexpr (sizeof(I) == 8) sbits = span ? 64 - __clzll(static_cast<long long>(span)) : 0;
   else sbits = span ? 32 - __clz(static_cast<int>(span)) : 0;
   const int shift = sbits > nbits ? sbits - nbits : 0;
+  using FO = FloatOf<typename S::Key>;
+  using F = typename FO::F;
+  bool lin = false;  // buckets over the values
+  F f0 = F(0), fscale = F(0);
+  if constexpr (FO::kFloat) {
+    // the extreme images hold the extreme values; NaNs and infinities sort
+    // outermost, so finite ends mean every key is finite
+    const F a = FO::val(lo), b = FO::val(hi);
+    const F w = b - a;
+    if (isfinite(a) && isfinite(b) && isfinite(w) && w > F(0)) {
+      lin = true;
+      f0 = a;
+      fscale = static_cast<F>(1 << nbits) / w;
+    }
+  }
+  const uint32_t dmax = (1u << nbits) - 1u;
+  // bucket of an image: monotone in the key (subtraction, scaling by a
+  // positive factor and truncation all keep the order), at most dmax
+  auto digit = [&](I img) -> uint32_t {
+    if constexpr (FO::kFloat) {
+      if (lin) {
+        const F t = (FO::val(img) - f0) * fscale;
+        const uint32_t d = t < static_cast<F>(dmax) ? static_cast<uint32_t>(t) : dmax;
+        return d;
+      }
+    }
+    return static_cast<uint32_t>((img - lo) >> shift);
+  };
   // sample test: each lane's first key (lanes past the end take no part)
   // goes to one of kBkCoarse ranges of buckets. Keys that
   // spread evenly put a few times NT / kBkCoarse in each; a range holding
@@ -383,7 +442,7 @@ __device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char*
   // overflow after the full count, so the merge sort takes them at once.
   {
     const int cshift = nbits > 6 ? nbits - 6 : 0;
-    if (tid < len) atomicAdd(&coarse[static_cast<uint32_t>((S::img(x[0]) - lo) >> shift) >> cshift], 1u);
+    if (tid < len) atomicAdd(&coarse[digit(S::img(x[0])) >> cshift], 1u);
     __syncthreads();
     uint32_t cm = coarse[lane];
     for (int d = 32; d >= 1; d >>= 1) {
@@ -400,7 +459,7 @@ __device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char*
   for (int r = 0; r < E; ++r) {
     br[r] = 0;
     if (r < nreal) {
-      const uint32_t d = static_cast<uint32_t>((S::img(x[r]) - lo) >> shift);
+      const uint32_t d = digit(S::img(x[r]));
       const uint32_t sh16 = (d & 1u) << 4;
       const uint32_t old = atomicAdd(&cnt[d >> 1], 1u << sh16);
       br[r] = (d << 16) | ((old >> sh16) & 0xFFFFu);

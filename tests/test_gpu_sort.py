@@ -140,7 +140,9 @@ def _base_case_keys(kind, n, seed):
     distinct values (a bucket overflows), exactly 16, 17, 32 and 33 copies of
     evenly spaced values (the largest bucket at and just past the two finishes'
     caps: ties inside buckets, buckets over two lanes' runs), and 64-bit and
-    floating-point images."""
+    floating-point images. Float blocks cut their range of values when every
+    key is finite (normal keys, keys on both sides of zero) and their range of
+    images otherwise (infinities and NaNs)."""
     rng = np.random.default_rng(seed)
     if kind == "uniform_u32":
         return rng.integers(0, 1 << 32, n, dtype=np.uint32)
@@ -156,6 +158,22 @@ def _base_case_keys(kind, n, seed):
         c = int(kind[len("copies"):].split("_")[0])
         a = np.repeat(np.arange(-(-n // c), dtype=np.uint64) * 1000003, c)[:n].astype(np.uint32)
         return rng.permutation(a)
+    if kind == "spanzero_f32":
+        # values on both sides of zero with both zeros: a sliver of the image range each
+        a = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+        a[rng.integers(0, n, 16)] = np.float32(0.0)
+        a[rng.integers(0, n, 16)] = np.float32(-0.0)
+        return a
+    if kind == "normal_inf_nan_f32":
+        # non-finite keys send the block back to image buckets
+        a = rng.standard_normal(n, dtype=np.float32)
+        a[rng.integers(0, n, 3)] = np.inf
+        a[rng.integers(0, n, 3)] = -np.inf
+        a[rng.integers(0, n, 2)] = np.float32("nan")
+        a[rng.integers(0, n, 1)] = -np.float32("nan")
+        return a
+    if kind == "normal_f64":
+        return rng.standard_normal(n)
     if kind == "signed_i64":
         return rng.integers(-(1 << 62), 1 << 62, n, dtype=np.int64)
     if kind == "uniform_f64":
@@ -163,8 +181,9 @@ def _base_case_keys(kind, n, seed):
     raise ValueError(kind)
 
 
-BASE_KINDS = ("uniform_u32", "narrow_u32", "normal_f32", "unit_f32", "few_u32", "copies16_u32",
-              "copies17_u32", "copies32_u32", "copies33_u32", "signed_i64", "uniform_f64")
+BASE_KINDS = ("uniform_u32", "narrow_u32", "normal_f32", "unit_f32", "spanzero_f32", "normal_inf_nan_f32",
+              "few_u32", "copies16_u32", "copies17_u32", "copies32_u32", "copies33_u32", "signed_i64",
+              "uniform_f64", "normal_f64")
 
 
 @pytest.mark.parametrize("pairs", [False, True])
