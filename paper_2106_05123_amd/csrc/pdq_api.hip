@@ -381,9 +381,11 @@ int finish_items(const Ctx& c, const Counters& snap, hipStream_t s) { return fin
 // created on first need (one per concurrent call and device) and kept until
 // the process ends.
 constexpr int kPinSlots = 4;
+constexpr size_t kStageBytes = 8192;  // pinned staging for the few words a host decision reads
 struct PinBlock {
   int dev = -1;
   Counters* host = nullptr;
+  unsigned char* stage = nullptr;
   hipEvent_t ev[kPinSlots] = {};
 };
 std::mutex g_pin_mu;
@@ -409,12 +411,14 @@ PinBlock* pin_acquire() {
   b->dev = dev;
   bool ok = hipHostMalloc(reinterpret_cast<void**>(&b->host), kPinSlots * sizeof(Counters), hipHostMallocDefault) ==
             hipSuccess;
+  ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->stage), kStageBytes, hipHostMallocDefault) == hipSuccess;
   for (int i = 0; ok && i < kPinSlots; ++i) ok = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();  // the failure must not be reported by a later launch
     for (auto& e : b->ev)
       if (e) (void)hipEventDestroy(e);
     if (b->host) (void)hipHostFree(b->host);
+    if (b->stage) (void)hipHostFree(b->stage);
     delete b;
     return nullptr;
   }
@@ -424,6 +428,44 @@ PinBlock* pin_acquire() {
 void pin_release(PinBlock* b) {
   std::lock_guard<std::mutex> lk(g_pin_mu);
   g_pin_free.push_back(b);
+}
+
+// Holds a call's block and gives it back when the call returns.
+struct PinGuard {
+  PinBlock* p;
+  ~PinGuard() {
+    if (p) pin_release(p);
+  }
+};
+
+// Device -> host reads of the few words a host decision needs. With a
+// pinned staging block every copy queues behind the kernels and one
+// synchronisation covers them all; into pageable memory (no block: the
+// call allocates nothing) each copy waits on its own.
+struct ReadItem {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+int read_to_host(PinBlock* pin, const ReadItem* it, int k, hipStream_t s) {
+  size_t total = 0;
+  for (int i = 0; i < k; ++i) total += (it[i].bytes + 7) & ~static_cast<size_t>(7);
+  const bool staged = pin && pin->stage && total <= kStageBytes;
+  size_t off = 0;
+  for (int i = 0; i < k; ++i) {
+    void* d = staged ? static_cast<void*>(pin->stage + off) : it[i].dst;
+    HIP_TRY(hipMemcpyAsync(d, it[i].src, it[i].bytes, hipMemcpyDeviceToHost, s));
+    off += (it[i].bytes + 7) & ~static_cast<size_t>(7);
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (staged) {
+    off = 0;
+    for (int i = 0; i < k; ++i) {
+      memcpy(it[i].dst, pin->stage + off, it[i].bytes);
+      off += (it[i].bytes + 7) & ~static_cast<size_t>(7);
+    }
+  }
+  return PDQ_OK;
 }
 
 int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size_t nseg, int kt, int order,
@@ -522,7 +564,7 @@ bool hopeless(uint64_t judge, uint64_t m) { return judge * 64ull > m; }
 // from the same initial parameters for o.steps steps. *steps_run receives
 // the steps of the kept fit.
 int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitBufs& f, hipStream_t s,
-            uint64_t go_limit = ~0ull, uint32_t* steps_run = nullptr) {
+            uint64_t go_limit = ~0ull, uint32_t* steps_run = nullptr, PinBlock* pin = nullptr) {
   int rc = run_fit_sample(keys, n, kt, o, f, s);
   if (rc != PDQ_OK) return rc;
   uint32_t steps = o.steps;
@@ -530,8 +572,9 @@ int run_fit(const void* keys, uint64_t n, uint32_t kt, const Opts& o, const FitB
     rc = run_fit_model(o, kStage1Steps, f, s, go_limit);
     if (rc != PDQ_OK) return rc;
     uint64_t info[kInfoWords] = {};
-    HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const ReadItem rd[] = {{info, f.info, sizeof(info)}};
+    rc = read_to_host(pin, rd, 1, s);
+    if (rc != PDQ_OK) return rc;
     const uint64_t choice = info[3] < kCandidates ? info[3] : 0;
     if (early_accept(info[4 + choice], kLearnSample) || hopeless(info[4 + choice], kLearnSample)) {
       if (steps_run) *steps_run = kStage1Steps;
@@ -591,7 +634,7 @@ struct LearnedResult {
 // `unordered`: the run scan has already seen both a descending and an
 // ascending adjacent pair, so the order scan is skipped.
 int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, LearnedResult& res, hipStream_t s,
-                bool unordered = false) {
+                bool unordered = false, PinBlock* pin = nullptr) {
   const uint32_t kt = c.key_type;
   const uint64_t n = c.n;
   const uint32_t kb = key_bytes(kt);
@@ -605,8 +648,9 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
     // by the plain path's first pass: find out before the fit is paid for
     uint32_t order_bits = 0;
     HIP_TRY(launch_order_scan(kt, c.keys[0], n, b.order, s));
-    HIP_TRY(hipMemcpyAsync(&order_bits, b.order, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    const ReadItem rd[] = {{&order_bits, b.order, 4}};
+    const int rc0 = read_to_host(pin, rd, 1, s);
+    if (rc0 != PDQ_OK) return rc0;
     if ((order_bits & 1u) == 0 || (order_bits & 2u) == 0) {
       res.ordered = 1;
       res.state = 2;
@@ -622,7 +666,7 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   const uint64_t go_limit = lim >= 0.0 ? static_cast<uint64_t>(lim) : 0ull;
   b.go = f.info + 7;
   uint32_t steps_run = o.steps;
-  int rc = run_fit(c.keys[0], n, kt, o, f, s, go_limit, &steps_run);
+  int rc = run_fit(c.keys[0], n, kt, o, f, s, go_limit, &steps_run, pin);
   if (rc != PDQ_OK) return rc;
   res.steps = steps_run;
   if (prof) {
@@ -637,12 +681,15 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   uint32_t count = 0, sync[2] = {0, 0};
   uint64_t info[kInfoWords] = {};
   float loss = 0.0f;
-  HIP_TRY(hipMemcpyAsync(totals, b.totals, sizeof(totals), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&count, f.count, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(sync, f.sync, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(info, f.info, sizeof(info), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&loss, f.losses + (steps_run - 1), 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  {
+    const ReadItem rd[] = {{totals, b.totals, sizeof(totals)},
+                           {&count, f.count, 4},
+                           {sync, f.sync, 8},
+                           {info, f.info, sizeof(info)},
+                           {&loss, f.losses + (steps_run - 1), 4}};
+    rc = read_to_host(pin, rd, 5, s);
+    if (rc != PDQ_OK) return rc;
+  }
   res.splitters = count;
   res.use_log = static_cast<uint32_t>(info[2]);
   res.loss = loss;
@@ -758,11 +805,14 @@ RunBufs run_bufs(const Layout& L, char* base, size_t n) {
 // few outliers, or two long runs is finished here by a merge and
 // plan->state says so; otherwise (state kRunUnsorted) the partition passes
 // sort it.
-int run_near_sorted(const Ctx& c, const Layout& L, char* base, RunPlan* plan, hipStream_t s) {
+int run_near_sorted(const Ctx& c, const Layout& L, char* base, RunPlan* plan, hipStream_t s, PinBlock* pin = nullptr) {
   const RunBufs rb = run_bufs(L, base, c.n);
   HIP_TRY(launch_run_scan(c, rb, s));
-  HIP_TRY(hipMemcpyAsync(plan, rb.plan, sizeof(RunPlan), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  {
+    const ReadItem rd[] = {{plan, rb.plan, sizeof(RunPlan)}};
+    const int rc = read_to_host(pin, rd, 1, s);
+    if (rc != PDQ_OK) return rc;
+  }
   if (plan->state == kRunOutliers) {
     HIP_TRY(launch_run_gather(c, rb, plan->nshort, s));
     if (plan->outliers > 1) {
@@ -1308,10 +1358,13 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
 
   Counters snap = {};
   HIP_TRY(launch_reset(c, s));
+  // pinned host memory for the call's reads (none in the call that allocates nothing)
+  PinBlock* pin = t_noalloc ? nullptr : pin_acquire();
+  const PinGuard pin_guard{pin};
   bool unordered = false;  // both a descending and an ascending pair seen
   if (!offsets && uses_runs(n, 1)) {
     RunPlan plan = {};
-    rc = run_near_sorted(c, L, base, &plan, s);
+    rc = run_near_sorted(c, L, base, &plan, s, pin);
     unordered = plan.descents > 0 && plan.ascent != 0;
     if (rc != PDQ_OK) return rc;
     if (plan.state != kRunUnsorted) {
@@ -1336,7 +1389,7 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   uint32_t src = 0;
   if (learned) {
     c.single = 0;  // the first partition pass sees the bins, not the whole range
-    rc = run_learned(c, o, L, base, prof, lres, s, unordered);
+    rc = run_learned(c, o, L, base, prof, lres, s, unordered, pin);
     if (rc != PDQ_OK) return rc;
     if (lres.state == 1) src = 1;
     else if (!o.tile && !dev_passes) c.tile = auto_tile(n, n);  // judged and fell back: one segment [0, n)
@@ -1361,10 +1414,8 @@ int run_sort(void* keys, uint32_t* vals, size_t n, const uint64_t* offsets, size
   const uint64_t bytes_per_key = 2ull * kb + (vals ? 8ull : 0ull);
   uint32_t pass = 0;
   uint64_t visits = 0;
-  PinBlock* pin = t_noalloc ? nullptr : pin_acquire();
   if (pin) {
     rc = run_passes_pipelined(c, o, L, base, snap, src, prof, bytes_per_key, timed, &pass, &visits, pin, s);
-    pin_release(pin);
   } else {
     rc = run_passes_sync(c, o, snap, src, prof, bytes_per_key, timed, &pass, &visits, s);
   }
