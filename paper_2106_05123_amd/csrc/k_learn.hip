@@ -628,26 +628,44 @@ __global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __r
   if (tid < kMaxSplitters) {
     const uint64_t q = (static_cast<uint64_t>(tid + 1) * m) / 256u;
     const uint64_t key = s[q];
-    uint64_t lo = 0, hi = q;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (s[mid] < key) lo = mid + 1;
-      else hi = mid;
+    // [first, last): the run of key in the sorted sample; the searches are
+    // skipped when a neighbour already shows the run is q alone
+    uint64_t first = q, last = q + 1;
+    if (q > 0 && s[q - 1] == key) {
+      uint64_t lo = 0, hi = q;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (s[mid] < key) lo = mid + 1;
+        else hi = mid;
+      }
+      first = lo;
     }
-    const uint64_t first = lo;
-    lo = q;
-    hi = m;
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) >> 1;
-      if (s[mid] <= key) lo = mid + 1;
-      else hi = mid;
+    if (q + 1 < m && s[q + 1] == key) {
+      uint64_t lo = q + 1, hi = m;
+      while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (s[mid] <= key) lo = mid + 1;
+        else hi = mid;
+      }
+      last = lo;
     }
-    const bool heavy = (lo - first) * 256u >= m;
+    const bool heavy = (last - first) * 256u >= m;
     uint64_t idx = q;
     if (!heavy) {
+      // first i with r[i] >= thr: the first lane block whose running
+      // maximum reaches thr (s_max holds them, in LDS), then inside it
       const float thr = static_cast<float>(tid + 1) / 256.0f;
-      lo = 0;
-      hi = m;
+      uint32_t tlo = 0, thi = kExtractThreads;
+      while (tlo < thi) {
+        const uint32_t mid = (tlo + thi) >> 1;
+        if (s_max[mid] < thr) tlo = mid + 1;
+        else thi = mid;
+      }
+      uint64_t lo = m, hi = m;
+      if (tlo < kExtractThreads) {
+        lo = static_cast<uint64_t>(tlo) * per < m ? static_cast<uint64_t>(tlo) * per : m;
+        hi = lo + per < m ? lo + per : m;
+      }
       while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
         if (r[mid] < thr) lo = mid + 1;
