@@ -43,6 +43,7 @@ struct Slot<K, false, false> {
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static V shf(V a, int src) { return __shfl(a, src, 64); }
   __device__ static uint32_t key(V v) { return K::inv(v); }
   __device__ static uint32_t idx(V) { return 0; }
   __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
@@ -64,6 +65,7 @@ struct Slot<K, true, false> {
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static V shf(V a, int src) { return __shfl(a, src, 64); }
   __device__ static uint32_t key(V v) { return K::inv(static_cast<uint32_t>(v >> 32)); }
   __device__ static uint32_t idx(V v) { return static_cast<uint32_t>(v); }
   __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
@@ -85,6 +87,7 @@ struct Slot<K, false, true> {
   __device__ static V sel(bool c, V a, V b) { return c ? a : b; }
   __device__ static bool lt(V a, V b) { return a < b; }
   __device__ static V xch(V a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static V shf(V a, int src) { return __shfl(a, src, 64); }
   __device__ static uint64_t key(V v) { return K::inv(v); }
   __device__ static uint32_t idx(V) { return 0; }
   __device__ static void st(unsigned char* s, int, int i, V v) { reinterpret_cast<V*>(s)[i] = v; }
@@ -107,6 +110,7 @@ struct Slot<K, true, true> {
   __device__ static V sel(bool c, V a, V b) { return KV{c ? a.k : b.k, c ? a.i : b.i}; }
   __device__ static bool lt(V a, V b) { return a.k < b.k || (a.k == b.k && a.i < b.i); }
   __device__ static V xch(V a, int m) { return KV{__shfl_xor(a.k, m, 64), static_cast<uint32_t>(__shfl_xor(a.i, m, 64))}; }
+  __device__ static V shf(V a, int src) { return KV{__shfl(a.k, src, 64), static_cast<uint32_t>(__shfl(a.i, src, 64))}; }
   __device__ static uint64_t key(V v) { return K::inv(v.k); }
   __device__ static uint32_t idx(V v) { return v.i; }
   // a plane of `plane` keys, then a plane of `plane` indices
@@ -530,27 +534,56 @@ __device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char*
       x[r] = at < len ? data[lds_pos<E>(at)] : pad;
     }
     lane_sort<S, E>(x);
+    // round 0: partners tid ^ 1, always in one wave: the partner's run comes
+    // by shuffles, no LDS and no barrier
+    {
+      const bool lower = (lane & 1) == 0;
+      V b[E];
 #pragma unroll
-    for (int round = 0; round < 2; ++round) {
-      // the lane's own places only, which no other lane reads until the barrier
+      for (int r = 0; r < E; ++r) b[r] = S::xch(x[E - 1 - r], 1);
+      // half-cleaner against the partner's run reversed: the lower lane
+      // keeps the E smallest of the pair, the upper lane the E largest,
+      // each as a bitonic sequence
 #pragma unroll
-      for (int r = 0; r < E; ++r) data[lds_pos<E>(tid * E + r)] = x[r];
+      for (int r = 0; r < E; ++r) {
+        const bool take = lower ? S::lt(b[r], x[r]) : S::lt(x[r], b[r]);
+        x[r] = S::sel(take, b[r], x[r]);
+      }
+      lane_merge<S, E>(x);
+    }
+    // round 1: partners (2m+1, 2m+2). Inside a wave by shuffles; across a
+    // wave boundary (lane 63 with the next wave's lane 0) the two runs go
+    // through LDS, in the counters' space (read for the last time by the
+    // scatter, before the barrier that preceded this step)
+    {
+      V* edge = reinterpret_cast<V*>(bk);  // [wave][0: lane 0, 1: lane 63][E]
+      if (lane == 0 || lane == 63) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) edge[(2 * wave + (lane == 63 ? 1 : 0)) * E + r] = x[r];
+      }
       __syncthreads();
-      const int partner = round == 0 ? (tid ^ 1) : ((tid & 1) ? tid + 1 : tid - 1);
+      const int partner = (tid & 1) ? tid + 1 : tid - 1;
+      const int src = (lane & 1) ? lane + 1 : lane - 1;  // lanes 0 and 63 read LDS instead
+      V b[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) b[r] = S::shf(x[E - 1 - r], src & 63);
+      if (lane == 63 && partner < NT) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) b[r] = edge[(2 * (wave + 1)) * E + (E - 1 - r)];
+      }
+      if (lane == 0 && partner >= 0) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) b[r] = edge[(2 * (wave - 1) + 1) * E + (E - 1 - r)];
+      }
       if (partner >= 0 && partner < NT) {
         const bool lower = tid < partner;
-        // half-cleaner against the partner's run reversed: the lower lane
-        // keeps the E smallest of the pair, the upper lane the E largest,
-        // each as a bitonic sequence
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-          const V b = data[lds_pos<E>(partner * E + (E - 1 - r))];
-          const bool take = lower ? S::lt(b, x[r]) : S::lt(x[r], b);
-          x[r] = S::sel(take, b, x[r]);
+          const bool take = lower ? S::lt(b[r], x[r]) : S::lt(x[r], b[r]);
+          x[r] = S::sel(take, b[r], x[r]);
         }
         lane_merge<S, E>(x);
       }
-      __syncthreads();  // partner reads done before the next writes
     }
     return kBkInRegs;
   }
