@@ -87,13 +87,15 @@ __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ 
   using S = typename K::T;
   __shared__ SplitTable<S> s_sp;
   __shared__ uint32_t s_cnt[kBinStride];
-  // the tile's keys are on their way while the splitter table is set up
+  // the tile's keys are on their way while the splitter table is set up;
+  // every lane loads (positions past the end read the last key and are not
+  // counted), so the loads are in flight together
   const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kBucketTile;
   typename K::T v[kPer];
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint64_t i = base + k * kNT + threadIdx.x;
-    v[k] = i < n ? keys[i] : typename K::T(0);
+    v[k] = keys[i < n ? i : n - 1];
   }
   uint32_t u;
   load_splitters(s_sp, b, u);
@@ -252,6 +254,7 @@ __global__ __launch_bounds__(256) void k_order_scan(const typename K::T* __restr
   constexpr uint32_t kRowsPer = 64;  // 16384 keys between two looks at the shared word
   constexpr uint64_t kChunk = 256ull * kRowsPer;
   __shared__ uint32_t s_flags, s_bits;
+  if (n < 2) return;  // no adjacent pair (and the loads below read positions n - 2, n - 1)
   const uint64_t nchunks = (n + kChunk - 1) / kChunk;
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     if (threadIdx.x == 0) {
@@ -262,13 +265,25 @@ __global__ __launch_bounds__(256) void k_order_scan(const typename K::T* __restr
     const uint32_t f = s_flags;
     if (f == 3u) return;  // the same value for the whole workgroup
     bool d = false, a = false;
-#pragma unroll 16
-    for (uint32_t r = 0; r < kRowsPer; ++r) {
-      const uint64_t i = ch * kChunk + static_cast<uint64_t>(r) * 256u + threadIdx.x;
-      if (i + 1 < n) {
-        const auto x = K::ord(keys[i]), y = K::ord(keys[i + 1]);
-        d |= y < x;
-        a |= y > x;
+    // every lane loads (positions past the last pair read the last pair and
+    // count for nothing): 16 rows of loads are issued before any is used
+    constexpr uint32_t kGroup = 16;
+    for (uint32_t r0 = 0; r0 < kRowsPer; r0 += kGroup) {
+      typename K::T xs[kGroup], ys[kGroup];
+      bool pair[kGroup];
+#pragma unroll
+      for (uint32_t q = 0; q < kGroup; ++q) {
+        const uint64_t i = ch * kChunk + static_cast<uint64_t>(r0 + q) * 256u + threadIdx.x;
+        pair[q] = i + 1 < n;
+        const uint64_t ic = pair[q] ? i : n - 2;
+        xs[q] = keys[ic];
+        ys[q] = keys[ic + 1];
+      }
+#pragma unroll
+      for (uint32_t q = 0; q < kGroup; ++q) {
+        const auto x = K::ord(xs[q]), y = K::ord(ys[q]);
+        d |= pair[q] && y < x;
+        a |= pair[q] && y > x;
       }
     }
     const uint32_t bits = (__any(d) ? 1u : 0u) | (__any(a) ? 2u : 0u);
@@ -282,7 +297,7 @@ template <class K>
 struct OrderL {
   static hipError_t run(const void* keys, uint64_t n, uint32_t* flags, hipStream_t s) {
     const uint64_t nchunks = (n + 16383) / 16384;
-    const uint32_t grid = static_cast<uint32_t>(nchunks < 512 ? nchunks : 512);
+    const uint32_t grid = static_cast<uint32_t>(nchunks < 4096 ? nchunks : 4096);
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(k_order_scan<K>, dim3(grid), dim3(256), 0, s, static_cast<const typename K::T*>(keys), n,
                        flags);

@@ -76,14 +76,25 @@ __global__ __launch_bounds__(kScanNT) void k_run_scan(const typename K::T* __res
       asc = asc || (i + 1 < n && K::ord(k[r]) < K::ord(nxt));
       mine += d[r] ? 1u : 0u;
     }
-    // some adjacent pair ascends (the learned pass needs both directions)
-    if (__ballot(asc) != 0 && lane_id() == 0) rb.count[1] = 1u;
+    // some adjacent pair ascends (the learned pass needs both directions);
+    // a look first spares the shared word a store from every wave
+    if (__ballot(asc) != 0 && lane_id() == 0 &&
+        __hip_atomic_load(&rb.count[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+      rb.count[1] = 1u;
     const uint64_t wsum = wave_sum_u64(mine);
     if (lane_id() == 0 && wsum) atomicAdd(&s_local, static_cast<uint32_t>(wsum));
     __syncthreads();
     if (tid == 0) {
       const uint32_t total = s_local;
-      const uint32_t old = total ? atomicAdd(rb.count, total) : 0u;
+      // once the count is past the limit the input goes to the partition
+      // passes and the exact count no longer matters: a look at the word
+      // spares it the read-modify-write of every later workgroup (one
+      // address, thousands of workgroups)
+      uint32_t old = 0;
+      if (total) {
+        old = __hip_atomic_load(rb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old <= kRunMaxDescents) old = atomicAdd(rb.count, total);
+      }
       s_base = old;
       s_go = (total == 0 || old + total <= kRunMaxDescents) ? 1u : 0u;
       s_local = 0;
