@@ -616,10 +616,20 @@ __global__ __launch_bounds__(kExtractThreads) void k_extract(const uint64_t* __r
     __syncthreads();
   }
   float run = tid > 0 ? s_max[tid - 1] : 0.0f;
-#pragma unroll 16
-  for (uint64_t i = b; i < e; ++i) {
-    run = y[i] > run ? y[i] : run;
-    r[i] = run;
+  // 16 loads of y, then their 16 running maxima: stores to r (another
+  // buffer, which the compiler cannot tell) would otherwise hold back each
+  // next load
+  for (uint64_t i0 = b; i0 < e; i0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = y[i0 + q < e ? i0 + q : e - 1];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (i0 + q < e) {
+        run = v[q] > run ? v[q] : run;
+        r[i0 + q] = run;
+      }
+    }
   }
   __threadfence_block();
   __syncthreads();
