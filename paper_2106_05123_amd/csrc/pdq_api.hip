@@ -605,6 +605,9 @@ BucketBufs bucket_bufs(char* area, uint64_t n, const uint64_t* splitters, const 
 
 struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair&) = delete;
+  EventPair& operator=(const EventPair&) = delete;
   bool make() { return hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
   double ms() const {
     float v = 0;
@@ -624,8 +627,11 @@ struct LearnedResult {
   uint64_t sample_judge = 0;
   uint64_t max_range = 0, equal = 0;
   float loss = 0.0f;
-  double fit_ms = 0, hist_ms = 0, scatter_ms = 0;
+  double fit_ms = 0, hist_ms = 0;
   uint64_t hist_bytes = 0, scatter_bytes = 0;
+  // the scatter's events live as long as the result: they are read once the
+  // whole sort has been waited for, so timing it costs no wait in the middle
+  EventPair scat;
 };
 
 // Fit, histogram, judge and (if the judge agrees) scatter into bins.
@@ -641,7 +647,8 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   const FitBufs f = fit_bufs(base + L.fit_out, base + L.fit_scratch, o.steps, o.grid);
   BucketBufs b = bucket_bufs(base + L.bucket, n, f.splitters, f.count);
   b.errors = &c.ctr->errors;
-  EventPair e_fit, e_hist, e_scat;
+  EventPair e_fit, e_hist;
+  EventPair& e_scat = res.scat;
   if (prof && !(e_fit.make() && e_hist.make() && e_scat.make())) return PDQ_ERR_HIP;
   if (!unordered) {
     // an input that is already non-decreasing or non-increasing is retired
@@ -726,8 +733,6 @@ int run_learned(Ctx& c, const Opts& o, const Layout& L, char* base, bool prof, L
   if (prof) HIP_TRY(hipEventRecord(e_scat.b, s));
   HIP_TRY(launch_bucket_init(c, b.begin, s));
   if (prof) {
-    HIP_TRY(hipEventSynchronize(e_scat.b));
-    res.scatter_ms = e_scat.ms();
     res.scatter_bytes = n * 2ull * (kb + (c.has_vals ? 4u : 0u));
   }
   res.state = 1;
@@ -1070,7 +1075,7 @@ void fill_learned_stats(pdq_stats* st, const LearnedResult& lres) {
   st->learned_sample_judge = lres.sample_judge;
   st->learned_fit_ms = lres.fit_ms;
   st->learned_hist_ms = lres.hist_ms;
-  st->learned_scatter_ms = lres.scatter_ms;
+  st->learned_scatter_ms = lres.state == 1 ? lres.scat.ms() : 0.0;  // the sort has been waited for
   st->learned_hist_bytes = lres.hist_bytes;
   st->learned_scatter_bytes = lres.scatter_bytes;
 }
