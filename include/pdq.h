@@ -18,8 +18,9 @@
  *     merge; PDQ_HEAPSORT selects the paper's in-place heapsort);
  *   - detection of already ordered segments (Section 5.2);
  *   - an LDS-resident base case for segments of at most 4096 keys, 16384
- *     with device-counted passes (Section 5.1's small-case sort, as a
- *     sorting network and an LDS merge sort).
+ *     with device-counted passes (Section 5.1's small-case sort: a sorting
+ *     network below 1024 keys; from 2048 keys an LDS bucket sort when the
+ *     keys spread evenly over their range, else an LDS merge sort).
  * With PDQ_LEARNED a multiway first pass runs before the partition passes
  * (the multiway partitioning Section 2 mentions as the road not taken): a
  * small MLP fitted to the CDF of a key sample proposes up to 255
