@@ -166,7 +166,7 @@ typedef struct pdq_options {
                             (partition tile, slots per lane of the two widest LDS classes):
                             (8192, 16), (16384, 16), (32768, 16), (8192, 32) */
   uint32_t batch_passes; /* device-counted passes (PDQ_BATCHED, and pdq_sort without
-                            PDQ_HOST_LOOP): 0 = automatic (h + 2 + h/2, h the halvings that
+                            PDQ_HOST_LOOP): 0 = automatic (h + 3 + h/2, h the halvings that
                             bring the largest segment to the widest LDS class); k > 0 = k - 1
                             passes (at most 32); segments still live after them finish in the
                             persistent tail */

@@ -957,14 +957,12 @@ Ctx batch_ctx(Ctx c, const Opts& o, const Tuned& t) {
   return c;
 }
 
-// Passes queued for a largest segment of m keys: the halvings that bring it
-// to the widest LDS class, plus two for uneven splits. Anything deeper
-// finishes in the persistent tail.
 // Device-counted passes to queue for a largest segment of m keys: the
-// halvings that bring it to base_max, plus 2 and half of them again
+// halvings that bring it to base_max, plus 3 and half of them again
 // (splits are uneven, so some paths need more passes; a pass that finds no
 // live segment costs a few microseconds, while a segment left to the
-// persistent tail is partitioned by a single workgroup).
+// persistent tail is partitioned by a single workgroup). Anything deeper
+// finishes in the persistent tail.
 uint32_t batch_passes(uint64_t m, uint32_t base_max) {
   uint32_t p = 0;
   while (m > base_max && p < kMaxBatchPasses) {
@@ -972,7 +970,7 @@ uint32_t batch_passes(uint64_t m, uint32_t base_max) {
     ++p;
   }
   if (p == 0) return 0;
-  p += 2 + p / 2;
+  p += 3 + p / 2;
   return p < kMaxBatchPasses ? p : kMaxBatchPasses;
 }
 
