@@ -493,8 +493,9 @@ __device__ __forceinline__ int bucket_sort(typename S::V (&x)[E], unsigned char*
     const uint32_t t = __shfl_xor(mx, d, 64);
     mx = t > mx ? t : mx;
   }
-  uint32_t* wsum = reinterpret_cast<uint32_t*>(red);  // the range is consumed: reuse
-  __syncthreads();
+  // the range words are free again: every lane read them before the
+  // counting barrier
+  uint32_t* wsum = reinterpret_cast<uint32_t*>(red);
   if (lane == 63) wsum[wave] = incl;
   if (lane == 0) atomicMax(&sc[0], mx);
   __syncthreads();
