@@ -229,6 +229,29 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
     }
   }
   __syncthreads();
+  // a full tile takes every slot in a loop the compiler unrolls: the bin
+  // and run-start lookups of all the lane's keys are in flight together
+  // before the first store
+  if (cnt == kBucketTile) {
+    uint32_t pos[kPer];  // the row offsets are 32-bit: positions below 2^32
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      const uint32_t i = k * kNT + threadIdx.x;
+      const uint32_t bi = s_bin[i];
+      pos[k] = s_goff[bi] + (i - s_loc[bi]);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      const uint32_t i = k * kNT + threadIdx.x;
+      if (pos[k] >= n) {  // histogram and scatter disagree: never write outside the output
+        atomicOr(b.errors, kErrScatter);
+        continue;
+      }
+      kout[pos[k]] = s_key[i];
+      if constexpr (PAIRS) vout[pos[k]] = s_val[i];
+    }
+    return;
+  }
   for (uint32_t i = threadIdx.x; i < cnt; i += kNT) {
     const uint32_t bi = s_bin[i];
     const uint64_t pos = static_cast<uint64_t>(s_goff[bi]) + (i - s_loc[bi]);
