@@ -46,17 +46,31 @@ __device__ __forceinline__ void load_splitters(SplitTable<S>& t, const BucketBuf
   for (uint32_t i = threadIdx.x; i < 256; i += kNT) t.v[SplitTable<S>::at(i)] = i < u ? static_cast<S>(b.splitters[i]) : S(~S(0));
 }
 
-// Bin of a key image: branchless binary search for the number b of
-// splitters <= img (padding is clamped away), then the equality test.
-template <class S>
-__device__ __forceinline__ uint32_t bin_of(const SplitTable<S>& t, uint32_t u, S img) {
-  uint32_t pos = 0;
+// Bins of N key images: branchless binary search for the number b of
+// splitters <= img (padding is clamped away), then the equality test. The
+// search runs level by level over all N keys, so a level's N table probes
+// are in flight together instead of one key's eight probes back to back.
+template <class S, uint32_t N>
+__device__ __forceinline__ void bins_of(const SplitTable<S>& t, uint32_t u, const S (&img)[N], uint32_t (&bin)[N]) {
+  uint32_t pos[N];
 #pragma unroll
-  for (uint32_t step = 128; step >= 1; step >>= 1)
-    if (t.get(pos + step - 1) <= img) pos += step;
-  const uint32_t bsel = pos < u ? pos : u;
-  const bool eq = bsel > 0 && t.get(bsel - 1) == img;
-  return eq ? 2 * bsel - 1 : 2 * bsel;
+  for (uint32_t k = 0; k < N; ++k) pos[k] = 0;
+#pragma unroll
+  for (uint32_t step = 128; step >= 1; step >>= 1) {
+    S probe[N];
+#pragma unroll
+    for (uint32_t k = 0; k < N; ++k) probe[k] = t.get(pos[k] + step - 1);
+#pragma unroll
+    for (uint32_t k = 0; k < N; ++k) pos[k] += probe[k] <= img[k] ? step : 0u;
+  }
+  S below[N];
+#pragma unroll
+  for (uint32_t k = 0; k < N; ++k) {
+    pos[k] = pos[k] < u ? pos[k] : u;
+    below[k] = t.get(pos[k] > 0 ? pos[k] - 1 : 0);
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < N; ++k) bin[k] = pos[k] > 0 && below[k] == img[k] ? 2 * pos[k] - 1 : 2 * pos[k];
 }
 
 // Exclusive scan of s[0..512) in place by the 512 threads; returns the total.
@@ -101,10 +115,15 @@ __global__ __launch_bounds__(kNT) void k_hist(const typename K::T* __restrict__ 
   load_splitters(s_sp, b, u);
   for (uint32_t i = threadIdx.x; i < kBinStride; i += kNT) s_cnt[i] = 0;
   lds_barrier();
+  S img[kPer];
+  uint32_t bin[kPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) img[k] = K::ord(v[k]);
+  bins_of(s_sp, u, img, bin);
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint64_t i = base + k * kNT + threadIdx.x;
-    if (i < n) atomicAdd(&s_cnt[bin_of(s_sp, u, K::ord(v[k]))], 1u);
+    if (i < n) atomicAdd(&s_cnt[bin[k]], 1u);
   }
   __syncthreads();
   uint32_t* row = b.rows + static_cast<uint64_t>(blockIdx.x) * kBinStride;
@@ -210,10 +229,15 @@ __global__ __launch_bounds__(kNT) void k_scatter(const typename K::T* __restrict
     s_goff[i] = row[i];
   }
   lds_barrier();
+  {
+    T img[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) img[k] = K::ord(v[k]);
+    bins_of(s_sp, u, img, bin);
+  }
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint32_t i = k * kNT + threadIdx.x;
-    bin[k] = bin_of(s_sp, u, K::ord(v[k]));
     rank[k] = i < cnt ? atomicAdd(&s_loc[bin[k]], 1u) : 0u;
   }
   __syncthreads();
